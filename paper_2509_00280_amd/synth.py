@@ -1,0 +1,258 @@
+"""Seeded synthetic sparse tensors, factor initialisations and request streams.
+
+This module only draws random inputs.  It holds none of the method's
+arithmetic (no encoding, no MTTKRP, no solve): both the GPU path and the
+CPU oracle consume what it returns, so a parity test feeds the two sides the
+same bytes.
+
+Streams come from ``numpy.random.SeedSequence(seed).spawn``; every call with
+the same arguments returns bit-identical arrays on any host.
+
+The workloads stand in for the sparse tensors of the paper's evaluation
+(Section IV-A, Table I), which are not available here: ratings-like 3-mode
+tensors with power-law (Zipf) mode distributions, 4-mode tensors with a short
+date-like mode, and batches of small tensors for many independent
+decompositions (Section IV-D).  The per-mode label shuffle follows the
+"shuffled" experiments of Section IV-A.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "SparseCOO", "zipf_cdf", "draw_labels", "distinct_coo", "uniform_distinct_coo",
+    "normal_factors", "shuffle_labels", "config", "batch_config", "serving_requests",
+    "CONFIG_NAMES",
+]
+
+
+@dataclass
+class SparseCOO:
+    """A sparse tensor in coordinate form, in draw (input) order.
+
+    coords: uint32 array of shape (nmodes, nnz), 0-based coordinates (SoA).
+    vals:   float32 array of shape (nnz,).
+    dims:   tuple of mode lengths.
+    """
+    dims: tuple
+    coords: np.ndarray
+    vals: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nmodes(self) -> int:
+        return len(self.dims)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.vals.shape[0])
+
+
+def zipf_cdf(n: int, s: float) -> np.ndarray:
+    """Cumulative FP64 weights of a bounded Zipf law on {0..n-1}: P(i) ~ (i+1)^-s."""
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-float(s))
+    c = np.cumsum(w)
+    c /= c[-1]
+    return c
+
+
+def draw_labels(rng: np.random.Generator, n: int, count: int, dist) -> np.ndarray:
+    """Draw ``count`` labels in {0..n-1}.
+
+    dist is ``"uniform"`` or ``("zipf", s)``; Zipf is sampled by inverse CDF
+    (``searchsorted(side='right')``), so label 0 is the most frequent one.
+    """
+    if dist == "uniform":
+        return rng.integers(0, n, size=count, dtype=np.int64).astype(np.uint32)
+    kind, s = dist
+    assert kind == "zipf"
+    cdf = zipf_cdf(n, s)
+    u = rng.random(count)
+    idx = np.searchsorted(cdf, u, side="right")
+    np.minimum(idx, n - 1, out=idx)
+    return idx.astype(np.uint32)
+
+
+def _draw_values(rng: np.random.Generator, count: int, vdist) -> np.ndarray:
+    if vdist == "u01":
+        return rng.random(count, dtype=np.float32)
+    if vdist == "int1to5":
+        return rng.integers(1, 6, size=count, dtype=np.int64).astype(np.float32)
+    if vdist == "lognormal":
+        return rng.lognormal(0.0, 1.0, size=count).astype(np.float32)
+    if vdist == "normal":
+        return rng.standard_normal(count, dtype=np.float32)
+    raise ValueError(vdist)
+
+
+def _linear(coords: np.ndarray, dims) -> np.ndarray:
+    """Mixed-radix C-order cell number of each coordinate (needs prod(dims) < 2^63)."""
+    lin = np.zeros(coords.shape[1], dtype=np.int64)
+    for n, d in enumerate(dims):
+        lin *= int(d)
+        lin += coords[n].astype(np.int64)
+    return lin
+
+
+def distinct_coo(seed: int, dims, nnz: int, mode_dists, vdist, max_rounds: int = 40) -> SparseCOO:
+    """Draw coordinate+value pairs until ``nnz`` distinct coordinates exist.
+
+    Rounds draw ceil(1.5 * deficit) pairs; the first occurrence of each
+    coordinate (in draw order) is kept; the result is truncated to exactly
+    ``nnz`` in draw order.  If the box cannot be filled within ``max_rounds``
+    the realized count is smaller and recorded in ``meta['realized_nnz']``.
+    """
+    dims = tuple(int(d) for d in dims)
+    if math.prod(dims) >= 2 ** 63:
+        raise ValueError("box too large for the 63-bit cell numbering used to deduplicate")
+    nm = len(dims)
+    ss = np.random.SeedSequence(seed)
+    s_coord, s_val = ss.spawn(2)
+    rc = np.random.default_rng(s_coord)
+    rv = np.random.default_rng(s_val)
+    kept_c = np.zeros((nm, 0), dtype=np.uint32)
+    kept_v = np.zeros(0, dtype=np.float32)
+    kept_lin = np.zeros(0, dtype=np.int64)
+    rounds = 0
+    while kept_v.shape[0] < nnz and rounds < max_rounds:
+        deficit = nnz - kept_v.shape[0]
+        m = int(math.ceil(1.5 * deficit))
+        c = np.stack([draw_labels(rc, dims[n], m, mode_dists[n]) for n in range(nm)])
+        v = _draw_values(rv, m, vdist)
+        lin = _linear(c, dims)
+        all_lin = np.concatenate([kept_lin, lin])
+        _, first = np.unique(all_lin, return_index=True)
+        first.sort()
+        first = first[first >= kept_lin.shape[0]] - kept_lin.shape[0]
+        kept_c = np.concatenate([kept_c, c[:, first]], axis=1)
+        kept_v = np.concatenate([kept_v, v[first]])
+        kept_lin = np.concatenate([kept_lin, lin[first]])
+        rounds += 1
+    kept_c = np.ascontiguousarray(kept_c[:, :nnz])
+    kept_v = np.ascontiguousarray(kept_v[:nnz])
+    return SparseCOO(dims, kept_c, kept_v,
+                     meta={"seed": seed, "rounds": rounds, "realized_nnz": int(kept_v.shape[0]),
+                           "requested_nnz": int(nnz), "mode_dists": list(mode_dists), "vdist": vdist})
+
+
+def uniform_distinct_coo(seed: int, dims, nnz: int, vdist="u01") -> SparseCOO:
+    """``nnz`` distinct cells sampled uniformly without replacement from the box (C order)."""
+    dims = tuple(int(d) for d in dims)
+    ss = np.random.SeedSequence(seed)
+    s_coord, s_val = ss.spawn(2)
+    total = math.prod(dims)
+    lin = np.random.default_rng(s_coord).choice(total, size=nnz, replace=False)
+    coords = np.stack(np.unravel_index(lin, dims)).astype(np.uint32)
+    vals = _draw_values(np.random.default_rng(s_val), nnz, vdist)
+    return SparseCOO(dims, np.ascontiguousarray(coords), vals,
+                     meta={"seed": seed, "realized_nnz": nnz, "requested_nnz": nnz, "vdist": vdist})
+
+
+def normal_factors(seed: int, dims, rank: int) -> list:
+    """Row-major FP32 ``I_n x rank`` matrices with N(0,1) entries, one stream per mode."""
+    ss = np.random.SeedSequence(seed).spawn(len(dims))
+    return [np.random.default_rng(s).standard_normal((int(d), rank), dtype=np.float32) for s, d in zip(ss, dims)]
+
+
+def shuffle_labels(t: SparseCOO, seed: int) -> SparseCOO:
+    """Apply an independent uniform permutation to the labels of every mode."""
+    ss = np.random.SeedSequence(seed).spawn(t.nmodes)
+    c = np.empty_like(t.coords)
+    for n, (s, d) in enumerate(zip(ss, t.dims)):
+        p = np.random.default_rng(s).permutation(d).astype(np.uint32)
+        c[n] = p[t.coords[n]]
+    return SparseCOO(t.dims, c, t.vals.copy(), meta=dict(t.meta, shuffled=seed))
+
+
+CONFIG_NAMES = ("small", "ratings", "skewed4d")
+
+# name -> (master seed, dims, nnz, per-mode distributions, value law, rank, iterations)
+_CONFIGS = {
+    "small": (1, (200, 150, 100), 20_000, None, "u01", 16, 10),
+    "ratings": (2, (480_000, 18_000, 2_000), 100_000_000,
+                (("zipf", 1.1), ("zipf", 1.1), "uniform"), "int1to5", 32, 20),
+    "skewed4d": (3, (2_000_000, 100_000, 50_000, 24), 150_000_000,
+                 (("zipf", 1.3), ("zipf", 1.3), ("zipf", 1.3), "uniform"), "lognormal", 64, 10),
+}
+
+
+def config(name: str, nnz: int | None = None, shuffle: bool = False):
+    """One of the single-tensor workloads.
+
+    Returns (tensor, factors, rank, iters).  ``nnz`` scales the tensor down
+    (same shape and laws) for quick runs; ``shuffle`` permutes labels per mode.
+    """
+    seed, dims, full_nnz, dists, vdist, rank, iters = _CONFIGS[name]
+    n = full_nnz if nnz is None else int(nnz)
+    ss = np.random.SeedSequence(seed)
+    s_t, s_f, s_sh = (int(x.generate_state(1)[0]) for x in ss.spawn(3))
+    if dists is None:
+        t = uniform_distinct_coo(s_t, dims, n, vdist)
+    else:
+        t = distinct_coo(s_t, dims, n, dists, vdist)
+    if shuffle:
+        t = shuffle_labels(t, s_sh)
+    t.meta["config"] = name
+    return t, normal_factors(s_f, dims, rank), rank, iters
+
+
+def batch_config(seed: int = 4, count: int = 256, nnz_range=(10_000, 5_000_000),
+                 dim_range=(50, 200_000), zipf_s: float = 1.2, ranks=(16, 32)):
+    """Many small independent tensors (3 or 4 modes with p=1/2, log-uniform sizes).
+
+    Returns a list of (tensor, factors, rank).
+    """
+    root = np.random.SeedSequence(seed)
+    shape_rng = np.random.default_rng(root.spawn(1)[0])
+    members = root.spawn(count + 1)[1:]
+    out = []
+    lo_n, hi_n = np.log(nnz_range[0]), np.log(nnz_range[1])
+    lo_d, hi_d = np.log(dim_range[0]), np.log(dim_range[1])
+    for b in range(count):
+        nm = 3 if shape_rng.random() < 0.5 else 4
+        nnz = int(np.floor(np.exp(shape_rng.uniform(lo_n, hi_n))))
+        dims = tuple(int(np.floor(np.exp(shape_rng.uniform(lo_d, hi_d)))) for _ in range(nm))
+        rank = int(ranks[int(shape_rng.integers(0, len(ranks)))])
+        s_t, s_f = (int(x.generate_state(1)[0]) for x in members[b].spawn(2))
+        t = distinct_coo(s_t, dims, nnz, [("zipf", zipf_s)] * nm, "u01")
+        t.meta["member"] = b
+        out.append((t, normal_factors(s_f, dims, rank), rank))
+    return out
+
+
+def serving_requests(seed: int = 5, count: int = 2100, rate_per_s: float = 100.0,
+                     ranks=(16, 32, 48, 64), **batch_kw):
+    """Poisson arrivals of decomposition requests drawn like ``batch_config``.
+
+    Returns a list of dicts {t_arrive, tensor, factors, rank}.  Tensors are
+    generated lazily by ``materialize(req)`` to bound host memory.
+    """
+    root = np.random.SeedSequence(seed)
+    s_arr, s_shape = root.spawn(2)
+    gaps = np.random.default_rng(s_arr).exponential(1.0 / rate_per_s, size=count)
+    t = np.cumsum(gaps)
+    reqs = []
+    shape_seed = int(s_shape.generate_state(1)[0])
+    for i in range(count):
+        reqs.append({"id": i, "t_arrive": float(t[i]), "shape_seed": shape_seed, "index": i,
+                     "ranks": tuple(ranks), "batch_kw": batch_kw})
+    return reqs
+
+
+def materialize(req):
+    """Generate the tensor and initial factors of one serving request."""
+    kw = dict(req["batch_kw"])
+    rng = np.random.default_rng(np.random.SeedSequence([req["shape_seed"], req["index"]]))
+    lo_n, hi_n = np.log(kw.get("nnz_range", (10_000, 5_000_000))[0]), np.log(kw.get("nnz_range", (10_000, 5_000_000))[1])
+    lo_d, hi_d = np.log(kw.get("dim_range", (50, 200_000))[0]), np.log(kw.get("dim_range", (50, 200_000))[1])
+    nm = 3 if rng.random() < 0.5 else 4
+    nnz = int(np.floor(np.exp(rng.uniform(lo_n, hi_n))))
+    dims = tuple(int(np.floor(np.exp(rng.uniform(lo_d, hi_d)))) for _ in range(nm))
+    ranks = req["ranks"]
+    rank = int(ranks[int(rng.integers(0, len(ranks)))])
+    s_t, s_f = (int(x) for x in rng.integers(0, 2 ** 63 - 1, size=2))
+    t = distinct_coo(s_t, dims, nnz, [("zipf", kw.get("zipf_s", 1.2))] * nm, "u01")
+    return t, normal_factors(s_f, dims, rank), rank

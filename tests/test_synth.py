@@ -1,0 +1,59 @@
+"""Seeded generators: determinism, distinctness, marginal laws and sizes."""
+import numpy as np
+import scipy.stats
+
+from paper_2509_00280_amd import synth
+
+
+def test_small_config_is_deterministic_and_distinct():
+    t1, f1, r1, it1 = synth.config("small")
+    t2, f2, _, _ = synth.config("small")
+    assert t1.dims == (200, 150, 100) and t1.nnz == 20_000 and r1 == 16 and it1 == 10
+    np.testing.assert_array_equal(t1.coords, t2.coords)
+    np.testing.assert_array_equal(t1.vals, t2.vals)
+    for a, b in zip(f1, f2):
+        np.testing.assert_array_equal(a, b)
+    lin = np.ravel_multi_index(t1.coords.astype(np.int64), t1.dims)
+    assert np.unique(lin).size == t1.nnz
+    assert t1.vals.dtype == np.float32 and (t1.vals >= 0).all() and (t1.vals < 1).all()
+    assert f1[0].shape == (200, 16) and f1[0].dtype == np.float32
+
+
+def test_zipf_marginal_matches_exact_pmf():
+    rng = np.random.default_rng(0)
+    n, s, m = 40, 1.1, 200_000
+    x = synth.draw_labels(rng, n, m, ("zipf", s))
+    obs = np.bincount(x, minlength=n)
+    p = np.arange(1, n + 1, dtype=np.float64) ** -s
+    p /= p.sum()
+    chi2, pval = scipy.stats.chisquare(obs, p * m)
+    assert pval > 1e-4
+    assert obs.argmax() == 0
+
+
+def test_distinct_topup_scaled_ratings():
+    t, f, rank, iters = synth.config("ratings", nnz=200_000)
+    assert t.nnz == 200_000 and rank == 32 and iters == 20
+    lin = np.ravel_multi_index(t.coords.astype(np.int64), t.dims)
+    assert np.unique(lin).size == t.nnz
+    assert set(np.unique(t.vals).tolist()) <= {1.0, 2.0, 3.0, 4.0, 5.0}
+    # mode 0 skewed towards label 0, mode 2 roughly uniform
+    assert np.bincount(t.coords[0])[0] > 50 * t.nnz / t.dims[0]
+    assert np.bincount(t.coords[2], minlength=t.dims[2]).max() < 3 * t.nnz / t.dims[2]
+
+
+def test_shuffle_keeps_values_and_shape():
+    t, _, _, _ = synth.config("small")
+    s = synth.shuffle_labels(t, 9)
+    np.testing.assert_array_equal(s.vals, t.vals)
+    for n, d in enumerate(t.dims):
+        assert s.coords[n].max() < d
+        assert sorted(np.bincount(s.coords[n], minlength=d)) == sorted(np.bincount(t.coords[n], minlength=d))
+
+
+def test_batch_members_shapes():
+    batch = synth.batch_config(count=6, nnz_range=(1000, 5000), dim_range=(20, 300))
+    for t, f, r in batch:
+        assert t.nmodes in (3, 4) and r in (16, 32)
+        assert len(f) == t.nmodes and all(ff.shape == (d, r) for ff, d in zip(f, t.dims))
+        assert 1000 * 0.5 <= t.nnz <= 5000
