@@ -1,0 +1,263 @@
+/*
+ * spt.h — C-ABI of the MI355X (gfx950) sparse MTTKRP / CP-ALS library.
+ *
+ * The library stores a sparse tensor as a linearized, bit-interleaved
+ * coordinate list: every nonzero keeps its value and one integer position
+ * whose bits interleave the bits of its coordinates (Section III-C, problem
+ * formulation).  On that single, mode-agnostic copy it computes the mode-n
+ * MTTKRP for any n (Section II-B, Fig. 2) and the CP-ALS iteration that
+ * calls it along every mode (Section II-B).
+ *
+ * Conventions shared by every call:
+ *  - Modes and coordinates are 0-based.  1 <= nmodes <= SPT_MAX_MODES, every
+ *    mode length 1 <= I_n <= 2^32 - 2.
+ *  - Pointers are DEVICE pointers unless the comment says "host".  Arrays of
+ *    device pointers (factors) are themselves host arrays.
+ *  - Factor matrices and MTTKRP outputs are row-major FP32 I_n x rank with
+ *    leading dimension rank, 16-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are stream-ordered; a call that must synchronise says so.
+ *  - Every call returns an spt_status and never throws or aborts; on a
+ *    non-OK status out-parameters are left untouched and spt_last_error()
+ *    returns a message (thread-local).
+ *  - The caller owns every buffer it passes; the library owns the memory
+ *    behind an spt_tensor until spt_tensor_free.
+ */
+#ifndef SPT_H
+#define SPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPT_MAX_MODES 8
+#define SPT_MAX_KEY_BITS 128
+#define SPT_MAX_RANK 256      /* mttkrp */
+#define SPT_MAX_ALS_RANK 64   /* cp_als (the R x R solve keeps V^-1 in LDS) */
+
+typedef enum {
+    SPT_OK = 0,
+    SPT_E_INVALID_ARG = -1,   /* bad argument, detected on the host */
+    SPT_E_INDEX_RANGE = -2,   /* a coordinate i_n >= I_n (detected on the GPU by encode) */
+    SPT_E_TOO_MANY_BITS = -3, /* sum of ceil(log2 I_n) exceeds 128 */
+    SPT_E_BAD_LAYOUT = -4,    /* layout is not an interleaving of the modes' bits */
+    SPT_E_OOM = -5,           /* device allocation failed */
+    SPT_E_NOT_SPD = -6,       /* normal-equation matrix not positive definite after ridge retries */
+    SPT_E_DEVICE = -7,        /* a HIP runtime call failed */
+    SPT_E_BUSY = -8,          /* server: request does not fit the memory budget / queue closed */
+    SPT_E_NOT_FOUND = -9      /* server: unknown ticket */
+} spt_status;
+
+typedef struct spt_tensor_s *spt_tensor;
+
+/* Host-side description of an encoded tensor. */
+typedef struct {
+    int64_t nnz;
+    int nmodes;
+    int lp;                              /* total key bits, sum of ceil(log2 I_n) */
+    int key_words;                       /* 1 (u64 keys) or 2 (u128 keys, two u64 words) */
+    int64_t dims[SPT_MAX_MODES];
+    int lbits[SPT_MAX_MODES];            /* ceil(log2 I_n); 0 when I_n == 1 */
+    uint8_t layout[SPT_MAX_KEY_BITS];    /* layout[t] = mode whose next low bit is key bit t */
+    size_t encoded_bytes;                /* nnz * (8 * key_words + 4): keys + values */
+    double norm_x2;                      /* sum of squared values, FP64 */
+} spt_tensor_info;
+
+/* Per-mode execution plan of MTTKRP (chosen by a heuristic or spt_autotune). */
+#define SPT_STRATEGY_DIRECT 0   /* walk nonzeros in key order; atomics at every change of output row */
+#define SPT_STRATEGY_REGROUP 1  /* regroup each tile by output row in LDS; atomics once per (tile chunk, row) */
+typedef struct {
+    int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256, 512 or 1024 */
+    int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
+} spt_plan;
+
+/* ---------------------------------------------------------------------- */
+/* Encoding (Section III-C: linearized tensor, positions of l(p) bits).    */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Build the linearized tensor of a COO tensor on the GPU.
+ *   dims    host, nmodes mode lengths.
+ *   coords  device, uint32 structure-of-arrays: coords[n * nnz + e] = i_n of nonzero e.
+ *   vals    device, nnz FP32 values.
+ *   layout  host, NULL for the default (ALTO) interleaving — level by level,
+ *           modes of shorter bit length first, equal lengths in mode order —
+ *           else layout_len == l(p) mode ids, layout[t] = mode whose next
+ *           unused low bit becomes key bit t (the encoding matrix of the
+ *           paper's environment state, Section III-C.1).
+ * Keys are l(p)-bit integers (64-bit words, two when l(p) > 64), sorted
+ * ascending by a stable LSD radix sort: equal keys (duplicate coordinates)
+ * keep input order and stay separate elements.  The inputs are not kept.
+ * Synchronises `stream` once (coordinate-range check, norm).
+ * Errors: SPT_E_INVALID_ARG, SPT_E_TOO_MANY_BITS, SPT_E_BAD_LAYOUT,
+ * SPT_E_INDEX_RANGE (no handle is created), SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_encode(const int64_t *dims, int nmodes, const uint32_t *coords, const float *vals,
+                      int64_t nnz, const uint8_t *layout, int layout_len, void *stream,
+                      spt_tensor *out);
+
+/* Fill *info (host). */
+spt_status spt_tensor_get_info(spt_tensor t, spt_tensor_info *info);
+
+/*
+ * Copy the encoded tensor out (device buffers, any may be NULL):
+ *   keys  nnz * key_words uint64, element-major, low word first;
+ *   vals  nnz FP32 in key order;  perm  nnz uint32, input index of each element.
+ */
+spt_status spt_tensor_export(spt_tensor t, uint64_t *keys, float *vals, uint32_t *perm, void *stream);
+
+/* Decode every key back to coordinates: coords[n * nnz + j] (device, uint32 SoA). */
+spt_status spt_tensor_decode(spt_tensor t, uint32_t *coords, void *stream);
+
+/* Plan of the tensor (host copy) / replace it. */
+spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan);
+spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan);
+
+/* Release the handle (waits for nothing; the caller orders it after its last use). */
+void spt_tensor_free(spt_tensor t);
+
+/* ---------------------------------------------------------------------- */
+/* MTTKRP (Section II-B, Fig. 2).                                          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * out = X_(mode) times the Khatri-Rao product of the other factors, i.e. for
+ * every nonzero v at (i_0..i_{N-1}): out[i_mode, :] += v * prod_{k != mode}
+ * factors[k][i_k, :].  FP32 inputs, FP32 accumulation (order unspecified).
+ *   factors  host array of nmodes device pointers (factors[mode] is not read).
+ *   out      device, I_mode x rank, OVERWRITTEN (rows without nonzeros are 0).
+ * Fully asynchronous; host-side argument checks only.  1 <= rank <= SPT_MAX_RANK.
+ */
+spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
+                      void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* CP-ALS (Section II-B; the update follows Kolda and Bader's ALS).        */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Run up to max_iters CP-ALS iterations from the factors the caller passes.
+ * Per iteration, for n = 0..N-1: M = MTTKRP(n); V = Hadamard product of the
+ * Grams of the other factors (FP64, Gram via FP64 MFMA); factor n = M V^-1
+ * (FP64 Cholesky, ridge retry if V is not positive definite), columns
+ * normalised to unit 2-norm with the norms in lambda, rounded to FP32.
+ * Then fit = 1 - |X - Xhat| / |X| in FP64 (direct residual over the
+ * nonzeros once 1 - fit < 1e-2).  Stops after max_iters, or earlier when
+ * tol > 0 and |fit - previous fit| < tol (previous fit starts at 0).
+ *   factors  host array of nmodes device pointers, in: initial, out: normalised.
+ *   lambda   device, rank FP64 (out).
+ *   fit_out, iters_out  host (out).
+ * Synchronises `stream` once per iteration.  1 <= rank <= SPT_MAX_ALS_RANK.
+ * Errors: SPT_E_INVALID_ARG (also when |X| = 0), SPT_E_NOT_SPD, SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *const *factors,
+                      double *lambda, double *fit_out, int *iters_out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batches of independent tensors (many decompositions, Section IV-D).     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One persistent launch computes the mode-`mode` MTTKRP of every tensor in
+ * the batch; tensors with nmodes <= mode are skipped.  factors[b] is a host
+ * array of device pointers for tensor b, outs[b] its output (overwritten),
+ * ranks[b] its rank (<= 64).  Asynchronous.
+ */
+spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *const *const *factors,
+                              const int *ranks, int mode, float *const *outs, void *stream);
+
+/*
+ * CP-ALS of every tensor of the batch, advanced in lock step: each step runs
+ * one batched MTTKRP launch per mode index and one batched FP64 solve.
+ * Tensors stop individually (max_iters, tol); fits[b] and iters[b] are host
+ * arrays, lambdas[b] device arrays of ranks[b] doubles.  Synchronises once
+ * per iteration.
+ */
+spt_status spt_cp_als_batched(const spt_tensor *ts, int count, const int *ranks, int max_iters,
+                              double tol, float *const *const *factors, double *const *lambdas,
+                              double *fits, int *iters, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Autotuner (the measured search over encodings of Section III-C).        */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Search layouts (the default interleaving and valid local moves of it) and
+ * per-mode tile/strategy by timing all-mode MTTKRP on `stream`; re-encodes
+ * *t in place when a different layout wins and stores the winning plan.
+ * Measured candidates are cached per (tensor shape, nnz, rank, layout).
+ * budget_ms bounds the search's GPU time.  Host out: best_ms, the all-mode
+ * time of the winner.  Synchronises.
+ */
+spt_status spt_autotune(spt_tensor *t, const float *const *factors, int rank, double budget_ms,
+                        double *best_ms, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of CP-ALS requests.                        */
+/* ---------------------------------------------------------------------- */
+
+typedef struct spt_server_s *spt_server;
+
+typedef struct {
+    int nmodes;
+    int64_t dims[SPT_MAX_MODES];
+    int64_t nnz;
+    const uint32_t *coords;      /* host, SoA nmodes x nnz (copied at submit) */
+    const float *vals;           /* host, nnz (copied at submit) */
+    const float *const *init;    /* host array of nmodes host pointers, I_n x rank FP32 (copied) */
+    int rank;                    /* 1..SPT_MAX_ALS_RANK */
+    int max_iters;
+    double tol;
+} spt_request;
+
+typedef struct {
+    spt_status status;
+    double fit;
+    int iters;
+    double t_arrive, t_admit, t_done;   /* seconds on the server's monotonic clock */
+} spt_result;
+
+/*
+ * Create a server that owns one HIP stream and a worker thread.  Requests
+ * are admitted while their device bytes (encoded tensor, factors, MTTKRP
+ * output, Grams, workspace) fit hbm_budget_bytes and fewer than max_slots
+ * are active; every admitted request joins the running set at the next
+ * iteration boundary, so requests that arrive while others run share the
+ * GPU (continuous batching).
+ */
+spt_status spt_server_create(size_t hbm_budget_bytes, int max_slots, spt_server *out);
+
+/* Enqueue a copy of *req; returns a ticket (host). */
+spt_status spt_server_submit(spt_server s, const spt_request *req, uint64_t *ticket);
+
+/*
+ * Wait for a ticket; on completion copies the normalised factors into
+ * factors_out (host array of nmodes host pointers, may be NULL) and lambda
+ * (host, rank doubles, may be NULL).  timeout_s < 0 waits forever.
+ * Returns SPT_E_BUSY on timeout.
+ */
+spt_status spt_server_wait(spt_server s, uint64_t ticket, double timeout_s, spt_result *res,
+                           float *const *factors_out, double *lambda);
+
+/* Server clock (seconds), for callers that time arrivals. */
+double spt_server_now(spt_server s);
+
+/* Stop accepting, finish active work, join the worker and free everything. */
+void spt_server_destroy(spt_server s);
+
+/* ---------------------------------------------------------------------- */
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *spt_last_error(void);
+
+/* Library version string. */
+const char *spt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPT_H */

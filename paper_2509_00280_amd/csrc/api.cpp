@@ -1,0 +1,404 @@
+// Host runtime of the C-ABI: argument checks, the coordinate<->key codec, the
+// encoded-tensor handle, MTTKRP dispatch and the CP-ALS driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "spt_internal.h"
+
+namespace spt {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+spt_status fail(spt_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+spt_status hip_fail(hipError_t e, const char *what) {
+    const spt_status st = (e == hipErrorOutOfMemory) ? SPT_E_OOM : SPT_E_DEVICE;
+    return fail(st, std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what);
+}
+
+// ---------------------------------------------------------------- device memory
+// Stream-ordered allocations from the device's default pool; the pool keeps
+// freed blocks (release threshold raised once per device) so repeated
+// encode / cp_als calls do not go back to the driver.
+static std::once_flag g_pool_once[64];
+
+static void tune_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::call_once(g_pool_once[dev], [dev]() {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = ~0ull;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    });
+}
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    tune_pool();
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_free(void *p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// ---------------------------------------------------------------- codec
+void make_codec(int nmodes, const int *lbits, const uint8_t *layout, int lp, Codec *c) {
+    std::memset(c, 0, sizeof(*c));
+    c->nmodes = nmodes;
+    c->key_words = lp > 64 ? 2 : 1;
+    int nr = 0;
+    for (int n = 0; n < nmodes; ++n) {
+        std::vector<int> pos;  // pos[j] = key bit that holds coordinate bit j
+        for (int t = 0; t < lp; ++t)
+            if (layout[t] == n) pos.push_back(t);
+        const int start = nr;
+        int j = 0;
+        while (j < (int)pos.size()) {
+            const int kp = pos[j];
+            int len = 1;
+            while (j + len < (int)pos.size() && pos[j + len] == kp + len && (kp + len) / 32 == kp / 32) ++len;
+            c->runs[nr++] = Run{(uint8_t)(kp / 32), (uint8_t)(kp % 32), (uint8_t)j, (uint8_t)len};
+            j += len;
+        }
+        const int end = nr;
+        for (int w = 0; w <= 4; ++w) {
+            int r = start;
+            while (r < end && c->runs[r].word < w) ++r;
+            c->rb[n][w] = (uint8_t)(w == 4 ? end : r);
+        }
+        (void)lbits;
+    }
+    for (int n = nmodes; n < kMaxModes; ++n)
+        for (int w = 0; w <= 4; ++w) c->rb[n][w] = (uint8_t)nr;
+}
+
+static int bit_length(int64_t d) {  // ceil(log2 d) for d >= 1
+    int b = 0;
+    while ((int64_t(1) << b) < d) ++b;
+    return b;
+}
+
+static void default_plan(const Tensor *t, spt_plan *p) {
+    for (int n = 0; n < kMaxModes; ++n) {
+        p->tile[n] = 1024;
+        p->strategy[n] = SPT_STRATEGY_REGROUP;
+    }
+    (void)t;
+}
+
+static bool plan_ok(const spt_plan *p, int nmodes) {
+    for (int n = 0; n < nmodes; ++n) {
+        const int T = p->tile[n];
+        if (T != 256 && T != 512 && T != 1024) return false;
+        if (p->strategy[n] != SPT_STRATEGY_DIRECT && p->strategy[n] != SPT_STRATEGY_REGROUP) return false;
+    }
+    return true;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int mode, float *out, int tile) {
+    MttkrpArgs a{};
+    a.lo = t->lo;
+    a.hi = t->hi;
+    a.vals = t->vals;
+    a.nnz = t->nnz;
+    a.nmodes = t->nmodes;
+    a.mode = mode;
+    a.rank = rank;
+    a.tile = tile;
+    for (int k = 0; k < t->nmodes; ++k) a.f[k] = factors[k];
+    a.out = out;
+    a.codec = t->codec;
+    return a;
+}
+
+spt_status check_factors(const Tensor *t, const float *const *factors, int rank, int skip_mode) {
+    if (!factors) return fail(SPT_E_INVALID_ARG, "factors is NULL");
+    for (int k = 0; k < t->nmodes; ++k) {
+        if (k == skip_mode) continue;
+        if (!factors[k]) return fail(SPT_E_INVALID_ARG, "factor " + std::to_string(k) + " is NULL");
+        if (!aligned16(factors[k])) return fail(SPT_E_INVALID_ARG, "factor " + std::to_string(k) + " not 16-byte aligned");
+    }
+    (void)rank;
+    return SPT_OK;
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+struct spt_tensor_s : Tensor {};
+
+extern "C" {
+
+const char *spt_last_error(void) { return g_last_error.c_str(); }
+
+const char *spt_version(void) { return "spt-gfx950 0.1"; }
+
+spt_status spt_encode(const int64_t *dims, int nmodes, const uint32_t *coords, const float *vals, int64_t nnz,
+                      const uint8_t *layout, int layout_len, void *stream, spt_tensor *out) {
+    if (!dims || !out) return fail(SPT_E_INVALID_ARG, "dims/out is NULL");
+    if (nmodes < 1 || nmodes > kMaxModes) return fail(SPT_E_INVALID_ARG, "nmodes must be in 1..8");
+    if (nnz < 0 || nnz >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "nnz must be in [0, 2^32)");
+    if (nnz > 0 && (!coords || !vals)) return fail(SPT_E_INVALID_ARG, "coords/vals is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    spt_tensor_s *t = new (std::nothrow) spt_tensor_s();
+    if (!t) return fail(SPT_E_OOM, "host allocation failed");
+    t->nmodes = nmodes;
+    t->nnz = nnz;
+    int lp = 0;
+    for (int n = 0; n < nmodes; ++n) {
+        if (dims[n] < 1 || dims[n] > 0xFFFFFFFELL) {
+            delete t;
+            return fail(SPT_E_INVALID_ARG, "mode length must be in 1..2^32-2");
+        }
+        t->dims[n] = dims[n];
+        t->lbits[n] = bit_length(dims[n]);
+        lp += t->lbits[n];
+    }
+    if (lp > SPT_MAX_KEY_BITS) {
+        delete t;
+        return fail(SPT_E_TOO_MANY_BITS, "l(p) = " + std::to_string(lp) + " exceeds 128 bits");
+    }
+    t->lp = lp;
+    t->key_words = lp > 64 ? 2 : 1;
+    if (layout) {
+        if (layout_len != lp) {
+            delete t;
+            return fail(SPT_E_BAD_LAYOUT, "layout length " + std::to_string(layout_len) + " != l(p) " + std::to_string(lp));
+        }
+        int cnt[kMaxModes] = {};
+        for (int i = 0; i < lp; ++i) {
+            if (layout[i] >= nmodes) {
+                delete t;
+                return fail(SPT_E_BAD_LAYOUT, "layout names a mode out of range");
+            }
+            ++cnt[layout[i]];
+        }
+        for (int n = 0; n < nmodes; ++n)
+            if (cnt[n] != t->lbits[n]) {
+                delete t;
+                return fail(SPT_E_BAD_LAYOUT, "mode " + std::to_string(n) + " appears " + std::to_string(cnt[n]) +
+                                                  " times, needs " + std::to_string(t->lbits[n]));
+            }
+        std::memcpy(t->layout, layout, lp);
+    } else {
+        // default interleaving: level by level, modes ordered by (bit length, index)
+        int order[kMaxModes];
+        for (int n = 0; n < nmodes; ++n) order[n] = n;
+        std::stable_sort(order, order + nmodes, [&](int a, int b) { return t->lbits[a] < t->lbits[b]; });
+        int maxb = 0;
+        for (int n = 0; n < nmodes; ++n) maxb = std::max(maxb, t->lbits[n]);
+        int pos = 0;
+        for (int j = 0; j < maxb; ++j)
+            for (int i = 0; i < nmodes; ++i)
+                if (j < t->lbits[order[i]]) t->layout[pos++] = (uint8_t)order[i];
+    }
+    make_codec(nmodes, t->lbits, t->layout, lp, &t->codec);
+    default_plan(t, &t->plan);
+    spt_status st = launch_encode(t, coords, vals, s);
+    if (st != SPT_OK) {
+        delete t;
+        return st;
+    }
+    *out = t;
+    return SPT_OK;
+}
+
+spt_status spt_tensor_get_info(spt_tensor t, spt_tensor_info *info) {
+    if (!t || !info) return fail(SPT_E_INVALID_ARG, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->nnz = t->nnz;
+    info->nmodes = t->nmodes;
+    info->lp = t->lp;
+    info->key_words = t->key_words;
+    for (int n = 0; n < t->nmodes; ++n) {
+        info->dims[n] = t->dims[n];
+        info->lbits[n] = t->lbits[n];
+    }
+    std::memcpy(info->layout, t->layout, t->lp);
+    info->encoded_bytes = (size_t)t->nnz * (8 * t->key_words + 4);
+    info->norm_x2 = t->norm_x2;
+    return SPT_OK;
+}
+
+spt_status spt_tensor_export(spt_tensor t, uint64_t *keys, float *vals, uint32_t *perm, void *stream) {
+    if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
+    hipStream_t s = (hipStream_t)stream;
+    if (t->nnz == 0) return SPT_OK;
+    if (keys) {
+        spt_status st = launch_export(t, keys, s);
+        if (st != SPT_OK) return st;
+    }
+    if (vals) SPT_HIP(hipMemcpyAsync(vals, t->vals, sizeof(float) * t->nnz, hipMemcpyDeviceToDevice, s));
+    if (perm) SPT_HIP(hipMemcpyAsync(perm, t->perm, sizeof(uint32_t) * t->nnz, hipMemcpyDeviceToDevice, s));
+    return SPT_OK;
+}
+
+spt_status spt_tensor_decode(spt_tensor t, uint32_t *coords, void *stream) {
+    if (!t || (!coords && t->nnz)) return fail(SPT_E_INVALID_ARG, "NULL argument");
+    return launch_decode(t, coords, (hipStream_t)stream);
+}
+
+spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
+    if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
+    *plan = t->plan;
+    return SPT_OK;
+}
+
+spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
+    if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
+    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256/512/1024 and strategy 0/1");
+    t->plan = *plan;
+    return SPT_OK;
+}
+
+void spt_tensor_free(spt_tensor t) {
+    if (!t) return;
+    // the handle's buffers were allocated stream-ordered; release them on the null
+    // stream after the device is idle so no in-flight kernel still reads them
+    (void)hipDeviceSynchronize();
+    dev_free(t->lo, nullptr);
+    dev_free(t->hi, nullptr);
+    dev_free(t->vals, nullptr);
+    dev_free(t->perm, nullptr);
+    delete t;
+}
+
+spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out, void *stream) {
+    if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
+    if (mode < 0 || mode >= t->nmodes) return fail(SPT_E_INVALID_ARG, "mode out of range");
+    if (rank < 1 || rank > SPT_MAX_RANK) return fail(SPT_E_INVALID_ARG, "rank must be in 1..256");
+    if (!out) return fail(SPT_E_INVALID_ARG, "out is NULL");
+    if (!aligned16(out)) return fail(SPT_E_INVALID_ARG, "out not 16-byte aligned");
+    spt_status st = check_factors(t, factors, rank, mode);
+    if (st != SPT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = launch_fill_zero(out, t->dims[mode] * (int64_t)rank, s);
+    if (st != SPT_OK) return st;
+    const MttkrpArgs a = make_args(t, factors, rank, mode, out, t->plan.tile[mode]);
+    return launch_mttkrp(a, t->plan.strategy[mode], s);
+}
+
+spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *const *factors, double *lambda,
+                      double *fit_out, int *iters_out, void *stream) {
+    if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
+    if (rank < 1 || rank > SPT_MAX_ALS_RANK) return fail(SPT_E_INVALID_ARG, "rank must be in 1..64");
+    if (max_iters < 0) return fail(SPT_E_INVALID_ARG, "max_iters < 0");
+    if (!lambda || !fit_out || !iters_out) return fail(SPT_E_INVALID_ARG, "NULL output");
+    if (!(t->norm_x2 > 0.0)) return fail(SPT_E_INVALID_ARG, "tensor norm is zero");
+    spt_status st = check_factors(t, (const float *const *)factors, rank, -1);
+    if (st != SPT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int N = t->nmodes;
+    const int R = rank;
+    int64_t maxI = 0;
+    size_t gw = 0;
+    for (int n = 0; n < N; ++n) {
+        maxI = std::max(maxI, t->dims[n]);
+        gw = std::max(gw, gram_work_bytes(t->dims[n], R));
+    }
+    const int inner_parts = apply_blocks(t->dims[N - 1], R);
+    const int64_t resid_tiles = (t->nnz + 1023) / 1024;
+    float *M = (float *)dev_alloc(sizeof(float) * maxI * R, s);
+    double *grams = (double *)dev_alloc(sizeof(double) * N * R * R, s);
+    double *gram_m = (double *)dev_alloc(sizeof(double) * R * R, s);
+    double *S = (double *)dev_alloc(sizeof(double) * R * R, s);
+    double *gwork = (double *)dev_alloc(gw, s);
+    double *inner = (double *)dev_alloc(sizeof(double) * inner_parts, s);
+    double *resid = (double *)dev_alloc(sizeof(double) * 2 * std::max<int64_t>(resid_tiles, 1), s);
+    double *fitd = (double *)dev_alloc(sizeof(double) * 4 + sizeof(int) * kMaxModes, s);
+    auto cleanup = [&]() {
+        dev_free(M, s); dev_free(grams, s); dev_free(gram_m, s); dev_free(S, s); dev_free(gwork, s);
+        dev_free(inner, s); dev_free(resid, s); dev_free(fitd, s);
+    };
+    if (!M || !grams || !gram_m || !S || !gwork || !inner || !resid || !fitd) {
+        cleanup();
+        return fail(SPT_E_OOM, "cp_als: workspace allocation failed");
+    }
+    int *status = (int *)(fitd + 4);
+#define CK(x)                    \
+    do {                         \
+        spt_status st__ = (x);   \
+        if (st__ != SPT_OK) {    \
+            cleanup();           \
+            return st__;         \
+        }                        \
+    } while (0)
+    for (int k = 0; k < N; ++k) CK(launch_gram(factors[k], t->dims[k], R, grams + (size_t)k * R * R, gwork, gw, s));
+    double fit = 0.0, fit_prev = 0.0;
+    int it = 0;
+    while (it < max_iters) {
+        for (int n = 0; n < N; ++n) {
+            const int64_t In = t->dims[n];
+            CK(launch_fill_zero(M, In * R, s));
+            const MttkrpArgs a = make_args(t, (const float *const *)factors, R, n, M, t->plan.tile[n]);
+            CK(launch_mttkrp(a, t->plan.strategy[n], s));
+            CK(launch_gram(M, In, R, gram_m, gwork, gw, s));
+            CK(launch_solve_prep(grams, N, n, R, gram_m, S, lambda, status + n, s));
+            CK(launch_apply(M, In, R, S, factors[n], lambda, n == N - 1 ? inner : nullptr, nullptr, s));
+            CK(launch_gram(factors[n], In, R, grams + (size_t)n * R * R, gwork, gw, s));
+        }
+        CK(launch_fit(grams, N, R, lambda, inner, inner_parts, t->norm_x2, fitd, s));
+        double hf[4];
+        int hs[kMaxModes];
+        if (hipMemcpyAsync(hf, fitd, sizeof(hf), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hs, status, sizeof(int) * N, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            cleanup();
+            return hip_fail(hipGetLastError(), "cp_als: fit readback");
+        }
+        for (int n = 0; n < N; ++n)
+            if (hs[n] < 0) {
+                cleanup();
+                return fail(SPT_E_NOT_SPD, "cp_als: normal equations of mode " + std::to_string(n) +
+                                               " not positive definite after ridge retries");
+            }
+        fit = hf[0];
+        if (1.0 - fit < 1e-2 && t->nnz > 0) {
+            // near convergence the Gram shortcut loses accuracy (FP32 MTTKRP); take the
+            // residual directly over the nonzeros in FP64
+            MttkrpArgs a = make_args(t, (const float *const *)factors, R, -1, nullptr, 1024);
+            CK(launch_resid(a, lambda, resid, (int)resid_tiles, s));
+            CK(launch_fit_direct(resid, (int)resid_tiles, t->norm_x2, fitd, s));
+            if (hipMemcpyAsync(hf, fitd, sizeof(hf), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                cleanup();
+                return hip_fail(hipGetLastError(), "cp_als: direct fit readback");
+            }
+            fit = hf[0];
+        }
+        ++it;
+        if (tol > 0.0 && std::fabs(fit - fit_prev) < tol) break;
+        fit_prev = fit;
+    }
+#undef CK
+    cleanup();
+    *fit_out = fit;
+    *iters_out = it;
+    return SPT_OK;
+}
+
+}  // extern "C"

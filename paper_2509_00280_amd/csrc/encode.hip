@@ -1,0 +1,434 @@
+// Linearized-tensor construction on gfx950 (Section III-C, problem formulation):
+// bit deposit of every coordinate into an l(p)-bit key, then a stable LSD radix
+// sort of (key, input index) over the l(p) significant bits, then the value
+// gather and the FP64 sum of squares.
+//
+// Radix sort design (one pass per 8-bit digit):
+//   hist    : per 4096-element tile, a 256-bin digit histogram (per-wave LDS bins)
+//   scan    : one workgroup per digit scans the tiles' counts (digit-major array)
+//   scatter : each tile ranks its elements stably (wave ballots give the rank among
+//             equal digits in lane order, LDS carries counts across waves and rounds),
+//             regroups them by digit in LDS, then writes runs of equal digit
+//             contiguously so global stores coalesce.
+#include "spt_internal.h"
+
+namespace spt {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void deposit_runs(const Codec &c, int n, uint32_t coord, uint32_t (&w)[4]) {
+#pragma unroll
+    for (int word = 0; word < 4; ++word) {
+        const int r0 = c.rb[n][word], r1 = c.rb[n][word + 1];
+        for (int r = r0; r < r1; ++r) {
+            const Run run = c.runs[r];
+            const uint32_t bits = __builtin_amdgcn_ubfe(coord, run.cpos, run.len);
+            w[word] |= bits << run.kpos;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t extract_runs(const Codec &c, int n, const uint32_t (&w)[4]) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int word = 0; word < 4; ++word) {
+        const int r0 = c.rb[n][word], r1 = c.rb[n][word + 1];
+        for (int r = r0; r < r1; ++r) {
+            const Run run = c.runs[r];
+            x |= __builtin_amdgcn_ubfe(w[word], run.kpos, run.len) << run.cpos;
+        }
+    }
+    return x;
+}
+
+struct DimsArg {
+    uint32_t d[kMaxModes];
+};
+
+// key = interleave(coords); idx = e.  err[0] counts out-of-range nonzeros,
+// err[1] holds the smallest offending nonzero index, err[2] its mode.
+__global__ __launch_bounds__(kThreads) void k_deposit(const uint32_t *__restrict__ coords, int64_t nnz,
+                                                      DimsArg dims, Codec codec, uint64_t *__restrict__ lo,
+                                                      uint64_t *__restrict__ hi, int *__restrict__ err) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kThreads) {
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int n = 0; n < codec.nmodes; ++n) {
+            const uint32_t i = __builtin_nontemporal_load(coords + (int64_t)n * nnz + e);
+            if (i >= dims.d[n]) {
+                atomicAdd(err, 1);
+                atomicMin((unsigned long long *)(err + 2), ((unsigned long long)e << 8) | (unsigned)n);
+            }
+            deposit_runs(codec, n, i, w);
+        }
+        lo[e] = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+        if (codec.key_words == 2) hi[e] = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+    }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                         uint32_t *__restrict__ counts, int nblocks) {
+    __shared__ uint32_t h[4][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) h[w][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * ITEMS);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t e = base + i * kThreads + tid;
+        if (e < n) {
+            const uint32_t d = (uint32_t)(keys[e] >> shift) & 255u;
+            atomicAdd(&h[wave][d], 1u);
+        }
+    }
+    __syncthreads();
+    counts[(int64_t)tid * nblocks + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+}
+
+// Exclusive scan of counts[d * nblocks + b] over b for one digit d per workgroup.
+__global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t *__restrict__ counts, int nblocks,
+                                                         uint32_t *__restrict__ totals) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t carry_s;
+    const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t *row = counts + (int64_t)d * nblocks;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nblocks; b0 += kThreads) {
+        const int b = b0 + tid;
+        const uint32_t v = b < nblocks ? row[b] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int w = 0; w < wave; ++w) wbase += wsum[w];
+        const uint32_t carry = carry_s;
+        if (b < nblocks) row[b] = carry + wbase + x - v;
+        __syncthreads();
+        if (tid == kThreads - 1) carry_s = carry + wbase + x;
+        __syncthreads();
+    }
+    if (tid == 0) totals[d] = carry_s;
+}
+
+// Exclusive scan of 256 values held one per thread (block of 256).
+__device__ __forceinline__ uint32_t block_scan_256(uint32_t v, uint32_t *wsum) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    __syncthreads();
+    return base + x - v;
+}
+
+template <int KW, int ITEMS>
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const uint64_t *__restrict__ in_lo, const uint64_t *__restrict__ in_hi, const uint32_t *__restrict__ in_idx,
+    uint64_t *__restrict__ out_lo, uint64_t *__restrict__ out_hi, uint32_t *__restrict__ out_idx, int64_t n,
+    int word, int shift, const uint32_t *__restrict__ counts, const uint32_t *__restrict__ totals, int nblocks) {
+    constexpr int TILE = kThreads * ITEMS;
+    __shared__ uint64_t s_lo[TILE];
+    __shared__ uint64_t s_hi[KW == 2 ? TILE : 1];
+    __shared__ uint32_t s_idx[TILE];
+    __shared__ uint32_t digit_off[256];
+    __shared__ uint32_t local_start[256];
+    __shared__ uint32_t run_cnt[256];
+    __shared__ uint32_t wc[4][256];
+    __shared__ uint32_t wsum[4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x;
+    const int64_t base = (int64_t)b * TILE;
+
+    {
+        const uint32_t tot = totals[tid];
+        const uint32_t digit_base = block_scan_256(tot, wsum);
+        const uint32_t mine = counts[(int64_t)tid * nblocks + b];
+        const uint32_t next = (b + 1 < nblocks) ? counts[(int64_t)tid * nblocks + b + 1] : tot;
+        const uint32_t cnt_b = next - mine;
+        digit_off[tid] = digit_base + mine;
+        local_start[tid] = block_scan_256(cnt_b, wsum);
+        run_cnt[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    }
+    __syncthreads();
+
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t e = base + i * kThreads + tid;
+        const bool valid = e < n;
+        uint64_t klo = 0, khi = 0;
+        uint32_t idx = 0, d = 0;
+        if (valid) {
+            klo = in_lo[e];
+            if (KW == 2) khi = in_hi[e];
+            idx = in_idx ? in_idx[e] : (uint32_t)e;
+            d = (uint32_t)(((word == 0) ? klo : khi) >> shift) & 255u;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t m = __ballot(valid && ((d >> bit) & 1u));
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        const uint32_t rank_w = __popcll(peers & lt_mask);
+        if (valid && rank_w == 0) wc[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = local_start[d] + run_cnt[d] + rank_w;
+            for (int w = 0; w < wave; ++w) pos += wc[w][d];
+            s_lo[pos] = klo;
+            if (KW == 2) s_hi[pos] = khi;
+            s_idx[pos] = idx;
+        }
+        __syncthreads();
+        run_cnt[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+        __syncthreads();
+    }
+
+    const int cnt = (int)((n - base) < TILE ? (n - base) : TILE);
+    for (int q = tid; q < cnt; q += kThreads) {
+        const uint64_t klo = s_lo[q];
+        const uint64_t khi = (KW == 2) ? s_hi[q] : 0;
+        const uint32_t d = (uint32_t)(((word == 0) ? klo : khi) >> shift) & 255u;
+        const int64_t dst = (int64_t)digit_off[d] + (q - (int)local_start[d]);
+        out_lo[dst] = klo;
+        if (KW == 2) out_hi[dst] = khi;
+        out_idx[dst] = s_idx[q];
+    }
+}
+
+// vals_out[j] = vals_in[idx[j]]; per-block partial sums of squares in FP64.
+__global__ __launch_bounds__(kThreads) void k_gather_vals(const float *__restrict__ vin, const uint32_t *__restrict__ idx,
+                                                          float *__restrict__ vout, int64_t n,
+                                                          double *__restrict__ partials) {
+    __shared__ double ws[4];
+    double acc = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
+        const float v = vin[idx[j]];
+        vout[j] = v;
+        acc += (double)v * (double)v;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(kThreads) void k_decode(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
+                                                     int64_t nnz, Codec codec, uint32_t *__restrict__ coords) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kThreads) {
+        const uint64_t a = lo[e];
+        const uint64_t b = codec.key_words == 2 ? hi[e] : 0;
+        const uint32_t w[4] = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+        for (int n = 0; n < codec.nmodes; ++n) coords[(int64_t)n * nnz + e] = extract_runs(codec, n, w);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_export_keys(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
+                                                          int64_t nnz, int kw, uint64_t *__restrict__ keys) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kThreads) {
+        if (kw == 2) {
+            keys[2 * e] = lo[e];
+            keys[2 * e + 1] = hi[e];
+        } else {
+            keys[e] = lo[e];
+        }
+    }
+}
+
+__global__ void k_init_err(int *err) {
+    err[0] = 0;
+    err[1] = 0;
+    *(unsigned long long *)(err + 2) = ~0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_f64(const double *__restrict__ parts, int n, double *__restrict__ out) {
+    __shared__ double ws[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) acc += parts[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void k_zero_f64(double *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+int grid_for(int64_t n, int per_block, int cap) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+__global__ void k_iota(uint32_t *p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = (uint32_t)e;
+}
+
+// Stable LSD sort of (lo[, hi]) keys over the t->lp significant bits.  On
+// success *lo_io / *hi_io point at the sorted keys (the other buffers are
+// released) and *idx_out at the input index of every sorted element.
+template <int KW, int ITEMS>
+spt_status radix_sort(const Tensor *t, uint64_t **lo_io, uint64_t **hi_io, uint32_t **idx_out, hipStream_t s) {
+    const int64_t n = t->nnz;
+    constexpr int TILE = kThreads * ITEMS;
+    const int nblocks = (int)((n + TILE - 1) / TILE);
+    const int passes = (t->lp + 7) / 8;
+    uint64_t *lo = *lo_io, *hi = *hi_io;
+    uint64_t *lo2 = passes ? (uint64_t *)dev_alloc(sizeof(uint64_t) * n, s) : nullptr;
+    uint64_t *hi2 = (KW == 2 && passes) ? (uint64_t *)dev_alloc(sizeof(uint64_t) * n, s) : nullptr;
+    uint32_t *idx_a = (uint32_t *)dev_alloc(sizeof(uint32_t) * n, s);
+    uint32_t *idx_b = passes > 1 ? (uint32_t *)dev_alloc(sizeof(uint32_t) * n, s) : nullptr;
+    uint32_t *counts = (uint32_t *)dev_alloc(sizeof(uint32_t) * 256 * (size_t)nblocks, s);
+    uint32_t *totals = (uint32_t *)dev_alloc(sizeof(uint32_t) * 256, s);
+    if ((passes && !lo2) || (KW == 2 && passes && !hi2) || !idx_a || (passes > 1 && !idx_b) || !counts || !totals) {
+        dev_free(lo2, s); dev_free(hi2, s); dev_free(idx_a, s); dev_free(idx_b, s);
+        dev_free(counts, s); dev_free(totals, s);
+        return fail(SPT_E_OOM, "radix sort: device allocation failed");
+    }
+    uint64_t *src_lo = lo, *src_hi = hi, *dst_lo = lo2, *dst_hi = hi2;
+    uint32_t *src_idx = nullptr, *dst_idx = idx_a;
+    for (int p = 0; p < passes; ++p) {
+        const int bit = 8 * p;
+        const int word = bit / 64, shift = bit % 64;
+        const uint64_t *kw = word == 0 ? src_lo : src_hi;
+        hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3(nblocks), dim3(kThreads), 0, s, kw, n, shift, counts, nblocks);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, counts, nblocks, totals);
+        hipLaunchKernelGGL((k_radix_scatter<KW, ITEMS>), dim3(nblocks), dim3(kThreads), 0, s, src_lo, src_hi, src_idx,
+                           dst_lo, dst_hi, dst_idx, n, word, shift, counts, totals, nblocks);
+        SPT_HIP(hipGetLastError());
+        std::swap(src_lo, dst_lo);
+        std::swap(src_hi, dst_hi);
+        src_idx = dst_idx;
+        dst_idx = (dst_idx == idx_a) ? idx_b : idx_a;
+    }
+    if (src_idx == nullptr) {  // no key bits at all: the input order is the sorted order
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(n, kThreads, 65536)), dim3(kThreads), 0, s, idx_a, n);
+        SPT_HIP(hipGetLastError());
+        src_idx = idx_a;
+    }
+    dev_free(dst_lo, s);  // after the swap, dst_* is the buffer not holding the result
+    if (KW == 2) dev_free(dst_hi, s);
+    dev_free(src_idx == idx_a ? idx_b : idx_a, s);
+    dev_free(counts, s);
+    dev_free(totals, s);
+    *lo_io = src_lo;
+    *hi_io = KW == 2 ? src_hi : nullptr;
+    *idx_out = src_idx;
+    return SPT_OK;
+}
+
+}  // namespace
+
+spt_status launch_encode(Tensor *t, const uint32_t *coords, const float *vals, hipStream_t s) {
+    const int64_t n = t->nnz;
+    const int64_t n1 = n > 0 ? n : 1;
+    t->lo = t->hi = nullptr;
+    t->vals = nullptr;
+    t->perm = nullptr;
+    t->norm_x2 = 0.0;
+    int *err = (int *)dev_alloc(64, s);
+    double *partials = (double *)dev_alloc(sizeof(double) * 1025, s);
+    uint64_t *lo = (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s);
+    uint64_t *hi = t->key_words == 2 ? (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s) : nullptr;
+    float *vout = (float *)dev_alloc(sizeof(float) * n1, s);
+    uint32_t *idx = nullptr;
+    auto cleanup = [&]() {
+        dev_free(err, s); dev_free(partials, s); dev_free(lo, s); dev_free(hi, s); dev_free(vout, s);
+        dev_free(idx, s);
+    };
+    if (!err || !partials || !lo || (t->key_words == 2 && !hi) || !vout) {
+        cleanup();
+        return fail(SPT_E_OOM, "encode: device allocation failed");
+    }
+    DimsArg dims{};
+    for (int k = 0; k < t->nmodes; ++k) dims.d[k] = (uint32_t)t->dims[k];
+    hipLaunchKernelGGL(k_init_err, dim3(1), dim3(1), 0, s, err);
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, partials + 1024, 1);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_deposit, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, coords, n, dims,
+                           t->codec, lo, hi, err);
+        SPT_HIP(hipGetLastError());
+        // keys whose coordinates were out of range are still valid bit patterns,
+        // so sorting them is harmless; the single check below rejects the tensor.
+        spt_status st = t->key_words == 2 ? radix_sort<2, 8>(t, &lo, &hi, &idx, s)
+                                          : radix_sort<1, 16>(t, &lo, &hi, &idx, s);
+        if (st != SPT_OK) {
+            cleanup();
+            return st;
+        }
+        const int g = grid_for(n, kThreads * 8, 1024);
+        hipLaunchKernelGGL(k_gather_vals, dim3(g), dim3(kThreads), 0, s, vals, idx, vout, n, partials);
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kThreads), 0, s, partials, g, partials + 1024);
+        SPT_HIP(hipGetLastError());
+    } else {
+        idx = (uint32_t *)dev_alloc(sizeof(uint32_t), s);
+    }
+    struct {
+        int e[4];
+        double nx2;
+    } h{};
+    SPT_HIP(hipMemcpyAsync(h.e, err, sizeof(h.e), hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipMemcpyAsync(&h.nx2, partials + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    if (h.e[0] != 0) {
+        const unsigned long long packed = (unsigned long long)(uint32_t)h.e[2] | ((unsigned long long)(uint32_t)h.e[3] << 32);
+        cleanup();
+        return fail(SPT_E_INDEX_RANGE, std::to_string(h.e[0]) + " coordinate(s) out of range; first at nonzero " +
+                                           std::to_string(packed >> 8) + ", mode " + std::to_string(packed & 255));
+    }
+    dev_free(err, s);
+    dev_free(partials, s);
+    t->lo = lo;
+    t->hi = hi;
+    t->vals = vout;
+    t->perm = idx;
+    t->norm_x2 = h.nx2;
+    return SPT_OK;
+}
+
+spt_status launch_decode(const Tensor *t, uint32_t *coords, hipStream_t s) {
+    if (t->nnz == 0) return SPT_OK;
+    hipLaunchKernelGGL(k_decode, dim3(grid_for(t->nnz, kThreads, 16384)), dim3(kThreads), 0, s, t->lo, t->hi, t->nnz,
+                       t->codec, coords);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s) {
+    if (t->nnz == 0) return SPT_OK;
+    hipLaunchKernelGGL(k_export_keys, dim3(grid_for(t->nnz, kThreads, 16384)), dim3(kThreads), 0, s, t->lo, t->hi,
+                       t->nnz, t->key_words, keys);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_sum_f64(const double *parts, int n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kThreads), 0, s, parts, n, out);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+}  // namespace spt

@@ -1,0 +1,127 @@
+// Internal declarations shared by the library's HIP and host sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/spt.h"
+
+namespace spt {
+
+constexpr int kMaxModes = SPT_MAX_MODES;
+constexpr int kMaxRuns = 160;          // l(p) <= 128 bits plus splits at 32-bit word boundaries
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+
+// A maximal group of consecutive coordinate bits that land on consecutive key
+// bits inside one 32-bit word of the key: coordinate bits [cpos, cpos+len) of
+// mode n  <->  bits [kpos, kpos+len) of 32-bit key word `word`.
+struct Run {
+    uint8_t word;
+    uint8_t kpos;
+    uint8_t cpos;
+    uint8_t len;
+};
+
+// Bit map between coordinates and keys, passed by value to kernels.
+// Runs of mode n that live in key word w are runs[rb[n][w] .. rb[n][w+1]).
+struct Codec {
+    int nmodes;
+    int key_words;  // 64-bit words per key: 1 or 2
+    uint8_t rb[kMaxModes][5];
+    Run runs[kMaxRuns];
+};
+
+// Build the codec of a layout (layout[t] = mode feeding key bit t).
+void make_codec(int nmodes, const int *lbits, const uint8_t *layout, int lp, Codec *c);
+
+// ---------------------------------------------------------------- device memory
+void *dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+spt_status fail(spt_status st, const std::string &msg);
+spt_status hip_fail(hipError_t e, const char *what);
+
+#define SPT_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e__ = (call);                                        \
+        if (e__ != hipSuccess) return ::spt::hip_fail(e__, #call);      \
+    } while (0)
+
+// ---------------------------------------------------------------- tensor handle
+struct Tensor {
+    int nmodes = 0;
+    int64_t nnz = 0;
+    int64_t dims[kMaxModes] = {};
+    int lbits[kMaxModes] = {};
+    int lp = 0;
+    int key_words = 1;
+    uint8_t layout[SPT_MAX_KEY_BITS] = {};
+    Codec codec{};
+    uint64_t *lo = nullptr;   // nnz key words (bits 0..63)
+    uint64_t *hi = nullptr;   // nnz key words (bits 64..127), only when key_words == 2
+    float *vals = nullptr;    // nnz values in key order
+    uint32_t *perm = nullptr; // input index of each element
+    double norm_x2 = 0.0;
+    spt_plan plan{};
+};
+
+// ---------------------------------------------------------------- kernels (launchers)
+// encode.hip
+spt_status launch_encode(Tensor *t, const uint32_t *coords, const float *vals, hipStream_t s);
+spt_status launch_decode(const Tensor *t, uint32_t *coords, hipStream_t s);
+spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s);
+
+// mttkrp.hip
+struct MttkrpArgs {
+    const uint64_t *lo;
+    const uint64_t *hi;
+    const float *vals;
+    int64_t nnz;
+    int nmodes;
+    int mode;
+    int rank;
+    int tile;
+    const float *f[kMaxModes];
+    float *out;
+    Codec codec;
+};
+spt_status launch_fill_zero(float *p, int64_t n, hipStream_t s);
+spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s);
+
+// Per-tensor descriptor of the batched persistent MTTKRP.
+struct BatchItem {
+    MttkrpArgs a;
+    int64_t first_tile;  // prefix sum of tiles over the batch
+    int strategy;
+    int pad;
+};
+spt_status launch_mttkrp_batched(const BatchItem *items_dev, int count, int64_t total_tiles,
+                                 int nmodes_max, int *counter_dev, hipStream_t s);
+
+// residual over the nonzeros (direct fit): out2[0] += sum (v - xhat)^2, out2[1] += sum xhat^2
+spt_status launch_resid(const MttkrpArgs &a, const double *lam, double *partials, int nparts, hipStream_t s);
+
+// dense.hip
+spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double *work, size_t work_bytes,
+                       hipStream_t s);
+size_t gram_work_bytes(int64_t rows, int rank);
+// solve preparation: V = Hadamard of grams[k != mode]; Cholesky with ridge; W = V^-1;
+// lambda_r = sqrt((W Gm W)_rr) (1 if 0); S = W diag(1/lambda).  status_out: 0 ok, >0 ridge retries, <0 failure.
+spt_status launch_solve_prep(const double *grams, int nmodes, int mode, int rank, const double *gram_m,
+                             double *S, double *lambda, int *status_out, hipStream_t s);
+// C = fp32(M S) row by row; optional fused inner-product partials sum_{i,r} M C lambda.
+spt_status launch_apply(const float *M, int64_t rows, int rank, const double *S, float *C,
+                        const double *lambda, double *inner_partials, int *nparts_out, hipStream_t s);
+int apply_blocks(int64_t rows, int rank);
+// fit: out[0] = fit (shortcut), out[1] = |Xhat|^2; reads inner partials
+spt_status launch_fit(const double *grams, int nmodes, int rank, const double *lambda,
+                      const double *inner_partials, int nparts, double norm_x2, double *out, hipStream_t s);
+spt_status launch_fit_direct(const double *resid_partials, int nparts, double norm_x2, double *out,
+                             hipStream_t s);
+spt_status launch_sum_f64(const double *parts, int n, double *out, hipStream_t s);
+
+}  // namespace spt
