@@ -66,11 +66,21 @@ typedef struct {
     double norm_x2;                      /* sum of squared values, FP64 */
 } spt_tensor_info;
 
-/* Per-mode execution plan of MTTKRP (chosen by a heuristic or spt_autotune). */
-#define SPT_STRATEGY_DIRECT 0   /* walk nonzeros in key order; atomics at every change of output row */
+/*
+ * Per-mode execution plan of MTTKRP (chosen by a heuristic or spt_autotune).
+ * Every strategy computes the same result; they differ in how the partial
+ * sums of nonzeros that share an output row are combined.
+ */
+#define SPT_STRATEGY_DIRECT 0   /* walk nonzeros in key order; FP32 atomics at every change of output row */
 #define SPT_STRATEGY_REGROUP 1  /* regroup each tile by output row in LDS; atomics once per (tile chunk, row) */
+#define SPT_STRATEGY_TABLE 2    /* persistent workgroups accumulate rows in an LDS table; flushed rows are
+                                   written as records and summed per row after a radix sort (no atomics
+                                   except for rows split between two reducer chunks) */
+#define SPT_STRATEGY_PRIV 3     /* the whole output (or column slices of it) lives in each workgroup's LDS;
+                                   workgroup partials are summed (small modes) */
+#define SPT_STRATEGY_AUTO 4     /* PRIV when the output fits LDS in at most two column passes, else TABLE */
 typedef struct {
-    int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256, 512 or 1024 */
+    int tile[SPT_MAX_MODES];      /* DIRECT/REGROUP: nonzeros per workgroup tile: 256, 512 or 1024 */
     int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
 } spt_plan;
 
@@ -129,7 +139,9 @@ void spt_tensor_free(spt_tensor t);
  * factors[k][i_k, :].  FP32 inputs, FP32 accumulation (order unspecified).
  *   factors  host array of nmodes device pointers (factors[mode] is not read).
  *   out      device, I_mode x rank, OVERWRITTEN (rows without nonzeros are 0).
- * Fully asynchronous; host-side argument checks only.  1 <= rank <= SPT_MAX_RANK.
+ * Asynchronous; host-side argument checks only.  1 <= rank <= SPT_MAX_RANK.
+ * The first call at a (mode, rank) under the TABLE strategy builds that
+ * mode's plan (a counting pass) and synchronises the stream once.
  */
 spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
                       void *stream);

@@ -77,20 +77,22 @@ void make_codec(int nmodes, const int *lbits, const uint8_t *layout, int lp, Cod
         while (j < (int)pos.size()) {
             const int kp = pos[j];
             int len = 1;
-            while (j + len < (int)pos.size() && pos[j + len] == kp + len && (kp + len) / 32 == kp / 32) ++len;
-            c->runs[nr++] = Run{(uint8_t)(kp / 32), (uint8_t)(kp % 32), (uint8_t)j, (uint8_t)len};
+            while (len < 31 && j + len < (int)pos.size() && pos[j + len] == kp + len && (kp + len) / 32 == kp / 32)
+                ++len;
+            c->run[nr++] = pack_run(kp / 32, kp % 32, j, len);
             j += len;
         }
         const int end = nr;
         for (int w = 0; w <= 4; ++w) {
             int r = start;
-            while (r < end && c->runs[r].word < w) ++r;
+            while (r < end && (int)(c->run[r] & 0xFFu) < w) ++r;
             c->rb[n][w] = (uint8_t)(w == 4 ? end : r);
         }
         (void)lbits;
     }
     for (int n = nmodes; n < kMaxModes; ++n)
         for (int w = 0; w <= 4; ++w) c->rb[n][w] = (uint8_t)nr;
+    c->nruns = nr;
 }
 
 static int bit_length(int64_t d) {  // ceil(log2 d) for d >= 1
@@ -102,7 +104,7 @@ static int bit_length(int64_t d) {  // ceil(log2 d) for d >= 1
 static void default_plan(const Tensor *t, spt_plan *p) {
     for (int n = 0; n < kMaxModes; ++n) {
         p->tile[n] = 1024;
-        p->strategy[n] = SPT_STRATEGY_REGROUP;
+        p->strategy[n] = SPT_STRATEGY_AUTO;
     }
     (void)t;
 }
@@ -111,7 +113,7 @@ static bool plan_ok(const spt_plan *p, int nmodes) {
     for (int n = 0; n < nmodes; ++n) {
         const int T = p->tile[n];
         if (T != 256 && T != 512 && T != 1024) return false;
-        if (p->strategy[n] != SPT_STRATEGY_DIRECT && p->strategy[n] != SPT_STRATEGY_REGROUP) return false;
+        if (p->strategy[n] < SPT_STRATEGY_DIRECT || p->strategy[n] > SPT_STRATEGY_AUTO) return false;
     }
     return true;
 }
@@ -128,7 +130,7 @@ MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int
     a.mode = mode;
     a.rank = rank;
     a.tile = tile;
-    for (int k = 0; k < t->nmodes; ++k) a.f[k] = factors[k];
+    for (int k = 0; k < t->nmodes; ++k) a.f[k] = factors ? factors[k] : nullptr;
     a.out = out;
     a.codec = t->codec;
     return a;
@@ -270,7 +272,7 @@ spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
 
 spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
     if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
-    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256/512/1024 and strategy 0/1");
+    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256/512/1024 and strategy 0..4");
     t->plan = *plan;
     return SPT_OK;
 }
@@ -280,6 +282,7 @@ void spt_tensor_free(spt_tensor t) {
     // the handle's buffers were allocated stream-ordered; release them on the null
     // stream after the device is idle so no in-flight kernel still reads them
     (void)hipDeviceSynchronize();
+    release_plans(t);
     dev_free(t->lo, nullptr);
     dev_free(t->hi, nullptr);
     dev_free(t->vals, nullptr);
@@ -295,11 +298,7 @@ spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int m
     if (!aligned16(out)) return fail(SPT_E_INVALID_ARG, "out not 16-byte aligned");
     spt_status st = check_factors(t, factors, rank, mode);
     if (st != SPT_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    st = launch_fill_zero(out, t->dims[mode] * (int64_t)rank, s);
-    if (st != SPT_OK) return st;
-    const MttkrpArgs a = make_args(t, factors, rank, mode, out, t->plan.tile[mode]);
-    return launch_mttkrp(a, t->plan.strategy[mode], s);
+    return run_mttkrp(t, factors, rank, mode, out, (hipStream_t)stream);
 }
 
 spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *const *factors, double *lambda,
@@ -353,9 +352,7 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
     while (it < max_iters) {
         for (int n = 0; n < N; ++n) {
             const int64_t In = t->dims[n];
-            CK(launch_fill_zero(M, In * R, s));
-            const MttkrpArgs a = make_args(t, (const float *const *)factors, R, n, M, t->plan.tile[n]);
-            CK(launch_mttkrp(a, t->plan.strategy[n], s));
+            CK(run_mttkrp(t, (const float *const *)factors, R, n, M, s));
             CK(launch_gram(M, In, R, gram_m, gwork, gw, s));
             CK(launch_solve_prep(grams, N, n, R, gram_m, S, lambda, status + n, s));
             CK(launch_apply(M, In, R, S, factors[n], lambda, n == N - 1 ? inner : nullptr, nullptr, s));

@@ -10,7 +10,7 @@
 //             equal digits in lane order, LDS carries counts across waves and rounds),
 //             regroups them by digit in LDS, then writes runs of equal digit
 //             contiguously so global stores coalesce.
-#include "spt_internal.h"
+#include "tile_common.h"
 
 namespace spt {
 
@@ -18,29 +18,21 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ void deposit_runs(const Codec &c, int n, uint32_t coord, uint32_t (&w)[4]) {
+__device__ __forceinline__ void deposit_runs(const CodecRegs &c, int n, uint32_t coord, uint32_t (&w)[4]) {
 #pragma unroll
     for (int word = 0; word < 4; ++word) {
-        const int r0 = c.rb[n][word], r1 = c.rb[n][word + 1];
+        const int r0 = __builtin_amdgcn_readlane(c.rb, n * 5 + word);
+        const int r1 = __builtin_amdgcn_readlane(c.rb, n * 5 + word + 1);
         for (int r = r0; r < r1; ++r) {
-            const Run run = c.runs[r];
-            const uint32_t bits = __builtin_amdgcn_ubfe(coord, run.cpos, run.len);
-            w[word] |= bits << run.kpos;
+            const uint32_t d = run_desc(c, r);
+            const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
+            w[word] |= __builtin_amdgcn_ubfe(coord, cpos, len) << kpos;
         }
     }
 }
 
-__device__ __forceinline__ uint32_t extract_runs(const Codec &c, int n, const uint32_t (&w)[4]) {
-    uint32_t x = 0;
-#pragma unroll
-    for (int word = 0; word < 4; ++word) {
-        const int r0 = c.rb[n][word], r1 = c.rb[n][word + 1];
-        for (int r = r0; r < r1; ++r) {
-            const Run run = c.runs[r];
-            x |= __builtin_amdgcn_ubfe(w[word], run.kpos, run.len) << run.cpos;
-        }
-    }
-    return x;
+__device__ __forceinline__ uint32_t extract_runs(const CodecRegs &c, int n, const uint32_t (&w)[4]) {
+    return decode_mode(c, n, 4, w);
 }
 
 struct DimsArg {
@@ -52,6 +44,7 @@ struct DimsArg {
 __global__ __launch_bounds__(kThreads) void k_deposit(const uint32_t *__restrict__ coords, int64_t nnz,
                                                       DimsArg dims, Codec codec, uint64_t *__restrict__ lo,
                                                       uint64_t *__restrict__ hi, int *__restrict__ err) {
+    const CodecRegs cl = load_codec_regs(codec);
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kThreads) {
         uint32_t w[4] = {0, 0, 0, 0};
         for (int n = 0; n < codec.nmodes; ++n) {
@@ -60,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_deposit(const uint32_t *__restrict
                 atomicAdd(err, 1);
                 atomicMin((unsigned long long *)(err + 2), ((unsigned long long)e << 8) | (unsigned)n);
             }
-            deposit_runs(codec, n, i, w);
+            deposit_runs(cl, n, i, w);
         }
         lo[e] = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
         if (codec.key_words == 2) hi[e] = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
@@ -235,11 +228,12 @@ __global__ __launch_bounds__(kThreads) void k_gather_vals(const float *__restric
 
 __global__ __launch_bounds__(kThreads) void k_decode(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
                                                      int64_t nnz, Codec codec, uint32_t *__restrict__ coords) {
+    const CodecRegs cl = load_codec_regs(codec);
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kThreads) {
         const uint64_t a = lo[e];
         const uint64_t b = codec.key_words == 2 ? hi[e] : 0;
         const uint32_t w[4] = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
-        for (int n = 0; n < codec.nmodes; ++n) coords[(int64_t)n * nnz + e] = extract_runs(codec, n, w);
+        for (int n = 0; n < codec.nmodes; ++n) coords[(int64_t)n * nnz + e] = extract_runs(cl, n, w);
     }
 }
 
@@ -291,11 +285,10 @@ __global__ void k_iota(uint32_t *p, int64_t n) {
 // success *lo_io / *hi_io point at the sorted keys (the other buffers are
 // released) and *idx_out at the input index of every sorted element.
 template <int KW, int ITEMS>
-spt_status radix_sort(const Tensor *t, uint64_t **lo_io, uint64_t **hi_io, uint32_t **idx_out, hipStream_t s) {
-    const int64_t n = t->nnz;
+spt_status radix_sort(int64_t n, int nbits, uint64_t **lo_io, uint64_t **hi_io, uint32_t **idx_out, hipStream_t s) {
     constexpr int TILE = kThreads * ITEMS;
     const int nblocks = (int)((n + TILE - 1) / TILE);
-    const int passes = (t->lp + 7) / 8;
+    const int passes = (nbits + 7) / 8;
     uint64_t *lo = *lo_io, *hi = *hi_io;
     uint64_t *lo2 = passes ? (uint64_t *)dev_alloc(sizeof(uint64_t) * n, s) : nullptr;
     uint64_t *hi2 = (KW == 2 && passes) ? (uint64_t *)dev_alloc(sizeof(uint64_t) * n, s) : nullptr;
@@ -373,8 +366,8 @@ spt_status launch_encode(Tensor *t, const uint32_t *coords, const float *vals, h
         SPT_HIP(hipGetLastError());
         // keys whose coordinates were out of range are still valid bit patterns,
         // so sorting them is harmless; the single check below rejects the tensor.
-        spt_status st = t->key_words == 2 ? radix_sort<2, 8>(t, &lo, &hi, &idx, s)
-                                          : radix_sort<1, 16>(t, &lo, &hi, &idx, s);
+        spt_status st = t->key_words == 2 ? radix_sort<2, 8>(n, t->lp, &lo, &hi, &idx, s)
+                                          : radix_sort<1, 16>(n, t->lp, &lo, &hi, &idx, s);
         if (st != SPT_OK) {
             cleanup();
             return st;
@@ -423,6 +416,15 @@ spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s) {
                        t->nnz, t->key_words, keys);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
+}
+
+spt_status sort_u64_keys(uint64_t **keys_io, int64_t n, int nbits, uint32_t **idx_out, hipStream_t s) {
+    if (n <= 0) {
+        *idx_out = nullptr;
+        return SPT_OK;
+    }
+    uint64_t *hi = nullptr;
+    return radix_sort<1, 16>(n, nbits, keys_io, &hi, idx_out, s);
 }
 
 spt_status launch_sum_f64(const double *parts, int n, double *out, hipStream_t s) {

@@ -22,7 +22,7 @@
 // Workgroups are mapped to tiles XCD-aware: consecutive workgroup ids are
 // dealt round-robin over the 8 XCDs, so each XCD gets a contiguous range of
 // tiles and its L2 sees the locality of the key order.
-#include "spt_internal.h"
+#include "tile_common.h"
 
 namespace spt {
 
@@ -63,12 +63,6 @@ __device__ __forceinline__ uint32_t row_hash(uint32_t r, int hbits) {
     return (r ^ (r >> hbits) ^ (r >> (2 * hbits)));
 }
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nwg) {
-    const int64_t q = nwg >> 3, r = nwg & 7;
-    const int64_t x = b & 7, j = b >> 3;
-    return x * q + (x < r ? x : r) + j;
-}
-
 // In-place exclusive scan of n (multiple of 256, <= 2048) u32 values in LDS.
 __device__ __forceinline__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *wsum) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -98,7 +92,7 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t *a, int n, uint32_
 // tile order sorted by coordinate of mode `gmode`.  Returns the valid count.
 template <int NMAX, bool REGROUP>
 __device__ __forceinline__ int stage_tile(const MttkrpArgs &a, int64_t tile, const TileLds &L, int gmode,
-                                          uint32_t *wsum) {
+                                          uint32_t *wsum, const CodecRegs &cr) {
     const int T = a.tile;
     const int tid = threadIdx.x;
     const int64_t base = tile * (int64_t)T;
@@ -141,11 +135,13 @@ __device__ __forceinline__ int stage_tile(const MttkrpArgs &a, int64_t tile, con
 #pragma unroll
             for (int word = 0; word < 4; ++word) {
                 if (word < nwords) {
-                    const int r0 = a.codec.rb[k][word], r1 = a.codec.rb[k][word + 1];
+                    const int r0 = __builtin_amdgcn_readlane(cr.rb, k * 5 + word);
+                    const int r1 = __builtin_amdgcn_readlane(cr.rb, k * 5 + word + 1);
                     for (int r = r0; r < r1; ++r) {
-                        const Run run = a.codec.runs[r];
+                        const uint32_t d = run_desc(cr, r);
+                        const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) x[u] |= __builtin_amdgcn_ubfe(w[u][word], run.kpos, run.len) << run.cpos;
+                        for (int u = 0; u < 4; ++u) x[u] |= __builtin_amdgcn_ubfe(w[u][word], kpos, len) << cpos;
                     }
                 }
             }
@@ -205,20 +201,6 @@ __device__ __forceinline__ void flush_row(float *__restrict__ out, uint32_t row,
 #pragma unroll
             for (int q = 0; q < VEC; ++q) unsafeAtomicAdd(o + col + q, acc.v[b][q]);
         }
-    }
-}
-
-template <int VEC>
-__device__ __forceinline__ void load_vec(const float *p, float (&x)[VEC]) {
-    if constexpr (VEC == 4) {
-        const float4 t = *reinterpret_cast<const float4 *>(p);
-        x[0] = t.x;
-        x[1] = t.y;
-        x[2] = t.z;
-        x[3] = t.w;
-    } else {
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) x[q] = p[q];
     }
 }
 
@@ -310,7 +292,8 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs a, int64_t ntile
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const TileLds L = carve(lds, a.tile, NMAX);
-    const int cnt = stage_tile<NMAX, REGROUP>(a, tile, L, a.mode, wsum);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    const int cnt = stage_tile<NMAX, REGROUP>(a, tile, L, a.mode, wsum, cr);
     walk_tile<G, VEC, NB, NMAX, REGROUP>(a, L, cnt);
 }
 
@@ -351,15 +334,16 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_batched(const BatchItem *__
             else hi = mid - 1;
         }
         const int b = __builtin_amdgcn_readfirstlane(lo);
-        const MttkrpArgs a = items[b].a;
+        const MttkrpArgs &a = items[b].a;
         const int strategy = items[b].strategy;
         const int64_t tile = it - items[b].first_tile;
         const TileLds L = carve(lds, a.tile, NMAX);
+        const CodecRegs cr = load_codec_regs(a.codec);
         if (strategy == SPT_STRATEGY_REGROUP) {
-            const int cnt = stage_tile<NMAX, true>(a, tile, L, a.mode, wsum);
+            const int cnt = stage_tile<NMAX, true>(a, tile, L, a.mode, wsum, cr);
             walk_any<NMAX, true>(a, L, cnt);
         } else {
-            const int cnt = stage_tile<NMAX, false>(a, tile, L, a.mode, wsum);
+            const int cnt = stage_tile<NMAX, false>(a, tile, L, a.mode, wsum, cr);
             walk_any<NMAX, false>(a, L, cnt);
         }
         __syncthreads();  // LDS is reused by the next item
@@ -377,7 +361,8 @@ __global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles
     __shared__ double red[2][kThreads / 64];
     const int64_t tile = blockIdx.x;
     const TileLds L = carve(lds, a.tile, NMAX);
-    const int cnt = stage_tile<NMAX, false>(a, tile, L, -1, wsum);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    const int cnt = stage_tile<NMAX, false>(a, tile, L, -1, wsum, cr);
     constexpr int GROUPS = kThreads / G;
     const int tid = threadIdx.x, g = tid / G, j = tid % G;
     const int R = a.rank, T = a.tile;

@@ -1,0 +1,218 @@
+// MTTKRP launch plans: strategy resolution, LDS sizing and the counting pass
+// that fixes every workgroup's record offsets for the TABLE strategy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "spt_internal.h"
+
+namespace spt {
+
+namespace {
+
+// Dynamic LDS available to one table/privatised workgroup (160 KB per CU on
+// gfx950, minus the kernel's static LDS and a margin).
+constexpr size_t kLdsBudget = 160 * 1024 - 512;
+
+int next_pow2_bits(int v) {
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+// Largest accumulator that fits LDS for the TABLE strategy; cap >= sub-tile size.
+bool table_params(int nmodes, int R, int *ts, int *cap, int *hbits, int *stride) {
+    const int st = R + 1;
+    for (int t : {512, 256}) {
+        int best = 0, best_h = 0;
+        for (int c = 16; c <= 8192; c += 16) {
+            const int hb = next_pow2_bits(2 * c);
+            if (table_lds_needed(nmodes, t, c, hb, st, false, true) > kLdsBudget) break;
+            best = c;
+            best_h = hb;
+        }
+        if (best >= t) {
+            *ts = t;
+            *cap = best;
+            *hbits = best_h;
+            *stride = st;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Column passes for PRIV: the smallest pass count whose slice fits LDS.
+bool priv_params(int nmodes, int64_t rows, int R, int max_pass, int *npass, int *rs, int *stride) {
+    if (rows > 65535) return false;
+    for (int p = 1; p <= max_pass; p *= 2) {
+        int w = (R + p - 1) / p;
+        if ((R & 3) == 0) w = (w + 3) & ~3;
+        if ((int64_t)(p - 1) * w >= R) break;
+        const int st = w + 1;
+        if (table_lds_needed(nmodes, 512, (int)rows, 0, st, true, true) <= kLdsBudget) {
+            *npass = (R + w - 1) / w;
+            *rs = w;
+            *stride = st;
+            return true;
+        }
+    }
+    return false;
+}
+
+}  // namespace
+
+int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+void release_plans(Tensor *t) {
+    for (int n = 0; n < kMaxModes; ++n) {
+        if (t->mplan[n].rec_off) (void)hipFree(t->mplan[n].rec_off);
+        t->mplan[n] = ModePlan{};
+    }
+}
+
+spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out) {
+    ModePlan &p = t->mplan[mode];
+    int want = t->plan.strategy[mode];
+    const int64_t rows = t->dims[mode];
+    int npass = 1, rs = rank, stride = rank + 1;
+    if (want == SPT_STRATEGY_AUTO) {
+        want = priv_params(t->nmodes, rows, rank, 2, &npass, &rs, &stride) ? SPT_STRATEGY_PRIV : SPT_STRATEGY_TABLE;
+    }
+    if (p.valid && p.rank == rank && p.strategy == want) {
+        *out = &p;
+        return SPT_OK;
+    }
+    if (p.rec_off) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(p.rec_off);
+    }
+    p = ModePlan{};
+    p.rank = rank;
+    p.strategy = want;
+    if (want == SPT_STRATEGY_PRIV) {
+        if (!priv_params(t->nmodes, rows, rank, 64, &npass, &rs, &stride))
+            return fail(SPT_E_INVALID_ARG, "PRIV strategy: mode " + std::to_string(mode) + " output does not fit LDS");
+        const int64_t nsub = (t->nnz + 511) / 512;
+        p.ts = 512;
+        p.cap = (int)rows;
+        p.npass = npass;
+        p.rs = rs;
+        p.stride = stride;
+        p.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(device_cus(), nsub));
+        p.sub_per_wg = (nsub + p.nwg - 1) / p.nwg;
+        p.nwg = (int)std::max<int64_t>(1, (nsub + p.sub_per_wg - 1) / std::max<int64_t>(p.sub_per_wg, 1));
+    } else if (want == SPT_STRATEGY_TABLE) {
+        if (!table_params(t->nmodes, rank, &p.ts, &p.cap, &p.hbits, &p.stride))
+            return fail(SPT_E_INVALID_ARG, "TABLE strategy: rank too large for the LDS accumulator");
+        const int64_t nsub = (t->nnz + p.ts - 1) / p.ts;
+        p.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(device_cus(), nsub));
+        p.sub_per_wg = std::max<int64_t>(1, (nsub + p.nwg - 1) / p.nwg);
+        p.nwg = (int)std::max<int64_t>(1, (nsub + p.sub_per_wg - 1) / p.sub_per_wg);
+        // counting pass: the same flush decisions as the real kernel, records only counted
+        int64_t *cnt = nullptr;
+        SPT_HIP(hipMalloc(&cnt, sizeof(int64_t) * p.nwg));
+        TableArgs ta{};
+        ta.a = make_args(t, nullptr, rank, mode, nullptr, 0);
+        ta.cap = p.cap;
+        ta.hbits = p.hbits;
+        ta.stride = p.stride;
+        ta.rs = rank;
+        ta.ts = p.ts;
+        ta.sub_per_wg = p.sub_per_wg;
+        ta.rec_cnt = cnt;
+        spt_status st = t->nnz > 0 ? launch_table_count(ta, p.nwg, s) : SPT_OK;
+        std::vector<int64_t> h(p.nwg, 0);
+        if (st == SPT_OK && t->nnz > 0) {
+            if (hipMemcpyAsync(h.data(), cnt, sizeof(int64_t) * p.nwg, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                st = hip_fail(hipGetLastError(), "plan: record counts");
+        }
+        if (st != SPT_OK) {
+            (void)hipFree(cnt);
+            return st;
+        }
+        int64_t run = 0;
+        for (int w = 0; w < p.nwg; ++w) {
+            const int64_t c = h[w];
+            h[w] = run;
+            run += c;
+        }
+        p.records = run;
+        if (hipMemcpy(cnt, h.data(), sizeof(int64_t) * p.nwg, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(cnt);
+            return hip_fail(hipGetLastError(), "plan: record offsets");
+        }
+        p.rec_off = cnt;
+    } else {
+        p.ts = t->plan.tile[mode];
+    }
+    p.valid = 1;
+    *out = &p;
+    return SPT_OK;
+}
+
+spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
+    ModePlan *p = nullptr;
+    spt_status st = resolve_plan(t, mode, rank, s, &p);
+    if (st != SPT_OK) return st;
+    const int64_t rows = t->dims[mode];
+    if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
+        st = launch_fill_zero(out, rows * (int64_t)rank, s);
+        if (st != SPT_OK || t->nnz == 0) return st;
+        return launch_mttkrp(make_args(t, factors, rank, mode, out, t->plan.tile[mode]), p->strategy, s);
+    }
+    TableArgs ta{};
+    ta.a = make_args(t, factors, rank, mode, out, 0);
+    ta.cap = p->cap;
+    ta.hbits = p->hbits;
+    ta.stride = p->stride;
+    ta.rs = p->rs;
+    ta.ts = p->ts;
+    ta.sub_per_wg = p->sub_per_wg;
+    if (p->strategy == SPT_STRATEGY_PRIV) {
+        float *part = (float *)dev_alloc(sizeof(float) * (size_t)p->nwg * rows * rank, s);
+        if (!part) return fail(SPT_E_OOM, "mttkrp: partials allocation failed");
+        ta.rec_val = part;
+        st = launch_priv(ta, p->nwg, p->npass, s);
+        if (st == SPT_OK) st = launch_reduce_priv(part, p->nwg, rows, rank, out, s);
+        dev_free(part, s);
+        return st;
+    }
+    // TABLE
+    const int64_t P = p->records;
+    uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * std::max<int64_t>(P, 1), s);
+    float *rval = (float *)dev_alloc(sizeof(float) * std::max<int64_t>(P, 1) * rank, s);
+    if (!rrow || !rval) {
+        dev_free(rrow, s);
+        dev_free(rval, s);
+        return fail(SPT_E_OOM, "mttkrp: record allocation failed");
+    }
+    ta.rec_row = rrow;
+    ta.rec_val = rval;
+    ta.rec_off = p->rec_off;
+    st = launch_table(ta, p->nwg, s);
+    uint32_t *idx = nullptr;
+    if (st == SPT_OK) st = sort_u64_keys(&rrow, P, t->lbits[mode], &idx, s);
+    if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
+    if (st == SPT_OK) st = launch_reduce_records(rrow, idx, rval, P, rank, out, s);
+    dev_free(rrow, s);
+    dev_free(rval, s);
+    dev_free(idx, s);
+    return st;
+}
+
+}  // namespace spt

@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/spt.h"
+#include "spt.h"  // include/ is on the include path
 
 namespace spt {
 
@@ -16,21 +16,21 @@ constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
 // A maximal group of consecutive coordinate bits that land on consecutive key
 // bits inside one 32-bit word of the key: coordinate bits [cpos, cpos+len) of
-// mode n  <->  bits [kpos, kpos+len) of 32-bit key word `word`.
-struct Run {
-    uint8_t word;
-    uint8_t kpos;
-    uint8_t cpos;
-    uint8_t len;
-};
+// mode n  <->  bits [kpos, kpos+len) of 32-bit key word `word`.  Packed as
+// word | kpos << 8 | cpos << 16 | len << 24.
+__host__ __device__ inline uint32_t pack_run(int word, int kpos, int cpos, int len) {
+    return (uint32_t)word | ((uint32_t)kpos << 8) | ((uint32_t)cpos << 16) | ((uint32_t)len << 24);
+}
 
 // Bit map between coordinates and keys, passed by value to kernels.
-// Runs of mode n that live in key word w are runs[rb[n][w] .. rb[n][w+1]).
+// Runs of mode n that live in 32-bit key word w are run[rb[n][w] .. rb[n][w+1]).
 struct Codec {
     int nmodes;
     int key_words;  // 64-bit words per key: 1 or 2
+    int nruns;
+    int pad;
     uint8_t rb[kMaxModes][5];
-    Run runs[kMaxRuns];
+    uint32_t run[kMaxRuns];
 };
 
 // Build the codec of a layout (layout[t] = mode feeding key bit t).
@@ -52,6 +52,17 @@ spt_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // ---------------------------------------------------------------- tensor handle
+// Resolved launch plan of one mode at one rank (plan.cpp).
+struct ModePlan {
+    int valid = 0;
+    int rank = 0;
+    int strategy = -1;       // resolved: DIRECT, REGROUP, TABLE or PRIV
+    int cap = 0, hbits = 0, stride = 0, rs = 0, npass = 1, ts = 512, nwg = 0;
+    int64_t sub_per_wg = 0;
+    int64_t records = 0;     // TABLE: records written per call
+    int64_t *rec_off = nullptr;  // TABLE: device, nwg offsets
+};
+
 struct Tensor {
     int nmodes = 0;
     int64_t nnz = 0;
@@ -67,13 +78,26 @@ struct Tensor {
     uint32_t *perm = nullptr; // input index of each element
     double norm_x2 = 0.0;
     spt_plan plan{};
+    ModePlan mplan[kMaxModes];
 };
+
+// plan.cpp
+int device_cus();
+spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out);
+// mode-`mode` MTTKRP into out (overwritten), per the tensor's plan
+spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+void release_plans(Tensor *t);
 
 // ---------------------------------------------------------------- kernels (launchers)
 // encode.hip
 spt_status launch_encode(Tensor *t, const uint32_t *coords, const float *vals, hipStream_t s);
 spt_status launch_decode(const Tensor *t, uint32_t *coords, hipStream_t s);
 spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s);
+// Stable LSD radix sort of n 64-bit keys over their low nbits bits.  *keys_io is
+// replaced by the sorted keys (the input buffer may be released); *idx_out
+// receives a new buffer with the input index of every sorted key.  Buffers come
+// from dev_alloc on stream s.
+spt_status sort_u64_keys(uint64_t **keys_io, int64_t n, int nbits, uint32_t **idx_out, hipStream_t s);
 
 // mttkrp.hip
 struct MttkrpArgs {
@@ -90,6 +114,7 @@ struct MttkrpArgs {
     Codec codec;
 };
 spt_status launch_fill_zero(float *p, int64_t n, hipStream_t s);
+MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int mode, float *out, int tile);
 spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s);
 
 // Per-tensor descriptor of the batched persistent MTTKRP.
@@ -101,6 +126,29 @@ struct BatchItem {
 };
 spt_status launch_mttkrp_batched(const BatchItem *items_dev, int count, int64_t total_tiles,
                                  int nmodes_max, int *counter_dev, hipStream_t s);
+
+// mttkrp_table.hip: persistent-workgroup LDS accumulation (see that file).
+struct TableArgs {
+    MttkrpArgs a;
+    int cap;      // accumulator rows (TABLE) or output rows (PRIV)
+    int hbits;    // log2 of the accumulator hash index size (TABLE)
+    int stride;   // floats per accumulator row (columns + 1 padding)
+    int rs;       // PRIV: columns per pass
+    int ts;       // nonzeros per sub-tile: 256 or 512
+    int pad;
+    int64_t sub_per_wg;
+    uint64_t *rec_row;        // TABLE: record rows
+    float *rec_val;           // TABLE: records [P][R]; PRIV: partials [W][rows][R]
+    const int64_t *rec_off;   // TABLE: first record of each workgroup
+    int64_t *rec_cnt;         // counting pass: records of each workgroup
+};
+size_t table_lds_needed(int nmodes, int ts, int cap, int hbits, int stride, bool priv, bool with_acc);
+spt_status launch_table_count(const TableArgs &t, int nwg, hipStream_t s);
+spt_status launch_table(const TableArgs &t, int nwg, hipStream_t s);
+spt_status launch_priv(const TableArgs &t, int nwg, int npass, hipStream_t s);
+spt_status launch_reduce_priv(const float *part, int nwg, int64_t rows, int R, float *out, hipStream_t s);
+spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, const float *rec_val, int64_t P, int R,
+                                 float *out, hipStream_t s);
 
 // residual over the nonzeros (direct fit): out2[0] += sum (v - xhat)^2, out2[1] += sum xhat^2
 spt_status launch_resid(const MttkrpArgs &a, const double *lam, double *partials, int nparts, hipStream_t s);

@@ -71,9 +71,36 @@ def draw_labels(rng: np.random.Generator, n: int, count: int, dist) -> np.ndarra
     assert kind == "zipf"
     cdf = zipf_cdf(n, s)
     u = rng.random(count)
-    idx = np.searchsorted(cdf, u, side="right")
+    idx = _searchsorted_right(cdf, u)
     np.minimum(idx, n - 1, out=idx)
     return idx.astype(np.uint32)
+
+
+def _searchsorted_right(table: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """``np.searchsorted(table, x, side='right')`` (multi-threaded through torch when present)."""
+    try:
+        import torch
+    except ImportError:
+        return np.searchsorted(table, x, side="right")
+    return torch.searchsorted(torch.from_numpy(table), torch.from_numpy(x), right=True).numpy()
+
+
+def _first_occurrences(lin: np.ndarray) -> np.ndarray:
+    """Indices of the first occurrence of every distinct value, in increasing index order.
+
+    Same result as ``np.sort(np.unique(lin, return_index=True)[1])``; a stable
+    sort keeps the earliest index first among equal values.
+    """
+    try:
+        import torch
+    except ImportError:
+        return np.sort(np.unique(lin, return_index=True)[1])
+    sv, si = torch.sort(torch.from_numpy(lin), stable=True)
+    head = torch.ones(sv.shape[0], dtype=torch.bool)
+    if sv.shape[0] > 1:
+        head[1:] = sv[1:] != sv[:-1]
+    first, _ = torch.sort(si[head])
+    return first.numpy()
 
 
 def _draw_values(rng: np.random.Generator, count: int, vdist) -> np.ndarray:
@@ -124,8 +151,7 @@ def distinct_coo(seed: int, dims, nnz: int, mode_dists, vdist, max_rounds: int =
         v = _draw_values(rv, m, vdist)
         lin = _linear(c, dims)
         all_lin = np.concatenate([kept_lin, lin])
-        _, first = np.unique(all_lin, return_index=True)
-        first.sort()
+        first = _first_occurrences(all_lin)
         first = first[first >= kept_lin.shape[0]] - kept_lin.shape[0]
         kept_c = np.concatenate([kept_c, c[:, first]], axis=1)
         kept_v = np.concatenate([kept_v, v[first]])

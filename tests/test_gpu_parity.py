@@ -87,7 +87,7 @@ def test_encode_bad_layout(spt):
 
 
 @pytest.mark.parametrize("rank", [16, 5, 32, 64])
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
 def test_mttkrp_small_all_modes(spt, small, rank, strategy):
     t, _, _, _ = small
     F = synth.normal_factors(100 + rank, t.dims, rank)
@@ -102,18 +102,53 @@ def test_mttkrp_small_all_modes(spt, small, rank, strategy):
         assert bad == 0 and err <= TOL
 
 
-@pytest.mark.parametrize("tile", [256, 512, 1024])
-def test_mttkrp_skewed_tiles_ragged(spt, tile):
+@pytest.mark.parametrize("tile,strategy", [(256, 1), (512, 1), (1024, 1), (1024, 2), (1024, 4)])
+def test_mttkrp_skewed_tiles_ragged(spt, tile, strategy):
     # 4-mode power-law tensor with a ragged last tile, rank 64
     t, F, rank, _ = synth.config("skewed4d", nnz=300_001)
     c, v = to_dev(t)
     h = spt.encode(t.dims, c, v)
-    h.set_plan(tile=tile)
+    h.set_plan(tile=tile, strategy=strategy)
     Fd = factors_dev(F)
     for n in range(4):
         out = spt.mttkrp(h, Fd, n).cpu().numpy()
         err, bad = mttkrp_error(t, F, n, out)
         print(f"tile {tile} mode {n}: err {err:.3e}", flush=True)
+        assert bad == 0 and err <= TOL
+
+
+@pytest.mark.parametrize("strategy", [2, 3])
+def test_mttkrp_priv_column_passes_and_table_flushes(spt, strategy):
+    # mode 0 (1000 rows x rank 64) needs two LDS column passes under PRIV;
+    # under TABLE every mode flushes its accumulator many times
+    rng = np.random.default_rng(8)
+    dims = (1000, 300, 50)
+    n = 400_000
+    coords = np.stack([rng.integers(0, d, size=n) for d in dims]).astype(np.uint32)
+    t = synth.SparseCOO(dims, coords, rng.standard_normal(n).astype(np.float32))
+    F = synth.normal_factors(9, dims, 64)
+    c, v = to_dev(t)
+    h = spt.encode(dims, c, v)
+    h.set_plan(strategy=strategy)
+    Fd = factors_dev(F)
+    for mode in range(3):
+        out = spt.mttkrp(h, Fd, mode).cpu().numpy()
+        err, bad = mttkrp_error(t, F, mode, out)
+        print(f"strategy {strategy} mode {mode}: err {err:.3e}", flush=True)
+        assert bad == 0 and err <= TOL
+
+
+@pytest.mark.parametrize("strategy", [2, 4])
+def test_mttkrp_ratings_table_parity(spt, strategy):
+    t, F, rank, _ = synth.config("ratings", nnz=2_000_000)
+    c, v = to_dev(t)
+    h = spt.encode(t.dims, c, v)
+    h.set_plan(strategy=strategy)
+    Fd = factors_dev(F)
+    for mode in range(3):
+        out = spt.mttkrp(h, Fd, mode).cpu().numpy()
+        err, bad = mttkrp_error(t, F, mode, out)
+        print(f"ratings strategy {strategy} mode {mode}: err {err:.3e}", flush=True)
         assert bad == 0 and err <= TOL
 
 
