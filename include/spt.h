@@ -78,7 +78,12 @@ typedef struct {
                                    except for rows split between two reducer chunks) */
 #define SPT_STRATEGY_PRIV 3     /* the whole output (or column slices of it) lives in each workgroup's LDS;
                                    workgroup partials are summed (small modes) */
-#define SPT_STRATEGY_AUTO 4     /* PRIV when the output fits LDS in at most two column passes, else TABLE */
+#define SPT_STRATEGY_AUTO 4     /* PRIV for outputs that fit LDS in one pass with at most 256 rows,
+                                   else SEGMENT */
+#define SPT_STRATEGY_SEGMENT 5  /* regroup each tile by output row in LDS; every segment sum becomes a
+                                   record written with plain stores; records are radix-sorted by row
+                                   and summed (no atomics except for rows split between two reducer
+                                   chunks) */
 typedef struct {
     int tile[SPT_MAX_MODES];      /* DIRECT/REGROUP: nonzeros per workgroup tile: 256, 512 or 1024 */
     int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
@@ -140,8 +145,8 @@ void spt_tensor_free(spt_tensor t);
  *   factors  host array of nmodes device pointers (factors[mode] is not read).
  *   out      device, I_mode x rank, OVERWRITTEN (rows without nonzeros are 0).
  * Asynchronous; host-side argument checks only.  1 <= rank <= SPT_MAX_RANK.
- * The first call at a (mode, rank) under the TABLE strategy builds that
- * mode's plan (a counting pass) and synchronises the stream once.
+ * The first call at a (mode, rank) under the TABLE or SEGMENT strategy
+ * builds that mode's plan (a counting pass) and synchronises the stream once.
  */
 spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
                       void *stream);

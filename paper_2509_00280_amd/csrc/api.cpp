@@ -113,7 +113,7 @@ static bool plan_ok(const spt_plan *p, int nmodes) {
     for (int n = 0; n < nmodes; ++n) {
         const int T = p->tile[n];
         if (T != 256 && T != 512 && T != 1024) return false;
-        if (p->strategy[n] < SPT_STRATEGY_DIRECT || p->strategy[n] > SPT_STRATEGY_AUTO) return false;
+        if (p->strategy[n] < SPT_STRATEGY_DIRECT || p->strategy[n] > SPT_STRATEGY_SEGMENT) return false;
     }
     return true;
 }
@@ -272,7 +272,9 @@ spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
 
 spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
     if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
-    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256/512/1024 and strategy 0..4");
+    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256/512/1024 and strategy 0..5");
+    (void)hipDeviceSynchronize();  // resolved plans (record offsets) may still be in use
+    release_plans(t);
     t->plan = *plan;
     return SPT_OK;
 }

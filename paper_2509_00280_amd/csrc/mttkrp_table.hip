@@ -391,7 +391,7 @@ template <int G, int VEC, int NB>
 __global__ __launch_bounds__(256) void k_reduce_records(const uint64_t *__restrict__ srow,
                                                         const uint32_t *__restrict__ sidx,
                                                         const float *__restrict__ rec_val, int64_t P, int R,
-                                                        int chunk, float *__restrict__ out) {
+                                                        int chunk, int64_t rows, float *__restrict__ out) {
     constexpr int GROUPS = 256 / G;
     const int g = threadIdx.x / G, j = threadIdx.x % G;
     const int64_t c0 = ((int64_t)blockIdx.x * GROUPS + g) * chunk;
@@ -407,6 +407,7 @@ __global__ __launch_bounds__(256) void k_reduce_records(const uint64_t *__restri
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[b][v] = 0.f;
     auto emit = [&](uint64_t r, bool whole) {
+        if (r >= (uint64_t)rows) return;  // sentinel records of unused slots
         float *o = out + (int64_t)r * R;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -512,13 +513,13 @@ spt_status launch_reduce_priv(const float *part, int nwg, int64_t rows, int R, f
 }
 
 spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, const float *rec_val, int64_t P, int R,
-                                 float *out, hipStream_t s) {
+                                 int64_t rows, float *out, hipStream_t s) {
     if (P <= 0) return SPT_OK;
     constexpr int chunk = 16;
     auto go = [&](auto kern, int G) -> spt_status {
         const int groups = 256 / G;
         const int64_t blocks = (P + (int64_t)groups * chunk - 1) / ((int64_t)groups * chunk);
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, srow, sidx, rec_val, P, R, chunk, out);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, srow, sidx, rec_val, P, R, chunk, rows, out);
         SPT_HIP(hipGetLastError());
         return SPT_OK;
     };

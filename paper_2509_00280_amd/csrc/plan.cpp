@@ -90,7 +90,8 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
     const int64_t rows = t->dims[mode];
     int npass = 1, rs = rank, stride = rank + 1;
     if (want == SPT_STRATEGY_AUTO) {
-        want = priv_params(t->nmodes, rows, rank, 2, &npass, &rs, &stride) ? SPT_STRATEGY_PRIV : SPT_STRATEGY_TABLE;
+        want = (rows <= 256 && priv_params(t->nmodes, rows, rank, 1, &npass, &rs, &stride)) ? SPT_STRATEGY_PRIV
+                                                                                              : SPT_STRATEGY_SEGMENT;
     }
     if (p.valid && p.rank == rank && p.strategy == want) {
         *out = &p;
@@ -157,6 +158,39 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
             return hip_fail(hipGetLastError(), "plan: record offsets");
         }
         p.rec_off = cnt;
+    } else if (want == SPT_STRATEGY_SEGMENT) {
+        // counting pass: distinct output rows of every tile; a tile's record range
+        // holds those plus (groups - 1) slots for segments cut by chunk edges
+        p.ts = t->plan.tile[mode];
+        const int64_t ntiles = (t->nnz + p.ts - 1) / p.ts;
+        int64_t *off = nullptr;
+        SPT_HIP(hipMalloc(&off, sizeof(int64_t) * (ntiles + 1)));
+        std::vector<int64_t> h(ntiles + 1, 0);
+        spt_status st = SPT_OK;
+        if (ntiles > 0) {
+            st = launch_count_distinct(make_args(t, nullptr, rank, mode, nullptr, p.ts), off, s);
+            if (st == SPT_OK && (hipMemcpyAsync(h.data(), off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                                 hipStreamSynchronize(s) != hipSuccess))
+                st = hip_fail(hipGetLastError(), "plan: distinct rows per tile");
+        }
+        if (st != SPT_OK) {
+            (void)hipFree(off);
+            return st;
+        }
+        const int slack = seg_groups(rank) - 1;
+        int64_t run = 0;
+        for (int64_t i = 0; i < ntiles; ++i) {
+            const int64_t c = h[i] + slack;
+            h[i] = run;
+            run += c;
+        }
+        h[ntiles] = run;
+        p.records = run;
+        if (hipMemcpy(off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(off);
+            return hip_fail(hipGetLastError(), "plan: record offsets");
+        }
+        p.rec_off = off;
     } else {
         p.ts = t->plan.tile[mode];
     }
@@ -170,6 +204,30 @@ spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode
     spt_status st = resolve_plan(t, mode, rank, s, &p);
     if (st != SPT_OK) return st;
     const int64_t rows = t->dims[mode];
+    if (p->strategy == SPT_STRATEGY_SEGMENT && t->nnz > 0) {
+        const int64_t P = p->records;
+        uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * std::max<int64_t>(P, 1), s);
+        float *rval = (float *)dev_alloc(sizeof(float) * std::max<int64_t>(P, 1) * rank, s);
+        if (!rrow || !rval) {
+            dev_free(rrow, s);
+            dev_free(rval, s);
+            return fail(SPT_E_OOM, "mttkrp: record allocation failed");
+        }
+        MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
+        a.rec_row = rrow;
+        a.rec_val = rval;
+        a.rec_off = p->rec_off;
+        a.rec_sentinel = (uint64_t)1 << t->lbits[mode];
+        st = launch_mttkrp_seg(a, s);
+        uint32_t *idx = nullptr;
+        if (st == SPT_OK) st = sort_u64_keys(&rrow, P, t->lbits[mode] + 1, &idx, s);
+        if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
+        if (st == SPT_OK) st = launch_reduce_records(rrow, idx, rval, P, rank, rows, out, s);
+        dev_free(rrow, s);
+        dev_free(rval, s);
+        dev_free(idx, s);
+        return st;
+    }
     if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
         st = launch_fill_zero(out, rows * (int64_t)rank, s);
         if (st != SPT_OK || t->nnz == 0) return st;
@@ -208,7 +266,7 @@ spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode
     uint32_t *idx = nullptr;
     if (st == SPT_OK) st = sort_u64_keys(&rrow, P, t->lbits[mode], &idx, s);
     if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
-    if (st == SPT_OK) st = launch_reduce_records(rrow, idx, rval, P, rank, out, s);
+    if (st == SPT_OK) st = launch_reduce_records(rrow, idx, rval, P, rank, rows, out, s);
     dev_free(rrow, s);
     dev_free(rval, s);
     dev_free(idx, s);

@@ -111,11 +111,19 @@ struct MttkrpArgs {
     int tile;
     const float *f[kMaxModes];
     float *out;
+    // SEGMENT strategy: record output
+    uint64_t *rec_row;
+    float *rec_val;
+    const int64_t *rec_off;   // per tile, ntiles + 1 entries
+    uint64_t rec_sentinel;
     Codec codec;
 };
 spt_status launch_fill_zero(float *p, int64_t n, hipStream_t s);
 MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int mode, float *out, int tile);
 spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s);
+int seg_groups(int rank);
+spt_status launch_count_distinct(const MttkrpArgs &a, int64_t *counts, hipStream_t s);
+spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 
 // Per-tensor descriptor of the batched persistent MTTKRP.
 struct BatchItem {
@@ -148,7 +156,7 @@ spt_status launch_table(const TableArgs &t, int nwg, hipStream_t s);
 spt_status launch_priv(const TableArgs &t, int nwg, int npass, hipStream_t s);
 spt_status launch_reduce_priv(const float *part, int nwg, int64_t rows, int R, float *out, hipStream_t s);
 spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, const float *rec_val, int64_t P, int R,
-                                 float *out, hipStream_t s);
+                                 int64_t rows, float *out, hipStream_t s);
 
 // residual over the nonzeros (direct fit): out2[0] += sum (v - xhat)^2, out2[1] += sum xhat^2
 spt_status launch_resid(const MttkrpArgs &a, const double *lam, double *partials, int nparts, hipStream_t s);

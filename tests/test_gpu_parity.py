@@ -87,7 +87,7 @@ def test_encode_bad_layout(spt):
 
 
 @pytest.mark.parametrize("rank", [16, 5, 32, 64])
-@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4, 5])
 def test_mttkrp_small_all_modes(spt, small, rank, strategy):
     t, _, _, _ = small
     F = synth.normal_factors(100 + rank, t.dims, rank)
@@ -102,7 +102,8 @@ def test_mttkrp_small_all_modes(spt, small, rank, strategy):
         assert bad == 0 and err <= TOL
 
 
-@pytest.mark.parametrize("tile,strategy", [(256, 1), (512, 1), (1024, 1), (1024, 2), (1024, 4)])
+@pytest.mark.parametrize("tile,strategy", [(256, 1), (512, 1), (1024, 1), (1024, 2), (1024, 4), (256, 5), (512, 5),
+                                           (1024, 5)])
 def test_mttkrp_skewed_tiles_ragged(spt, tile, strategy):
     # 4-mode power-law tensor with a ragged last tile, rank 64
     t, F, rank, _ = synth.config("skewed4d", nnz=300_001)
@@ -117,7 +118,7 @@ def test_mttkrp_skewed_tiles_ragged(spt, tile, strategy):
         assert bad == 0 and err <= TOL
 
 
-@pytest.mark.parametrize("strategy", [2, 3])
+@pytest.mark.parametrize("strategy", [2, 3, 5])
 def test_mttkrp_priv_column_passes_and_table_flushes(spt, strategy):
     # mode 0 (1000 rows x rank 64) needs two LDS column passes under PRIV;
     # under TABLE every mode flushes its accumulator many times
@@ -138,7 +139,7 @@ def test_mttkrp_priv_column_passes_and_table_flushes(spt, strategy):
         assert bad == 0 and err <= TOL
 
 
-@pytest.mark.parametrize("strategy", [2, 4])
+@pytest.mark.parametrize("strategy", [2, 4, 5])
 def test_mttkrp_ratings_table_parity(spt, strategy):
     t, F, rank, _ = synth.config("ratings", nnz=2_000_000)
     c, v = to_dev(t)
