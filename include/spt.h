@@ -267,6 +267,24 @@ void spt_server_destroy(spt_server s);
 
 /* ---------------------------------------------------------------------- */
 
+/* ---------------------------------------------------------------------- */
+/* Instrumentation.                                                        */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * on != 0: from now on bracket every MTTKRP call (spt_mttkrp, and the
+ * MTTKRP steps inside spt_cp_als) with two HIP events on its stream.  Any
+ * call clears what was recorded.  Adds two event records per call.
+ */
+spt_status spt_profile_enable(int on);
+
+/*
+ * Host out: ms[n] = summed GPU time of the recorded MTTKRP calls of mode n,
+ * launches[n] = their count (arrays of SPT_MAX_MODES).  Waits for the
+ * recorded events.
+ */
+spt_status spt_profile_read(double *ms, int64_t *launches);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *spt_last_error(void);
 

@@ -159,6 +159,13 @@ const char *spt_last_error(void) { return g_last_error.c_str(); }
 
 const char *spt_version(void) { return "spt-gfx950 0.1"; }
 
+spt_status spt_profile_enable(int on) { return profile_enable(on); }
+
+spt_status spt_profile_read(double *ms, int64_t *launches) {
+    if (!ms || !launches) return fail(SPT_E_INVALID_ARG, "NULL output");
+    return profile_read(ms, launches);
+}
+
 spt_status spt_encode(const int64_t *dims, int nmodes, const uint32_t *coords, const float *vals, int64_t nnz,
                       const uint8_t *layout, int layout_len, void *stream, spt_tensor *out) {
     if (!dims || !out) return fail(SPT_E_INVALID_ARG, "dims/out is NULL");
@@ -285,6 +292,7 @@ void spt_tensor_free(spt_tensor t) {
     // stream after the device is idle so no in-flight kernel still reads them
     (void)hipDeviceSynchronize();
     release_plans(t);
+    release_ws(t);
     dev_free(t->lo, nullptr);
     dev_free(t->hi, nullptr);
     dev_free(t->vals, nullptr);

@@ -10,6 +10,8 @@
 //   apply       C = fp32(M S) row block by row block (FP64 FMAs), with the
 //               fit's inner product sum M .* C * lambda fused in.
 //   fit         |Xhat|^2 = lambda^T (Hadamard of all Grams) lambda and the fit.
+#include <algorithm>
+
 #include "spt_internal.h"
 
 namespace spt {
@@ -17,79 +19,75 @@ namespace spt {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kGramRowsPerChunk = 4096;
-constexpr int kGramMaxChunks = 512;
-constexpr int kTilesPerWave = 4;
+constexpr int kGramRowsPerWave = 256;
+constexpr int kGramMaxWaves = 4096;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 int gram_nb(int R) { return (R + 15) / 16; }
-int gram_ntiles(int R) { const int nb = gram_nb(R); return nb * (nb + 1) / 2; }
-int gram_chunks(int64_t rows) {
-    int64_t c = (rows + kGramRowsPerChunk - 1) / kGramRowsPerChunk;
-    if (c < 1) c = 1;
-    if (c > kGramMaxChunks) c = kGramMaxChunks;
-    return (int)c;
+// workgroups of the Gram kernel (4 waves, one row slice each)
+int gram_chunks(int64_t rows, int R) {
+    const int ld = gram_nb(R) * 16;
+    int64_t waves = (rows + kGramRowsPerWave - 1) / kGramRowsPerWave;
+    const int64_t cap = std::max<int64_t>(4, (int64_t)(32u << 20) / ((int64_t)ld * ld * 8));  // ~32 MB of partials
+    waves = std::min<int64_t>(std::min<int64_t>(waves, kGramMaxWaves), cap);
+    return (int)std::max<int64_t>(1, (waves + 3) / 4);
 }
 
-// Partial Grams of row chunks.  Tile t (pb <= qb) of R in 16x16 blocks; the
-// wave's lane layout for v_mfma_f64_16x16x4_f64: A[m][k] from lane m + 16k,
-// B[k][n] from lane n + 16k, D[m][n] in lane n + 16*(m%4), element m/4.
+// Partial Grams of row slices, one slice per wave.  A wave owns every
+// 16x16 tile (pb <= qb) of R for its rows, so consecutive MFMAs go to
+// independent accumulators; UNR groups of 4 rows are loaded before use.
+// Lane layout of v_mfma_f64_16x16x4_f64: A[m][k] from lane m + 16k, B[k][n]
+// from lane n + 16k, D[m][n] in lane n + 16*(m%4), element m/4.
+template <int NB, int UNR>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restrict__ C, int64_t rows, int R,
                                                            double *__restrict__ work) {
-    const int nb = (R + 15) / 16;
-    const int ntiles = nb * (nb + 1) / 2;
+    constexpr int NT = NB * (NB + 1) / 2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t_base = blockIdx.y * (4 * kTilesPerWave) + wave;
-    int pb[kTilesPerWave], qb[kTilesPerWave];
-    bool act[kTilesPerWave];
-#pragma unroll
-    for (int i = 0; i < kTilesPerWave; ++i) {
-        int t = t_base + 4 * i;
-        act[i] = t < ntiles;
-        if (!act[i]) t = 0;
-        // decode t -> (p, q) with p <= q, row-major over the upper triangle
-        int p = 0, rem = t;
-        while (rem >= nb - p) {
-            rem -= nb - p;
-            ++p;
-        }
-        pb[i] = p;
-        qb[i] = p + rem;
-    }
-    double4_t acc[kTilesPerWave];
-#pragma unroll
-    for (int i = 0; i < kTilesPerWave; ++i) acc[i] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const int64_t slice = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t nslices = (int64_t)gridDim.x * 4;
+    const int64_t r_per = ((rows + nslices - 1) / nslices + 4 * UNR - 1) / (4 * UNR) * (4 * UNR);
+    const int64_t r0 = slice * r_per;
+    const int64_t r1 = min(r0 + r_per, rows);
     const int kr = lane >> 4, cc = lane & 15;
-    const int64_t r_per = ((rows + gridDim.x - 1) / gridDim.x + 3) & ~3LL;
-    const int64_t r0 = (int64_t)blockIdx.x * r_per;
-    const int64_t r1 = r0 + r_per < rows ? r0 + r_per : rows;
-    for (int64_t i0 = r0; i0 < r1; i0 += 4) {
-        const int64_t row = i0 + kr;
-        const float *rp = C + row * R;
-        const bool rok = row < r1;
+    double4_t acc[NT];
 #pragma unroll
-        for (int i = 0; i < kTilesPerWave; ++i) {
-            if (act[i]) {
-                const int ca = pb[i] * 16 + cc, cb = qb[i] * 16 + cc;
-                const double a = (rok && ca < R) ? (double)rp[ca] : 0.0;
-                const double b = (rok && cb < R) ? (double)rp[cb] : 0.0;
-                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+    for (int i = 0; i < NT; ++i) acc[i] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = r0; i0 < r1; i0 += 4 * UNR) {
+        double v[UNR][NB];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t row = i0 + 4 * u + kr;
+            const bool rok = row < r1;
+            const float *rp = C + row * R;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int c = b * 16 + cc;
+                v[u][b] = (rok && c < R) ? (double)rp[c] : 0.0;
             }
         }
-    }
-    const int ld = nb * 16;
-    double *wb = work + (size_t)blockIdx.x * ld * ld;
 #pragma unroll
-    for (int i = 0; i < kTilesPerWave; ++i) {
-        if (act[i]) {
+        for (int u = 0; u < UNR; ++u) {
+            int t = 0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int m = 4 * v + (lane >> 4), n = lane & 15;
-                wb[(size_t)(pb[i] * 16 + m) * ld + qb[i] * 16 + n] = acc[i][v];
-            }
+            for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+                for (int qb = pb; qb < NB; ++qb, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][pb], v[u][qb], acc[t], 0, 0, 0);
         }
     }
+    const int ld = NB * 16;
+    double *wb = work + (size_t)slice * ld * ld;
+    int t = 0;
+#pragma unroll
+    for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+        for (int qb = pb; qb < NB; ++qb, ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = 4 * e + (lane >> 4), n = lane & 15;
+                wb[(size_t)(pb * 16 + m) * ld + qb * 16 + n] = acc[t][e];
+            }
 }
 
 // G[p][q] = sum over chunks (upper block triangle mirrored), deterministic order.
@@ -346,17 +344,21 @@ __global__ __launch_bounds__(kThreads) void k_fit_direct(const double *__restric
 
 size_t gram_work_bytes(int64_t rows, int rank) {
     const int ld = gram_nb(rank) * 16;
-    return (size_t)gram_chunks(rows) * ld * ld * sizeof(double);
+    return (size_t)gram_chunks(rows, rank) * 4 * ld * ld * sizeof(double);
 }
 
 spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double *work, size_t work_bytes,
                        hipStream_t s) {
-    const int chunks = gram_chunks(rows);
+    if (rank > 64) return fail(SPT_E_INVALID_ARG, "gram: rank above 64");
+    const int chunks = gram_chunks(rows, rank);
     if (gram_work_bytes(rows, rank) > work_bytes) return fail(SPT_E_INVALID_ARG, "gram: workspace too small");
-    const int ty = (gram_ntiles(rank) + 4 * kTilesPerWave - 1) / (4 * kTilesPerWave);
-    hipLaunchKernelGGL(k_gram_partial, dim3(chunks, ty), dim3(kThreads), 0, s, C, rows, rank, work);
+    const int nb = gram_nb(rank);
+    if (nb == 1) hipLaunchKernelGGL((k_gram_partial<1, 4>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
+    else if (nb == 2) hipLaunchKernelGGL((k_gram_partial<2, 4>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
+    else if (nb == 3) hipLaunchKernelGGL((k_gram_partial<3, 2>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
+    else hipLaunchKernelGGL((k_gram_partial<4, 2>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
     int rb = (rank * rank + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(rb), dim3(kThreads), 0, s, work, chunks, rank, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(rb), dim3(kThreads), 0, s, work, chunks * 4, rank, G);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

@@ -418,13 +418,43 @@ spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s) {
     return SPT_OK;
 }
 
-spt_status sort_u64_keys(uint64_t **keys_io, int64_t n, int nbits, uint32_t **idx_out, hipStream_t s) {
-    if (n <= 0) {
-        *idx_out = nullptr;
-        return SPT_OK;
+size_t sort_ws_counts(int64_t n) { return 256 * (size_t)((n + kThreads * 16 - 1) / (kThreads * 16)) + 256; }
+
+// Stable LSD radix sort of n keys over their low nbits bits in caller-owned
+// buffers: keys and keys2 (n each) ping-pong, idx_a / idx_b (n each) receive
+// the input index of every sorted key, counts holds sort_ws_counts(n) words.
+// *sorted_out / *idx_out point at the buffers holding the result.
+spt_status sort_u64_keys_ws(uint64_t *keys, uint64_t *keys2, uint32_t *idx_a, uint32_t *idx_b, uint32_t *counts,
+                            int64_t n, int nbits, uint64_t **sorted_out, uint32_t **idx_out, hipStream_t s) {
+    constexpr int ITEMS = 16;
+    constexpr int TILE = kThreads * ITEMS;
+    *sorted_out = keys;
+    *idx_out = idx_a;
+    if (n <= 0) return SPT_OK;
+    const int nblocks = (int)((n + TILE - 1) / TILE);
+    const int passes = (nbits + 7) / 8;
+    uint32_t *totals = counts + 256 * (size_t)nblocks;
+    uint64_t *src = keys, *dst = keys2;
+    uint32_t *src_idx = nullptr, *dst_idx = idx_a;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3(nblocks), dim3(kThreads), 0, s, src, n, shift, counts, nblocks);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, counts, nblocks, totals);
+        hipLaunchKernelGGL((k_radix_scatter<1, ITEMS>), dim3(nblocks), dim3(kThreads), 0, s, src, (const uint64_t *)nullptr,
+                           src_idx, dst, (uint64_t *)nullptr, dst_idx, n, 0, shift, counts, totals, nblocks);
+        SPT_HIP(hipGetLastError());
+        std::swap(src, dst);
+        src_idx = dst_idx;
+        dst_idx = (dst_idx == idx_a) ? idx_b : idx_a;
     }
-    uint64_t *hi = nullptr;
-    return radix_sort<1, 16>(n, nbits, keys_io, &hi, idx_out, s);
+    if (src_idx == nullptr) {
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(n, kThreads, 65536)), dim3(kThreads), 0, s, idx_a, n);
+        SPT_HIP(hipGetLastError());
+        src_idx = idx_a;
+    }
+    *sorted_out = src;
+    *idx_out = src_idx;
+    return SPT_OK;
 }
 
 spt_status launch_sum_f64(const double *parts, int n, double *out, hipStream_t s) {

@@ -384,15 +384,16 @@ __global__ __launch_bounds__(256) void k_reduce_priv(const float *__restrict__ p
     }
 }
 
-// Records sorted by row: lane groups sum runs of equal row; a run wholly
-// inside the group's chunk is stored, a run crossing a chunk edge is added
-// atomically (out was zeroed).
+// Records sorted by row: lane groups sum runs of equal row over a chunk of
+// records (8 record loads in flight per lane); a run wholly inside the chunk
+// is stored, a run crossing a chunk edge is added atomically (out was zeroed).
 template <int G, int VEC, int NB>
 __global__ __launch_bounds__(256) void k_reduce_records(const uint64_t *__restrict__ srow,
                                                         const uint32_t *__restrict__ sidx,
                                                         const float *__restrict__ rec_val, int64_t P, int R,
                                                         int chunk, int64_t rows, float *__restrict__ out) {
     constexpr int GROUPS = 256 / G;
+    constexpr int UB = 8;
     const int g = threadIdx.x / G, j = threadIdx.x % G;
     const int64_t c0 = ((int64_t)blockIdx.x * GROUPS + g) * chunk;
     if (c0 >= P) return;
@@ -421,26 +422,42 @@ __global__ __launch_bounds__(256) void k_reduce_records(const uint64_t *__restri
             }
         }
     };
-    for (int64_t q = c0; q < c1; ++q) {
-        const uint64_t r = srow[q];
-        if (r != cur) {
-            emit(cur, starts_here);
-            cur = r;
-            starts_here = true;
+    for (int64_t q = c0; q < c1; q += UB) {
+        uint64_t r[UB];
+        float x[UB][NB][VEC];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+        for (int u = 0; u < UB; ++u) {
+            const bool ok = q + u < c1;
+            r[u] = ok ? srow[q + u] : ~0ull;
+            const float *src = rec_val + (int64_t)(ok ? sidx[q + u] : 0) * R;
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[b][v] = 0.f;
+            for (int b = 0; b < NB; ++b) {
+                const int c = (b * G + j) * VEC;
+                if (ok && c < R) {
+                    load_vec<VEC>(src + c, x[u][b]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) x[u][b][v] = 0.f;
+                }
+            }
         }
-        const float *src = rec_val + (int64_t)sidx[q] * R;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int c = (b * G + j) * VEC;
-            if (c < R) {
-                float x[VEC];
-                load_vec<VEC>(src + c, x);
+        for (int u = 0; u < UB; ++u) {
+            if (q + u < c1) {
+                if (r[u] != cur) {
+                    emit(cur, starts_here);
+                    cur = r[u];
+                    starts_here = true;
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[b][v] += x[v];
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) acc[b][v] = x[u][b][v];
+                } else {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) acc[b][v] += x[u][b][v];
+                }
             }
         }
     }
@@ -515,7 +532,7 @@ spt_status launch_reduce_priv(const float *part, int nwg, int64_t rows, int R, f
 spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, const float *rec_val, int64_t P, int R,
                                  int64_t rows, float *out, hipStream_t s) {
     if (P <= 0) return SPT_OK;
-    constexpr int chunk = 16;
+    constexpr int chunk = 64;
     auto go = [&](auto kern, int G) -> spt_status {
         const int groups = 256 / G;
         const int64_t blocks = (P + (int64_t)groups * chunk - 1) / ((int64_t)groups * chunk);

@@ -77,6 +77,33 @@ int device_cus() {
     return cus[dev];
 }
 
+void *tensor_ws(Tensor *t, int slot, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    if (t->ws_bytes[slot] >= bytes) return t->ws[slot];
+    if (t->ws[slot]) {
+        (void)hipStreamSynchronize(s);  // earlier work on this stream may still use the old buffer
+        (void)hipFree(t->ws[slot]);
+        t->ws[slot] = nullptr;
+        t->ws_bytes[slot] = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    t->ws[slot] = p;
+    t->ws_bytes[slot] = bytes;
+    return p;
+}
+
+void release_ws(Tensor *t) {
+    for (int i = 0; i < WS_NSLOTS; ++i) {
+        if (t->ws[i]) (void)hipFree(t->ws[i]);
+        t->ws[i] = nullptr;
+        t->ws_bytes[i] = 0;
+    }
+}
+
 void release_plans(Tensor *t) {
     for (int n = 0; n < kMaxModes; ++n) {
         if (t->mplan[n].rec_off) (void)hipFree(t->mplan[n].rec_off);
@@ -199,34 +226,116 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
     return SPT_OK;
 }
 
+// ---------------------------------------------------------------- instrumentation
+// When enabled, every MTTKRP call (all of its kernels) is bracketed by two HIP
+// events on the call's stream; spt_profile_read sums their elapsed times.
+namespace {
+struct ProfEvent {
+    int mode;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfEvent> g_prof;
+
+void prof_clear_locked() {
+    for (auto &e : g_prof) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    g_prof.clear();
+}
+}  // namespace
+
+spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    if (!on) return run_mttkrp_impl(t, factors, rank, mode, out, s);
+    ModePlan *p = nullptr;
+    spt_status st = resolve_plan(t, mode, rank, s, &p);  // plan building stays outside the timed range
+    if (st != SPT_OK) return st;
+    ProfEvent e{mode, nullptr, nullptr};
+    SPT_HIP(hipEventCreate(&e.a));
+    SPT_HIP(hipEventCreate(&e.b));
+    SPT_HIP(hipEventRecord(e.a, s));
+    st = run_mttkrp_impl(t, factors, rank, mode, out, s);
+    SPT_HIP(hipEventRecord(e.b, s));
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(e);
+    return st;
+}
+
+spt_status profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on = on != 0;
+    return SPT_OK;
+}
+
+spt_status profile_read(double *ms, int64_t *launches) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int n = 0; n < kMaxModes; ++n) {
+        ms[n] = 0.0;
+        launches[n] = 0;
+    }
+    for (auto &e : g_prof) {
+        SPT_HIP(hipEventSynchronize(e.b));
+        float v = 0.f;
+        SPT_HIP(hipEventElapsedTime(&v, e.a, e.b));
+        ms[e.mode] += v;
+        launches[e.mode] += 1;
+    }
+    return SPT_OK;
+}
+
+// Records path shared by SEGMENT and TABLE: the main kernel writes P
+// records, which are radix-sorted by row (rows + 1 bits, so the sentinel of
+// unused slots sorts last) and summed per row into out.
+spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int64_t rows, float *out, hipStream_t s,
+                              bool segment, TableArgs *ta = nullptr, int nwg = 0) {
+    const size_t n1 = (size_t)std::max<int64_t>(P, 1);
+    uint64_t *rrow = (uint64_t *)tensor_ws(t, WS_REC_ROW, sizeof(uint64_t) * n1, s);
+    float *rval = (float *)tensor_ws(t, WS_REC_VAL, sizeof(float) * n1 * rank, s);
+    uint64_t *keys2 = (uint64_t *)tensor_ws(t, WS_KEYS2, sizeof(uint64_t) * n1, s);
+    uint32_t *ia = (uint32_t *)tensor_ws(t, WS_IDX_A, sizeof(uint32_t) * n1, s);
+    uint32_t *ib = (uint32_t *)tensor_ws(t, WS_IDX_B, sizeof(uint32_t) * n1, s);
+    uint32_t *cnt = (uint32_t *)tensor_ws(t, WS_COUNTS, sizeof(uint32_t) * sort_ws_counts((int64_t)n1), s);
+    if (!rrow || !rval || !keys2 || !ia || !ib || !cnt) return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
+    const int mode = a.mode;
+    spt_status st;
+    if (segment) {
+        a.rec_row = rrow;
+        a.rec_val = rval;
+        st = launch_mttkrp_seg(a, s);
+    } else {
+        ta->rec_row = rrow;
+        ta->rec_val = rval;
+        st = launch_table(*ta, nwg, s);
+    }
+    uint64_t *srow = nullptr;
+    uint32_t *sidx = nullptr;
+    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, keys2, ia, ib, cnt, P, t->lbits[mode] + 1, &srow, &sidx, s);
+    if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
+    if (st == SPT_OK) st = launch_reduce_records(srow, sidx, rval, P, rank, rows, out, s);
+    return st;
+}
+
+spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
     ModePlan *p = nullptr;
     spt_status st = resolve_plan(t, mode, rank, s, &p);
     if (st != SPT_OK) return st;
     const int64_t rows = t->dims[mode];
     if (p->strategy == SPT_STRATEGY_SEGMENT && t->nnz > 0) {
         const int64_t P = p->records;
-        uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * std::max<int64_t>(P, 1), s);
-        float *rval = (float *)dev_alloc(sizeof(float) * std::max<int64_t>(P, 1) * rank, s);
-        if (!rrow || !rval) {
-            dev_free(rrow, s);
-            dev_free(rval, s);
-            return fail(SPT_E_OOM, "mttkrp: record allocation failed");
-        }
         MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
-        a.rec_row = rrow;
-        a.rec_val = rval;
         a.rec_off = p->rec_off;
         a.rec_sentinel = (uint64_t)1 << t->lbits[mode];
-        st = launch_mttkrp_seg(a, s);
-        uint32_t *idx = nullptr;
-        if (st == SPT_OK) st = sort_u64_keys(&rrow, P, t->lbits[mode] + 1, &idx, s);
-        if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
-        if (st == SPT_OK) st = launch_reduce_records(rrow, idx, rval, P, rank, rows, out, s);
-        dev_free(rrow, s);
-        dev_free(rval, s);
-        dev_free(idx, s);
-        return st;
+        return reduce_via_records(t, a, P, rank, rows, out, s, /*segment=*/true);
     }
     if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
         st = launch_fill_zero(out, rows * (int64_t)rank, s);
@@ -242,35 +351,18 @@ spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode
     ta.ts = p->ts;
     ta.sub_per_wg = p->sub_per_wg;
     if (p->strategy == SPT_STRATEGY_PRIV) {
-        float *part = (float *)dev_alloc(sizeof(float) * (size_t)p->nwg * rows * rank, s);
+        float *part = (float *)tensor_ws(t, WS_PART, sizeof(float) * (size_t)p->nwg * rows * rank, s);
         if (!part) return fail(SPT_E_OOM, "mttkrp: partials allocation failed");
         ta.rec_val = part;
         st = launch_priv(ta, p->nwg, p->npass, s);
         if (st == SPT_OK) st = launch_reduce_priv(part, p->nwg, rows, rank, out, s);
-        dev_free(part, s);
         return st;
     }
     // TABLE
-    const int64_t P = p->records;
-    uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * std::max<int64_t>(P, 1), s);
-    float *rval = (float *)dev_alloc(sizeof(float) * std::max<int64_t>(P, 1) * rank, s);
-    if (!rrow || !rval) {
-        dev_free(rrow, s);
-        dev_free(rval, s);
-        return fail(SPT_E_OOM, "mttkrp: record allocation failed");
-    }
-    ta.rec_row = rrow;
-    ta.rec_val = rval;
     ta.rec_off = p->rec_off;
-    st = launch_table(ta, p->nwg, s);
-    uint32_t *idx = nullptr;
-    if (st == SPT_OK) st = sort_u64_keys(&rrow, P, t->lbits[mode], &idx, s);
-    if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
-    if (st == SPT_OK) st = launch_reduce_records(rrow, idx, rval, P, rank, rows, out, s);
-    dev_free(rrow, s);
-    dev_free(rval, s);
-    dev_free(idx, s);
-    return st;
+    MttkrpArgs a = ta.a;
+    a.rec_off = p->rec_off;
+    return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/false, &ta, p->nwg);
 }
 
 }  // namespace spt

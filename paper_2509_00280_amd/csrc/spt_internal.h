@@ -63,6 +63,10 @@ struct ModePlan {
     int64_t *rec_off = nullptr;  // TABLE: device, nwg offsets
 };
 
+// Grow-only device buffers owned by a tensor handle and reused by its MTTKRP
+// calls (records and sort buffers), so steady-state calls allocate nothing.
+enum WsSlot { WS_REC_ROW, WS_REC_VAL, WS_KEYS2, WS_IDX_A, WS_IDX_B, WS_COUNTS, WS_PART, WS_NSLOTS };
+
 struct Tensor {
     int nmodes = 0;
     int64_t nnz = 0;
@@ -79,6 +83,8 @@ struct Tensor {
     double norm_x2 = 0.0;
     spt_plan plan{};
     ModePlan mplan[kMaxModes];
+    void *ws[WS_NSLOTS] = {};
+    size_t ws_bytes[WS_NSLOTS] = {};
 };
 
 // plan.cpp
@@ -87,17 +93,22 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
 void release_plans(Tensor *t);
+// workspace slot of at least `bytes` (synchronises s before replacing a smaller buffer)
+void *tensor_ws(Tensor *t, int slot, size_t bytes, hipStream_t s);
+void release_ws(Tensor *t);
+spt_status profile_enable(int on);
+spt_status profile_read(double *ms, int64_t *launches);
 
 // ---------------------------------------------------------------- kernels (launchers)
 // encode.hip
 spt_status launch_encode(Tensor *t, const uint32_t *coords, const float *vals, hipStream_t s);
 spt_status launch_decode(const Tensor *t, uint32_t *coords, hipStream_t s);
 spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s);
-// Stable LSD radix sort of n 64-bit keys over their low nbits bits.  *keys_io is
-// replaced by the sorted keys (the input buffer may be released); *idx_out
-// receives a new buffer with the input index of every sorted key.  Buffers come
-// from dev_alloc on stream s.
-spt_status sort_u64_keys(uint64_t **keys_io, int64_t n, int nbits, uint32_t **idx_out, hipStream_t s);
+// Stable LSD radix sort of n 64-bit keys over their low nbits bits in
+// caller-owned buffers (see encode.hip).
+size_t sort_ws_counts(int64_t n);
+spt_status sort_u64_keys_ws(uint64_t *keys, uint64_t *keys2, uint32_t *idx_a, uint32_t *idx_b, uint32_t *counts,
+                            int64_t n, int nbits, uint64_t **sorted_out, uint32_t **idx_out, hipStream_t s);
 
 // mttkrp.hip
 struct MttkrpArgs {

@@ -96,6 +96,8 @@ def lib():
     _sig(L, "spt_server_wait", st, [_VP, ctypes.c_uint64, d, ctypes.POINTER(Result), _PP, _VP])
     _sig(L, "spt_server_now", d, [_VP])
     _sig(L, "spt_server_destroy", None, [_VP])
+    _sig(L, "spt_profile_enable", st, [i])
+    _sig(L, "spt_profile_read", st, [ctypes.POINTER(d), ctypes.POINTER(i64)])
     _LIB = L
     return L
 
@@ -272,6 +274,19 @@ def autotune(t: Tensor, factors, budget_ms: float = 2000.0, stream=None):
                               _stream(stream)))
     t._h = h
     return best.value
+
+
+def profile_reset(on: bool = True):
+    """Clear recorded MTTKRP timings and (re)enable event timing."""
+    _check(lib().spt_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """Per-mode summed MTTKRP GPU time (ms) and launch counts since the last reset."""
+    ms = (ctypes.c_double * MAX_MODES)()
+    n = (ctypes.c_int64 * MAX_MODES)()
+    _check(lib().spt_profile_read(ms, n))
+    return {"mttkrp_ms": list(ms), "mttkrp_launches": list(n)}
 
 
 def version() -> str:
