@@ -34,9 +34,12 @@ def log(msg):
 
 
 def source_digest() -> str:
+    """Digest of the sources of every kernel one MTTKRP call runs (main kernel,
+    record sort, record reduction, plan); stored HBM counters are valid only for it."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2509_00280_amd", "csrc", "mttkrp.hip"), "rb") as f:
-        h.update(f.read())
+    for f in ("mttkrp_seg.hip", "mttkrp_table.hip", "encode.hip", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_2509_00280_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -58,7 +61,7 @@ def algorithmic_bytes(t, rank: int, mode: int) -> int:
 def cpu_baseline(t, factors, budget_s: float = 20.0):
     """The FP64 oracle MTTKRP (single thread, as it stands) on a bounded sample."""
     import oracle
-    n = min(t.nnz, 40_000_000)
+    n = min(t.nnz, 100_000_000)
     sample = slice(0, n)
     c = np.ascontiguousarray(t.coords[:, sample])
     v = np.ascontiguousarray(t.vals[sample])
@@ -77,6 +80,102 @@ def cpu_baseline(t, factors, budget_s: float = 20.0):
                       f"{el:.1f} s on 1 thread of {os.cpu_count()} host cores"}
 
 
+PROFILE_CMDS = {
+    "kt": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/kt -o kt -- "
+          "python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "cf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/cf -o cf -- python -u bench.py --copy-calibration",
+    "cw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/cw -o cw -- python -u bench.py --copy-calibration",
+    "bf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/bf -o bf -- "
+          "python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+    "bw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/bw -o bw -- "
+          "python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+}
+CALL_FIRST = ("k_mttkrp_seg", "k_mttkrp_table", "k_mttkrp<")
+CALL_LAST = ("k_reduce_records", "k_reduce_priv")
+
+
+def _kname(full: str) -> str:
+    import re
+    m = re.search(r"(k_\w+(?:<[^()]*>)?)\(", full)
+    return m.group(1) if m else full.split("(")[0][-60:]
+
+
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _call_windows(rows, key):
+    """Group dispatches (sorted by id) into MTTKRP calls: from a main MTTKRP kernel
+    through the next record/partial reduction.  Returns per-call sums of key(row)."""
+    rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+    calls, cur = [], None
+    for r in rows:
+        n = _kname(r["Kernel_Name"])
+        if n.startswith(CALL_FIRST):
+            cur = [0.0, []]
+        if cur is not None:
+            cur[0] += key(r)
+            cur[1].append(n)
+            if n.startswith(CALL_LAST):
+                calls.append(cur)
+                cur = None
+    return calls
+
+
+def summarize_profiles(d: str):
+    """Write the committed summaries from rocprofv3 CSV output under d."""
+    lines = ["# Kernel trace of the ratings benchmark (480000 x 18000 x 2000, 100M nonzeros, rank 32)",
+             f"# command: cd /tmp && export TMPDIR=/tmp; cd <repo>; {PROFILE_CMDS['kt']}",
+             "# columns: calls, average us, total ms, percent of GPU time, kernel", ""]
+    st = _read_csv(os.path.join(d, "kt", "kt_kernel_stats.csv"))
+    for r in sorted(st, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} {float(r['TotalDurationNs']) / 1e6:9.2f} "
+                     f"{float(r['Percentage']):6.2f}  {_kname(r['Name'])}")
+    tr = _read_csv(os.path.join(d, "kt", "kt_kernel_trace.csv"))
+    calls = _call_windows(tr, lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    main = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
+            if _kname(r["Kernel_Name"]).startswith(CALL_FIRST)]
+    if calls:
+        lines += ["", f"MTTKRP calls: {len(calls)}; kernel time per call (all kernels of the call) "
+                      f"avg {sum(c[0] for c in calls) / len(calls):.1f} us; main kernel avg {sum(main) / len(main):.1f} us",
+                  "kernels of one call: " + " ".join(calls[-1][1])]
+    with open(os.path.join(ROOT, "profiles", "mttkrp_ratings_kernels.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def copy_factor(sub):
+        rows = [r for r in _read_csv(os.path.join(d, sub, sub + "_counter_collection.csv"))
+                if "copyBuffer" in r["Kernel_Name"] or "elementwise" in r["Kernel_Name"].lower()]
+        big = [float(r["Counter_Value"]) for r in rows if float(r["Counter_Value"]) > 1e5]
+        kib = sum(big) / len(big)
+        return (1 << 30) / (kib * 1024.0), kib
+
+    ff, fk = copy_factor("cf")
+    wf, wk = copy_factor("cw")
+    cf_ = _call_windows(_read_csv(os.path.join(d, "bf", "bf_counter_collection.csv")), lambda r: float(r["Counter_Value"]))
+    cw_ = _call_windows(_read_csv(os.path.join(d, "bw", "bw_counter_collection.csv")), lambda r: float(r["Counter_Value"]))
+    fetch = sum(c[0] for c in cf_) / len(cf_) * 1024 * ff
+    write = sum(c[0] for c in cw_) / len(cw_) * 1024 * wf
+    from paper_2509_00280_amd import synth
+    nnz = synth._CONFIGS["ratings"][2]
+    out = ["# HBM traffic of one mode-n MTTKRP call (all of its kernels) in the ratings benchmark",
+           f"# commands (each its own run): cd /tmp && export TMPDIR=/tmp; cd <repo>;",
+           f"#   {PROFILE_CMDS['cf']}", f"#   {PROFILE_CMDS['cw']}", f"#   {PROFILE_CMDS['bf']}", f"#   {PROFILE_CMDS['bw']}",
+           f"# calibration: a 1 GiB device copy reads FETCH_SIZE {fk:.0f} KiB and WRITE_SIZE {wk:.0f} KiB per dispatch,",
+           f"# so FETCH_SIZE KiB x {ff:.3f} and WRITE_SIZE KiB x {wf:.3f} give bytes",
+           f"# calls averaged: {len(cf_)} (FETCH run), {len(cw_)} (WRITE run)",
+           f"source_digest: {source_digest()}",
+           f"nnz: {nnz}",
+           f"fetch_bytes_per_launch: {fetch:.0f}",
+           f"write_bytes_per_launch: {write:.0f}",
+           f"hbm_bytes_per_launch: {fetch + write:.0f}",
+           f"hbm_bytes_per_nnz: {(fetch + write) / nnz:.2f}"]
+    with open(PMC_FILE, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(lines + [""] + out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,9 +183,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nnz", type=float, default=None, help="scale the tensor down (debug only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write the profiles/ summaries from rocprofv3 CSV output under DIR (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -162,7 +266,8 @@ def main():
             traffic = float(pmc["hbm_bytes_per_launch"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "mttkrp", "algorithmic_bytes_per_launch": int(alg_avg),
+                "kernel": "one mode-n MTTKRP call (k_mttkrp_seg, record radix sort, k_reduce_records)",
+                "algorithmic_bytes_per_launch": int(alg_avg),
                 "avg_launch_ms": round(mk_ms, 4)}
     out = {
         "metric": "MTTKRP Gnnz/s per mode", "value": round(value, 3), "unit": "Gnnz/s",

@@ -80,12 +80,15 @@ typedef struct {
                                    workgroup partials are summed (small modes) */
 #define SPT_STRATEGY_AUTO 4     /* PRIV for outputs that fit LDS in one pass with at most 256 rows,
                                    else SEGMENT */
-#define SPT_STRATEGY_SEGMENT 5  /* regroup each tile by output row in LDS; every segment sum becomes a
-                                   record written with plain stores; records are radix-sorted by row
-                                   and summed (no atomics except for rows split between two reducer
-                                   chunks) */
+#define SPT_STRATEGY_SEGMENT 5  /* regroup each tile by output row in LDS; every run of at most 32
+                                   nonzeros of one row becomes a record written with plain stores;
+                                   records are radix-sorted by row and summed (no atomics except for
+                                   rows split between two reducer chunks) */
 typedef struct {
-    int tile[SPT_MAX_MODES];      /* DIRECT/REGROUP: nonzeros per workgroup tile: 256, 512 or 1024 */
+    int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256..1024 for DIRECT/REGROUP (larger
+                                     values act as 1024), 1024/2048/4096 for SEGMENT (smaller values,
+                                     and 4096 when it does not fit LDS for this mode count, act as
+                                     2048); default 2048 */
     int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
 } spt_plan;
 

@@ -103,7 +103,7 @@ static int bit_length(int64_t d) {  // ceil(log2 d) for d >= 1
 
 static void default_plan(const Tensor *t, spt_plan *p) {
     for (int n = 0; n < kMaxModes; ++n) {
-        p->tile[n] = 1024;
+        p->tile[n] = 2048;
         p->strategy[n] = SPT_STRATEGY_AUTO;
     }
     (void)t;
@@ -112,7 +112,7 @@ static void default_plan(const Tensor *t, spt_plan *p) {
 static bool plan_ok(const spt_plan *p, int nmodes) {
     for (int n = 0; n < nmodes; ++n) {
         const int T = p->tile[n];
-        if (T != 256 && T != 512 && T != 1024) return false;
+        if (T != 256 && T != 512 && T != 1024 && T != 2048 && T != 4096) return false;
         if (p->strategy[n] < SPT_STRATEGY_DIRECT || p->strategy[n] > SPT_STRATEGY_SEGMENT) return false;
     }
     return true;
@@ -279,7 +279,7 @@ spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
 
 spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
     if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
-    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256/512/1024 and strategy 0..5");
+    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256..4096 (power of two) and strategy 0..5");
     (void)hipDeviceSynchronize();  // resolved plans (record offsets) may still be in use
     release_plans(t);
     t->plan = *plan;

@@ -204,41 +204,9 @@ __device__ __forceinline__ void flush_row(float *__restrict__ out, uint32_t row,
     }
 }
 
-// Record sink of the SEGMENT strategy: each finished run (a segment of equal
-// output row, or the piece of one cut by a chunk edge) becomes one record
-// (row, R floats) written with plain stores into the tile's record range.
-struct RecSink {
-    int64_t base;   // first record of this tile
-    int *count;     // LDS counter of records written by the tile
-};
-
-template <int G, int VEC, int NB>
-__device__ __forceinline__ void emit_record(const MttkrpArgs &a, const RecSink &rs, uint32_t row, int R, int j,
-                                            const Acc<G, VEC, NB> &acc) {
-    const int lane = threadIdx.x & 63;
-    int idx = 0;
-    if (j == 0) idx = atomicAdd(rs.count, 1);
-    idx = __shfl(idx, lane - j, 64);
-    const int64_t pos = rs.base + idx;
-    if (j == 0) a.rec_row[pos] = (uint64_t)row;
-    float *o = a.rec_val + pos * R;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int col = (b * G + j) * VEC;
-        if (col < R) {
-            if constexpr (VEC == 4) {
-                *reinterpret_cast<float4 *>(o + col) = make_float4(acc.v[b][0], acc.v[b][1], acc.v[b][2], acc.v[b][3]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) o[col + q] = acc.v[b][q];
-            }
-        }
-    }
-}
-
 // Walk the staged tile and accumulate into out (see the file comment).
-template <int G, int VEC, int NB, int NMAX, bool REGROUP, bool REC = false>
-__device__ __forceinline__ void walk_tile(const MttkrpArgs &a, const TileLds &L, int cnt, RecSink rs = RecSink{0, nullptr}) {
+template <int G, int VEC, int NB, int NMAX, bool REGROUP>
+__device__ __forceinline__ void walk_tile(const MttkrpArgs &a, const TileLds &L, int cnt) {
     constexpr int GROUPS = kThreads / G;
     const int T = a.tile;
     const int tid = threadIdx.x;
@@ -299,10 +267,7 @@ __device__ __forceinline__ void walk_tile(const MttkrpArgs &a, const TileLds &L,
         for (int u = 0; u < kUnroll; ++u) {
             if (ok[u]) {
                 if (row[u] != cur) {
-                    if (cur != kNoRow) {
-                        if (REC) emit_record<G, VEC, NB>(a, rs, cur, R, j, acc);
-                        else flush_row<G, VEC, NB>(a.out, cur, R, j, acc);
-                    }
+                    if (cur != kNoRow) flush_row<G, VEC, NB>(a.out, cur, R, j, acc);
                     cur = row[u];
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
@@ -317,50 +282,7 @@ __device__ __forceinline__ void walk_tile(const MttkrpArgs &a, const TileLds &L,
             }
         }
     }
-    if (cur != kNoRow) {
-        if (REC) emit_record<G, VEC, NB>(a, rs, cur, R, j, acc);
-        else flush_row<G, VEC, NB>(a.out, cur, R, j, acc);
-    }
-}
-
-// SEGMENT: regrouped tiles whose segment sums become records.  The tile's
-// record range holds (distinct rows + groups - 1) slots, an upper bound on
-// the pieces a walk can produce; unused slots get the sentinel row, which the
-// reducer skips.
-template <int G, int VEC, int NB, int NMAX>
-__global__ __launch_bounds__(kThreads) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles) {
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[4];
-    __shared__ int s_nrec;
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const TileLds L = carve(lds, a.tile, NMAX);
-    const CodecRegs cr = load_codec_regs(a.codec);
-    if (threadIdx.x == 0) s_nrec = 0;
-    const int cnt = stage_tile<NMAX, true>(a, tile, L, a.mode, wsum, cr);
-    const int64_t base = a.rec_off[tile];
-    walk_tile<G, VEC, NB, NMAX, true, true>(a, L, cnt, RecSink{base, &s_nrec});
-    __syncthreads();
-    const int64_t capn = a.rec_off[tile + 1] - base;
-    for (int64_t i = s_nrec + threadIdx.x; i < capn; i += kThreads) a.rec_row[base + i] = a.rec_sentinel;
-}
-
-// Distinct output rows of every tile (the SEGMENT plan's counting pass).
-template <int NMAX>
-__global__ __launch_bounds__(kThreads) void k_count_distinct(MttkrpArgs a, int64_t ntiles, int64_t *__restrict__ out) {
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[4];
-    __shared__ int s_cnt;
-    const int64_t tile = blockIdx.x;
-    const TileLds L = carve(lds, a.tile, NMAX);
-    const CodecRegs cr = load_codec_regs(a.codec);
-    if (threadIdx.x == 0) s_cnt = 0;
-    stage_tile<NMAX, true>(a, tile, L, a.mode, wsum, cr);
-    int c = 0;
-    for (int i = threadIdx.x; i < 2 * a.tile; i += kThreads) c += L.hkey[i] != kNoRow;
-    atomicAdd(&s_cnt, c);
-    __syncthreads();
-    if (threadIdx.x == 0) out[tile] = s_cnt;
+    if (cur != kNoRow) flush_row<G, VEC, NB>(a.out, cur, R, j, acc);
 }
 
 template <int G, int VEC, int NB, int NMAX, bool REGROUP>
@@ -528,33 +450,6 @@ spt_status launch_walk(const MttkrpArgs &a, bool regroup, int64_t ntiles, hipStr
     return SPT_OK;
 }
 
-template <int G, int VEC, int NB, int NMAX>
-spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
-    const size_t lds = tile_lds_bytes(a.tile, NMAX, true);
-    hipLaunchKernelGGL((k_mttkrp_seg<G, VEC, NB, NMAX>), dim3((unsigned)ntiles), dim3(kThreads), lds, s, a, ntiles);
-    SPT_HIP(hipGetLastError());
-    return SPT_OK;
-}
-
-template <int NMAX>
-spt_status launch_seg_nmax(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
-    const int R = a.rank;
-    if ((R & 3) == 0) {
-        const int r4 = R >> 2;
-        if (r4 <= 1) return launch_seg_k<1, 4, 1, NMAX>(a, ntiles, s);
-        if (r4 <= 2) return launch_seg_k<2, 4, 1, NMAX>(a, ntiles, s);
-        if (r4 <= 4) return launch_seg_k<4, 4, 1, NMAX>(a, ntiles, s);
-        if (r4 <= 8) return launch_seg_k<8, 4, 1, NMAX>(a, ntiles, s);
-        if (r4 <= 16) return launch_seg_k<16, 4, 1, NMAX>(a, ntiles, s);
-        if (r4 <= 32) return launch_seg_k<32, 4, 1, NMAX>(a, ntiles, s);
-        return launch_seg_k<64, 4, 1, NMAX>(a, ntiles, s);
-    }
-    if (R <= 64) return launch_seg_k<64, 1, 1, NMAX>(a, ntiles, s);
-    if (R <= 128) return launch_seg_k<64, 1, 2, NMAX>(a, ntiles, s);
-    if (R <= 192) return launch_seg_k<64, 1, 3, NMAX>(a, ntiles, s);
-    return launch_seg_k<64, 1, 4, NMAX>(a, ntiles, s);
-}
-
 template <int NMAX>
 spt_status launch_nmax(const MttkrpArgs &a, bool regroup, int64_t ntiles, hipStream_t s) {
     const int R = a.rank;
@@ -613,37 +508,6 @@ spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s) {
     const bool regroup = strategy == SPT_STRATEGY_REGROUP;
     if (a.nmodes <= 4) return launch_nmax<4>(a, regroup, ntiles, s);
     return launch_nmax<8>(a, regroup, ntiles, s);
-}
-
-int seg_groups(int rank) {
-    int g;
-    if ((rank & 3) == 0) {
-        const int r4 = rank >> 2;
-        g = r4 <= 1 ? 1 : r4 <= 2 ? 2 : r4 <= 4 ? 4 : r4 <= 8 ? 8 : r4 <= 16 ? 16 : r4 <= 32 ? 32 : 64;
-    } else {
-        g = 64;
-    }
-    return kThreads / g;
-}
-
-spt_status launch_count_distinct(const MttkrpArgs &a, int64_t *counts, hipStream_t s) {
-    const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
-    if (ntiles == 0) return SPT_OK;
-    if (a.nmodes <= 4)
-        hipLaunchKernelGGL(k_count_distinct<4>, dim3((unsigned)ntiles), dim3(kThreads), tile_lds_bytes(a.tile, 4, true), s, a,
-                           ntiles, counts);
-    else
-        hipLaunchKernelGGL(k_count_distinct<8>, dim3((unsigned)ntiles), dim3(kThreads), tile_lds_bytes(a.tile, 8, true), s, a,
-                           ntiles, counts);
-    SPT_HIP(hipGetLastError());
-    return SPT_OK;
-}
-
-spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
-    const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
-    if (ntiles == 0) return SPT_OK;
-    if (a.nmodes <= 4) return launch_seg_nmax<4>(a, ntiles, s);
-    return launch_seg_nmax<8>(a, ntiles, s);
 }
 
 spt_status launch_mttkrp_batched(const BatchItem *items_dev, int count, int64_t total_tiles, int nmodes_max,

@@ -1,0 +1,359 @@
+// SEGMENT strategy of mode-n MTTKRP (Section II-B, Fig. 2) on gfx950.
+//
+// A workgroup of NT threads owns a tile of T = 4 NT consecutive nonzeros of
+// the key-ordered stream.
+//  1. Stage: coalesced non-temporal loads of keys and values; every thread
+//     decodes the coordinates of its four nonzeros into registers from the bit
+//     runs held in VGPRs.
+//  2. Regroup by output row: LDS hash (T slots, linear probing, CAS) of the
+//     mode-n coordinate; an LDS counter per slot gives each nonzero its rank
+//     (kept in registers with the slot).  One block scan of packed
+//     (nonzeros << 16 | pieces) per slot yields the position of every nonzero
+//     in row-grouped order and the first piece of every slot, where a row with
+//     c nonzeros in the tile is cut into ceil(c / L) pieces of at most L.
+//     The nonzeros' values and non-output coordinates are scattered straight
+//     into row-grouped order; a piece table maps piece -> slot.
+//  3. Walk: lane groups (G lanes x VEC columns) take pieces round-robin (every
+//     piece is at most L nonzeros, so the static deal is balanced), gather the
+//     N-1 factor rows of the piece's nonzeros with vector loads (UB nonzeros in
+//     flight), form v * Hadamard, sum the piece in registers (a segmented
+//     reduction over equal output index) and write one record (row, R floats)
+//     with plain stores at the tile's record base plus the piece index.  The
+//     number of pieces depends only on the tile's multiset of rows, so a
+//     counting pass fixes every tile's record range: no atomics, no padding.
+//  4. Records are radix-sorted by row and summed per row (mttkrp_table.hip).
+#include "tile_common.h"
+
+#ifndef SPT_SEG_UB
+#define SPT_SEG_UB 4
+#endif
+#ifndef SPT_SEG_PIECE
+#define SPT_SEG_PIECE 32
+#endif
+
+namespace spt {
+
+namespace {
+
+constexpr int kPiece = SPT_SEG_PIECE;  // nonzeros per piece (L)
+constexpr int kUnroll = SPT_SEG_UB;    // nonzeros in flight per lane group
+
+// LDS: crdg[nm - 1][T] u32 (non-output coordinates, row-grouped), valg[T] f32,
+// hkey[T] u32 (slot -> row), hcnt[T + 4] u32 (packed counts, then prefixes;
+// entry T holds the totals), ptab[T] u16 (piece -> slot).
+__host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes) {
+    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2;
+}
+
+struct SegLds {
+    uint32_t *crdg;
+    float *valg;
+    uint32_t *hkey;
+    uint32_t *hcnt;
+    uint16_t *ptab;
+};
+
+__device__ __forceinline__ SegLds seg_carve(char *p, int T, int nmodes) {
+    SegLds L;
+    L.crdg = (uint32_t *)p;
+    L.valg = (float *)(L.crdg + (size_t)(nmodes - 1) * T);
+    L.hkey = (uint32_t *)(L.valg + T);
+    L.hcnt = L.hkey + T;
+    L.ptab = (uint16_t *)(L.hcnt + T + 4);
+    return L;
+}
+
+// Stage and regroup one tile.  After return: hcnt[s] = (first position of
+// slot s) << 16 | (first piece of slot s); hcnt[T] = (cnt << 16) | pieces;
+// crdg/valg hold the tile in row-grouped order and ptab maps pieces to slots.
+// With SCATTER false only the counts are formed (the plan's counting pass).
+template <int NT, int NMAX, bool SCATTER>
+__device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, const SegLds &L, const CodecRegs &cr,
+                                          uint32_t *wsum) {
+    constexpr int T = 4 * NT;
+    const int tid = threadIdx.x;
+    const int64_t base = tile * (int64_t)T;
+    const int64_t rem = a.nnz - base;
+    const int cnt = rem < T ? (int)rem : T;
+    for (int i = tid; i < T; i += NT) {
+        L.hkey[i] = kNoRow;
+        L.hcnt[i] = 0;
+    }
+    uint32_t w[4][4];
+    float v[4];
+    const int nwords = 2 * a.codec.key_words;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT;
+        uint64_t klo = 0, khi = 0;
+        float x = 0.f;
+        if (e < cnt) {
+            klo = __builtin_nontemporal_load(a.lo + base + e);
+            if (nwords == 4) khi = __builtin_nontemporal_load(a.hi + base + e);
+            if (SCATTER) x = __builtin_nontemporal_load(a.vals + base + e);
+        }
+        w[u][0] = (uint32_t)klo;
+        w[u][1] = (uint32_t)(klo >> 32);
+        w[u][2] = (uint32_t)khi;
+        w[u][3] = (uint32_t)(khi >> 32);
+        v[u] = x;
+    }
+    // coordinates of every mode (only the output mode when counting)
+    uint32_t xc[NMAX][4];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xc[k][u] = 0;
+        if (k < a.nmodes && (SCATTER || k == a.mode)) {
+#pragma unroll
+            for (int word = 0; word < 4; ++word) {
+                if (word < nwords) {
+                    const int r0 = __builtin_amdgcn_readlane(cr.rb, k * 5 + word);
+                    const int r1 = __builtin_amdgcn_readlane(cr.rb, k * 5 + word + 1);
+                    for (int r = r0; r < r1; ++r) {
+                        const uint32_t d = run_desc(cr, r);
+                        const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) xc[k][u] |= __builtin_amdgcn_ubfe(w[u][word], kpos, len) << cpos;
+                    }
+                }
+            }
+        }
+    }
+    uint32_t rowv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        rowv[u] = 0;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k)
+            if (k == a.mode) rowv[u] = xc[k][u];
+    }
+    __syncthreads();  // hash cleared
+    uint32_t sr[4];   // slot << 16 | rank within the slot
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT;
+        sr[u] = 0;
+        if (e < cnt) {
+            const uint32_t row = rowv[u];
+            uint32_t s = mix_hash(row) & (uint32_t)(T - 1);
+            for (;;) {
+                const uint32_t prev = atomicCAS(&L.hkey[s], kNoRow, row);
+                if (prev == kNoRow || prev == row) break;
+                s = (s + 1) & (uint32_t)(T - 1);
+            }
+            sr[u] = (s << 16) | atomicAdd(&L.hcnt[s], 1u);
+        }
+    }
+    __syncthreads();
+    // packed (count << 16 | pieces) per slot, then one exclusive scan
+    for (int i = tid; i < T; i += NT) {
+        const uint32_t c = L.hcnt[i];
+        L.hcnt[i] = (c << 16) | ((c + kPiece - 1) / kPiece);
+    }
+    __syncthreads();
+    block_scan_lds(L.hcnt, T, NT, wsum);
+    if (tid == 0) {
+        // totals: elements = cnt; pieces = prefix of the last slot plus its own pieces
+        const uint32_t pl = L.hcnt[T - 1] & 0xFFFFu;
+        const uint32_t el = L.hcnt[T - 1] >> 16;
+        const uint32_t own = (uint32_t)cnt - el;
+        L.hcnt[T] = ((uint32_t)cnt << 16) | (pl + (own + kPiece - 1) / kPiece);
+    }
+    if constexpr (SCATTER) {
+        const int nm = a.nmodes, mode = a.mode;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * NT;
+            if (e < cnt) {
+                const int pos = (int)(L.hcnt[sr[u] >> 16] >> 16) + (int)(sr[u] & 0xFFFFu);
+                L.valg[pos] = v[u];
+#pragma unroll
+                for (int k = 0; k < NMAX; ++k)
+                    if (k < nm && k != mode) L.crdg[(k - (k > mode)) * T + pos] = xc[k][u];
+            }
+        }
+        __syncthreads();  // totals visible
+        for (int i = tid; i < T; i += NT) {
+            const uint32_t pk = L.hcnt[i];
+            const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
+            const uint32_t c = (nx >> 16) - (pk >> 16);
+            const uint32_t p0 = pk & 0xFFFFu, np = (c + kPiece - 1) / kPiece;
+            for (uint32_t q = 0; q < np; ++q) L.ptab[p0 + q] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT, int G, int VEC, int NB, int NMAX>
+__global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles) {
+    constexpr int T = 4 * NT;
+    constexpr int UB = kUnroll;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
+    const int npieces = (int)(L.hcnt[T] & 0xFFFFu);
+    const int64_t rbase = a.rec_off[tile];
+    const int j = threadIdx.x % G;
+    const int R = a.rank, mode = a.mode, nm = a.nmodes;
+    for (int k = threadIdx.x / G; k < npieces; k += NT / G) {
+        const int s = L.ptab[k];
+        const uint32_t pk = L.hcnt[s];
+        const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
+        const int first = (int)(pk >> 16), last = (int)(pn >> 16);
+        const int p0 = first + (k - (int)(pk & 0xFFFFu)) * kPiece;
+        const int p1 = min(p0 + kPiece, last);
+        float acc[NB][VEC];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[b][v] = 0.f;
+        for (int q = p0; q < p1; q += UB) {
+            int pp[UB];
+            float p[UB][NB][VEC];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const bool ok = q + u < p1;
+                pp[u] = ok ? q + u : p0;
+                const float x = ok ? L.valg[pp[u]] : 0.f;
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) p[u][b][v] = x;
+            }
+#pragma unroll
+            for (int kk = 0; kk < NMAX; ++kk) {
+                if (kk < nm && kk != mode) {
+                    const float *__restrict__ F = a.f[kk];
+                    const uint32_t *cg = L.crdg + (kk - (kk > mode)) * T;
+                    float xv[UB][NB][VEC];
+#pragma unroll
+                    for (int u = 0; u < UB; ++u) {
+                        const float *fr = F + (int64_t)cg[pp[u]] * R;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            const int c = (b * G + j) * VEC;
+                            if (c < R) {
+                                load_vec<VEC>(fr + c, xv[u][b]);
+                            } else {
+#pragma unroll
+                                for (int v = 0; v < VEC; ++v) xv[u][b][v] = 0.f;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < UB; ++u)
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) p[u][b][v] *= xv[u][b][v];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[b][v] += p[u][b][v];
+        }
+        const int64_t pos = rbase + k;
+        if (j == 0) a.rec_row[pos] = (uint64_t)L.hkey[s];
+        float *o = a.rec_val + pos * R;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int c = (b * G + j) * VEC;
+            if (c < R) {
+                if constexpr (VEC == 4) {
+                    *reinterpret_cast<float4 *>(o + c) = make_float4(acc[b][0], acc[b][1], acc[b][2], acc[b][3]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) o[c + v] = acc[b][v];
+                }
+            }
+        }
+    }
+}
+
+// Pieces of every tile (the plan's counting pass).
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntiles, int64_t *__restrict__ out) {
+    constexpr int T = 4 * NT;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t tile = blockIdx.x;
+    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
+    if (threadIdx.x == 0) out[tile] = L.hcnt[T] & 0xFFFFu;
+}
+
+template <int NT, int NMAX, int G, int VEC, int NB>
+spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
+    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
+    hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+template <int NT, int NMAX>
+spt_status launch_seg_nt(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
+    const int R = a.rank;
+    if ((R & 3) == 0) {
+        const int r4 = R >> 2;
+        if (r4 <= 1) return launch_seg_k<NT, NMAX, 1, 4, 1>(a, ntiles, s);
+        if (r4 <= 2) return launch_seg_k<NT, NMAX, 2, 4, 1>(a, ntiles, s);
+        if (r4 <= 4) return launch_seg_k<NT, NMAX, 4, 4, 1>(a, ntiles, s);
+        if (r4 <= 8) return launch_seg_k<NT, NMAX, 8, 4, 1>(a, ntiles, s);
+        if (r4 <= 16) return launch_seg_k<NT, NMAX, 16, 4, 1>(a, ntiles, s);
+        if (r4 <= 32) return launch_seg_k<NT, NMAX, 32, 4, 1>(a, ntiles, s);
+        return launch_seg_k<NT, NMAX, 64, 4, 1>(a, ntiles, s);
+    }
+    if (R <= 64) return launch_seg_k<NT, NMAX, 64, 1, 1>(a, ntiles, s);
+    if (R <= 128) return launch_seg_k<NT, NMAX, 64, 1, 2>(a, ntiles, s);
+    if (R <= 192) return launch_seg_k<NT, NMAX, 64, 1, 3>(a, ntiles, s);
+    return launch_seg_k<NT, NMAX, 64, 1, 4>(a, ntiles, s);
+}
+
+template <int NT>
+spt_status launch_count_nt(const MttkrpArgs &a, int64_t ntiles, int64_t *out, hipStream_t s) {
+    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
+    if (a.nmodes <= 4)
+        hipLaunchKernelGGL((k_count_pieces<NT, 4>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, out);
+    else
+        hipLaunchKernelGGL((k_count_pieces<NT, 8>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, out);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+}  // namespace
+
+// tile sizes served: 1024 (256 threads), 2048 (512), 4096 (1024 threads)
+bool seg_tile_ok(int tile, int nmodes) {
+    if (tile != 1024 && tile != 2048 && tile != 4096) return false;
+    return seg_lds_bytes(tile, nmodes) <= 160 * 1024 - 1024;
+}
+
+spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s) {
+    const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
+    if (ntiles == 0) return SPT_OK;
+    if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
+    if (a.tile == 1024) return launch_count_nt<256>(a, ntiles, counts, s);
+    if (a.tile == 2048) return launch_count_nt<512>(a, ntiles, counts, s);
+    return launch_count_nt<1024>(a, ntiles, counts, s);
+}
+
+spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
+    const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
+    if (ntiles == 0) return SPT_OK;
+    if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
+    const bool n4 = a.nmodes <= 4;
+    if (a.tile == 1024) return n4 ? launch_seg_nt<256, 4>(a, ntiles, s) : launch_seg_nt<256, 8>(a, ntiles, s);
+    if (a.tile == 2048) return n4 ? launch_seg_nt<512, 4>(a, ntiles, s) : launch_seg_nt<512, 8>(a, ntiles, s);
+    return n4 ? launch_seg_nt<1024, 4>(a, ntiles, s) : launch_seg_nt<1024, 8>(a, ntiles, s);
+}
+
+}  // namespace spt

@@ -111,6 +111,14 @@ void release_plans(Tensor *t) {
     }
 }
 
+// SEGMENT tile: the plan's tile if it is one the kernel serves and it fits
+// LDS, else 2048 (fits every mode count up to 8)
+int segment_tile(const Tensor *t, int mode) {
+    const int want = t->plan.tile[mode];
+    if (want >= 1024 && seg_tile_ok(want, t->nmodes)) return want;
+    return seg_tile_ok(2048, t->nmodes) ? 2048 : 1024;
+}
+
 spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out) {
     ModePlan &p = t->mplan[mode];
     int want = t->plan.strategy[mode];
@@ -186,16 +194,16 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
         }
         p.rec_off = cnt;
     } else if (want == SPT_STRATEGY_SEGMENT) {
-        // counting pass: distinct output rows of every tile; a tile's record range
-        // holds those plus (groups - 1) slots for segments cut by chunk edges
-        p.ts = t->plan.tile[mode];
+        // counting pass: pieces (runs of at most 32 nonzeros of one row) of every
+        // tile; a tile's records are exactly its pieces
+        p.ts = segment_tile(t, mode);
         const int64_t ntiles = (t->nnz + p.ts - 1) / p.ts;
         int64_t *off = nullptr;
         SPT_HIP(hipMalloc(&off, sizeof(int64_t) * (ntiles + 1)));
         std::vector<int64_t> h(ntiles + 1, 0);
         spt_status st = SPT_OK;
         if (ntiles > 0) {
-            st = launch_count_distinct(make_args(t, nullptr, rank, mode, nullptr, p.ts), off, s);
+            st = launch_count_pieces(make_args(t, nullptr, rank, mode, nullptr, p.ts), off, s);
             if (st == SPT_OK && (hipMemcpyAsync(h.data(), off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
                                  hipStreamSynchronize(s) != hipSuccess))
                 st = hip_fail(hipGetLastError(), "plan: distinct rows per tile");
@@ -204,10 +212,9 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
             (void)hipFree(off);
             return st;
         }
-        const int slack = seg_groups(rank) - 1;
         int64_t run = 0;
         for (int64_t i = 0; i < ntiles; ++i) {
-            const int64_t c = h[i] + slack;
+            const int64_t c = h[i];
             h[i] = run;
             run += c;
         }
@@ -319,7 +326,7 @@ spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int
     }
     uint64_t *srow = nullptr;
     uint32_t *sidx = nullptr;
-    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, keys2, ia, ib, cnt, P, t->lbits[mode] + 1, &srow, &sidx, s);
+    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, keys2, ia, ib, cnt, P, t->lbits[mode], &srow, &sidx, s);
     if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
     if (st == SPT_OK) st = launch_reduce_records(srow, sidx, rval, P, rank, rows, out, s);
     return st;
@@ -334,13 +341,12 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
         const int64_t P = p->records;
         MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
         a.rec_off = p->rec_off;
-        a.rec_sentinel = (uint64_t)1 << t->lbits[mode];
         return reduce_via_records(t, a, P, rank, rows, out, s, /*segment=*/true);
     }
     if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
         st = launch_fill_zero(out, rows * (int64_t)rank, s);
         if (st != SPT_OK || t->nnz == 0) return st;
-        return launch_mttkrp(make_args(t, factors, rank, mode, out, t->plan.tile[mode]), p->strategy, s);
+        return launch_mttkrp(make_args(t, factors, rank, mode, out, std::min(t->plan.tile[mode], 1024)), p->strategy, s);
     }
     TableArgs ta{};
     ta.a = make_args(t, factors, rank, mode, out, 0);

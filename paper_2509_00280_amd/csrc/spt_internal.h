@@ -126,14 +126,13 @@ struct MttkrpArgs {
     uint64_t *rec_row;
     float *rec_val;
     const int64_t *rec_off;   // per tile, ntiles + 1 entries
-    uint64_t rec_sentinel;
     Codec codec;
 };
 spt_status launch_fill_zero(float *p, int64_t n, hipStream_t s);
 MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int mode, float *out, int tile);
 spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s);
-int seg_groups(int rank);
-spt_status launch_count_distinct(const MttkrpArgs &a, int64_t *counts, hipStream_t s);
+bool seg_tile_ok(int tile, int nmodes);
+spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 
 // Per-tensor descriptor of the batched persistent MTTKRP.

@@ -102,7 +102,7 @@ def test_mttkrp_small_all_modes(spt, small, rank, strategy):
         assert bad == 0 and err <= TOL
 
 
-@pytest.mark.parametrize("tile,strategy", [(256, 1), (512, 1), (1024, 1), (1024, 2), (1024, 4), (256, 5), (512, 5),
+@pytest.mark.parametrize("tile,strategy", [(256, 1), (512, 1), (1024, 1), (1024, 2), (4096, 4), (2048, 5), (4096, 5),
                                            (1024, 5)])
 def test_mttkrp_skewed_tiles_ragged(spt, tile, strategy):
     # 4-mode power-law tensor with a ragged last tile, rank 64
