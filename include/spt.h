@@ -181,20 +181,29 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
 /* ---------------------------------------------------------------------- */
 
 /*
- * One persistent launch computes the mode-`mode` MTTKRP of every tensor in
- * the batch; tensors with nmodes <= mode are skipped.  factors[b] is a host
- * array of device pointers for tensor b, outs[b] its output (overwritten),
- * ranks[b] its rank (<= 64).  Asynchronous.
+ * Mode-`mode` MTTKRP of every tensor in the batch with one SEGMENT launch
+ * over all tensors' tiles (2048 nonzeros each), one radix sort of all
+ * records and one reduction; tensors with nmodes <= mode are skipped and
+ * their outs[b] is not touched.  factors[b] is a host array of device
+ * pointers for tensor b, outs[b] its output (I_mode x ranks[b], overwritten),
+ * 1 <= ranks[b] <= 64.  The first call at a mode plans every tensor that
+ * lacks a batched plan (one counting launch for all of them).  Synchronises
+ * `stream` before returning (the record workspace is released).
  */
 spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *const *const *factors,
                               const int *ranks, int mode, float *const *outs, void *stream);
 
 /*
- * CP-ALS of every tensor of the batch, advanced in lock step: each step runs
- * one batched MTTKRP launch per mode index and one batched FP64 solve.
- * Tensors stop individually (max_iters, tol); fits[b] and iters[b] are host
- * arrays, lambdas[b] device arrays of ranks[b] doubles.  Synchronises once
- * per iteration.
+ * CP-ALS of every tensor of the batch, advanced in lock step with the same
+ * update and fit as spt_cp_als: per mode index, one batched MTTKRP (as
+ * spt_mttkrp_batched, into one concatenated output) and one launch each of
+ * the batched Gram, FP64 solve and apply kernels (one workgroup per tensor;
+ * apply over all row blocks); then one fit launch for all tensors.  Tensors
+ * stop individually (max_iters, tol) and leave the batch.  factors[b] is a
+ * host array of device pointers (in: initial, out: normalised), lambdas[b]
+ * a device array of ranks[b] doubles, fits[b] and iters[b] host outputs.
+ * Synchronises once per iteration (plus once when a fit takes the direct
+ * residual).  Errors: as spt_cp_als, for the first failing tensor.
  */
 spt_status spt_cp_als_batched(const spt_tensor *ts, int count, const int *ranks, int max_iters,
                               double tol, float *const *const *factors, double *const *lambdas,

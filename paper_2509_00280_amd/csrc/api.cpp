@@ -151,8 +151,6 @@ spt_status check_factors(const Tensor *t, const float *const *factors, int rank,
 
 using namespace spt;
 
-struct spt_tensor_s : Tensor {};
-
 extern "C" {
 
 const char *spt_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,592 @@
+// Lock-step CP-ALS of many independent tensors (many decompositions run side
+// by side, as in the paper's workflow of repeated decompositions, Section
+// IV-D) and the batched MTTKRP behind it.
+//
+// Per mode index n, every member tensor with more than n modes takes part in
+// ONE launch of each step:
+//   * SEGMENT MTTKRP over all members' tiles (tiles of kBatchTile nonzeros);
+//     records carry rows of a concatenated output M_all (member b's rows start
+//     at row_base[b], leading dimension ld = the largest rank of the mode),
+//     one radix sort of all records by row, one segmented reduction into M_all;
+//   * Gram of every member's block of M_all, the FP64 normal-equation solve,
+//     the apply (factor = M S, rounded to FP32, fit inner product on the last
+//     mode), and the Gram of the new factor, each one workgroup per member
+//     (apply: a grid over all members' row blocks).
+// One FP64 fit kernel for all members and one host readback close the
+// iteration; members leave the active set when they converge.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "spt_internal.h"
+
+namespace spt {
+
+spt_status check_factors(const Tensor *t, const float *const *factors, int rank, int skip_mode);
+
+namespace {
+
+int bit_len(int64_t x) {  // bits to hold values 0..x-1
+    int b = 0;
+    while ((int64_t(1) << b) < x) ++b;
+    return b;
+}
+
+}  // namespace
+
+// Builds the batched SEGMENT plan of `mode` for every tensor that lacks it:
+// one counting launch over all their tiles and one readback.
+spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s) {
+    std::vector<Tensor *> need;
+    for (Tensor *t : ts)
+        if (t->nmodes > mode && !t->bseg_off[mode]) need.push_back(t);
+    if (need.empty()) return SPT_OK;
+    int nmax = 0;
+    std::vector<SegItem> items(need.size());
+    int64_t tiles = 0;
+    for (size_t i = 0; i < need.size(); ++i) {
+        items[i] = SegItem{};
+        items[i].a = make_args(need[i], nullptr, 1, mode, nullptr, kBatchTile);
+        items[i].first_tile = tiles;
+        tiles += (need[i]->nnz + kBatchTile - 1) / kBatchTile;
+        nmax = std::max(nmax, need[i]->nmodes);
+    }
+    if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "batch: too many modes for the batched tile");
+    SegItem *d_items = nullptr;
+    int64_t *d_cnt = nullptr;
+    SPT_HIP(hipMalloc(&d_items, sizeof(SegItem) * items.size()));
+    if (hipMalloc(&d_cnt, sizeof(int64_t) * std::max<int64_t>(tiles, 1)) != hipSuccess) {
+        (void)hipFree(d_items);
+        return hip_fail(hipGetLastError(), "batch plan: counts");
+    }
+    std::vector<int64_t> h(std::max<int64_t>(tiles, 1), 0);
+    spt_status st = SPT_OK;
+    if (hipMemcpyAsync(d_items, items.data(), sizeof(SegItem) * items.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "batch plan: upload");
+    if (st == SPT_OK) st = launch_count_pieces_batched(d_items, (int)items.size(), tiles, nmax, d_cnt, s);
+    if (st == SPT_OK && tiles > 0 &&
+        hipMemcpyAsync(h.data(), d_cnt, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "batch plan: readback");
+    if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "batch plan: sync");
+    (void)hipFree(d_items);
+    (void)hipFree(d_cnt);
+    if (st != SPT_OK) return st;
+    for (size_t i = 0; i < need.size(); ++i) {
+        Tensor *t = need[i];
+        const int64_t nt = (t->nnz + kBatchTile - 1) / kBatchTile;
+        std::vector<int64_t> off(nt + 1, 0);
+        int64_t run = 0;
+        for (int64_t k = 0; k < nt; ++k) {
+            off[k] = run;
+            run += h[items[i].first_tile + k];
+        }
+        off[nt] = run;
+        int64_t *d = nullptr;
+        SPT_HIP(hipMalloc(&d, sizeof(int64_t) * (nt + 1)));
+        if (hipMemcpy(d, off.data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(hipGetLastError(), "batch plan: offsets");
+        }
+        t->bseg_off[mode] = d;
+        t->bseg_records[mode] = run;
+    }
+    return SPT_OK;
+}
+
+// The batched MTTKRP pipeline of one mode into M_all (rows x ld, overwritten).
+spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_max,
+                                   int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
+                                   BatchMttkrpWs &ws, hipStream_t s) {
+    if (rows == 0) return SPT_OK;
+    if (records == 0 || total_tiles == 0) return launch_fill_zero(M_all, rows * (int64_t)ld, s);
+    if (records >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "batch: more than 2^32 records");
+    const size_t n1 = (size_t)records;
+    uint64_t *rrow = (uint64_t *)ws.rec_row.get(sizeof(uint64_t) * n1, s);
+    float *rval = (float *)ws.rec_val.get(sizeof(float) * n1 * ld, s);
+    uint64_t *k2 = (uint64_t *)ws.keys2.get(sizeof(uint64_t) * n1, s);
+    uint32_t *ia = (uint32_t *)ws.ia.get(sizeof(uint32_t) * n1, s);
+    uint32_t *ib = (uint32_t *)ws.ib.get(sizeof(uint32_t) * n1, s);
+    uint32_t *cnt = (uint32_t *)ws.cnt.get(sizeof(uint32_t) * sort_ws_counts(records), s);
+    if (!rrow || !rval || !k2 || !ia || !ib || !cnt) return fail(SPT_E_OOM, "batch: record workspace");
+    spt_status st = launch_mttkrp_seg_batched(d_items, count, total_tiles, nmodes_max, ld, vec4, rrow, rval, s);
+    uint64_t *srow = nullptr;
+    uint32_t *sidx = nullptr;
+    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, k2, ia, ib, cnt, records, bit_len(rows), &srow, &sidx, s);
+    if (st == SPT_OK) st = launch_fill_zero(M_all, rows * (int64_t)ld, s);
+    if (st == SPT_OK) st = launch_reduce_records(srow, sidx, rval, records, ld, rows, M_all, s);
+    return st;
+}
+
+// ---------------------------------------------------------------- engine
+BatchEngine::BatchEngine(hipStream_t s) : s_(s) {}
+
+BatchEngine::~BatchEngine() {
+    (void)hipStreamSynchronize(s_);
+    for (Member *m : members_) free_member_state(m);
+    release_buffers();
+}
+
+void BatchEngine::release_buffers() {
+    for (void *p : {(void *)d_items_, (void *)M_all_, (void *)fit_all_, (void *)status_all_, (void *)inner_all_, (void *)resid_})
+        if (p) (void)hipFree(p);
+    d_items_ = nullptr;
+    M_all_ = nullptr;
+    fit_all_ = nullptr;
+    status_all_ = nullptr;
+    inner_all_ = nullptr;
+    resid_ = nullptr;
+    items_bytes_ = M_bytes_ = fit_cap_ = inner_cap_ = resid_cap_ = 0;
+    ws_.release();
+}
+
+void BatchEngine::free_member_state(Member *m) {
+    if (m->state) (void)hipFree(m->state);
+    m->state = nullptr;
+}
+
+spt_status BatchEngine::add(Member *m) {
+    Tensor *t = m->t;
+    if (!t || m->R < 1 || m->R > SPT_MAX_ALS_RANK) return fail(SPT_E_INVALID_ARG, "batch: rank must be 1..64");
+    if (!(t->norm_x2 > 0.0)) return fail(SPT_E_INVALID_ARG, "batch: tensor norm is zero");
+    spt_status st = check_factors(t, (const float *const *)m->F, m->R, -1);
+    if (st != SPT_OK) return st;
+    const int N = t->nmodes, R = m->R;
+    const size_t bytes = sizeof(double) * ((size_t)N * R * R + 2 * (size_t)R * R);
+    SPT_HIP(hipMalloc(&m->state, bytes));
+    m->grams = (double *)m->state;
+    m->gram_m = m->grams + (size_t)N * R * R;
+    m->S = m->gram_m + (size_t)R * R;
+    m->fit = m->fit_prev = 0.0;
+    m->iters = 0;
+    m->done = false;
+    m->err = SPT_OK;
+    m->fresh = true;
+    members_.push_back(m);
+    dirty_ = true;
+    return SPT_OK;
+}
+
+void BatchEngine::remove(Member *m) {
+    auto it = std::find(members_.begin(), members_.end(), m);
+    if (it == members_.end()) return;
+    (void)hipStreamSynchronize(s_);
+    free_member_state(m);
+    members_.erase(it);
+    dirty_ = true;
+}
+
+// Per-mode item arrays and workspace sizes for the current members.
+spt_status BatchEngine::rebuild() {
+    std::vector<Member *> act;
+    for (Member *m : members_)
+        if (!m->done) act.push_back(m);
+    active_ = act;
+    nmodes_max_ = 0;
+    for (Member *m : act) nmodes_max_ = std::max(nmodes_max_, m->t->nmodes);
+    if (!act.empty() && !seg_batch_fits(nmodes_max_)) return fail(SPT_E_INVALID_ARG, "batch: too many modes");
+    std::vector<Tensor *> ts;
+    for (Member *m : act) ts.push_back(m->t);
+    for (int n = 0; n < nmodes_max_; ++n) {
+        spt_status st = ensure_batch_plans(ts, n, s_);
+        if (st != SPT_OK) return st;
+    }
+    // host images of every item array, packed into one upload
+    std::vector<char> blob;
+    auto put = [&blob](const void *p, size_t bytes) {
+        const size_t off = (blob.size() + 255) & ~size_t(255);
+        blob.resize(off + bytes);
+        if (bytes) std::memcpy(blob.data() + off, p, bytes);
+        return off;
+    };
+    const int A = (int)act.size();
+    // inner-product partials: one range per member for its last mode
+    std::vector<int64_t> inner_base(A, 0), inner_n(A, 0);
+    int64_t inner_total = 0;
+    modes_.assign(nmodes_max_, ModeItems{});
+    size_t M_need = 0;
+    int64_t max_records = 0;
+    for (int n = 0; n < nmodes_max_; ++n) {
+        ModeItems &mi = modes_[n];
+        std::vector<SegItem> seg;
+        std::vector<GramItem> gm, gc;
+        std::vector<SolveItem> sv;
+        std::vector<ApplyItem> ap;
+        int rmax = 0;
+        bool vec4 = true;
+        for (Member *m : act)
+            if (m->t->nmodes > n) {
+                rmax = std::max(rmax, m->R);
+                vec4 = vec4 && (m->R % 4 == 0);
+            }
+        const int ld = rmax;
+        const int rw = rmax > 0 ? apply_rows_per_launch_block(rmax) : 1;
+        int64_t tiles = 0, recs = 0, rows = 0, blocks = 0;
+        for (int i = 0; i < A; ++i) {
+            Member *m = act[i];
+            Tensor *t = m->t;
+            if (t->nmodes <= n) continue;
+            const int R = m->R;
+            SegItem si{};
+            si.a = make_args(t, (const float *const *)m->F, R, n, nullptr, kBatchTile);
+            si.a.rec_off = t->bseg_off[n];
+            si.first_tile = tiles;
+            si.rec_base = recs;
+            si.row_base = rows;
+            seg.push_back(si);
+            const int64_t In = t->dims[n];
+            // M_all block of this member: filled in below once M_all exists (offset only here)
+            GramItem g1{};
+            g1.C = reinterpret_cast<const float *>((uintptr_t)(rows * ld));  // element offset, rebased later
+            g1.rows = In;
+            g1.ld = ld;
+            g1.rank = R;
+            g1.G = m->gram_m;
+            gm.push_back(g1);
+            SolveItem so{};
+            so.grams = m->grams;
+            so.gram_m = m->gram_m;
+            so.S = m->S;
+            so.lambda = m->lambda;
+            so.status = nullptr;  // rebased below (status_all + 8 i)
+            so.nmodes = t->nmodes;
+            so.rank = R;
+            sv.push_back(so);
+            ApplyItem ai{};
+            ai.M = reinterpret_cast<const float *>((uintptr_t)(rows * ld));
+            ai.S = m->S;
+            ai.C = m->F[n];
+            ai.lambda = m->lambda;
+            const int64_t nb = std::max<int64_t>(1, (In + rw - 1) / rw);
+            if (n == t->nmodes - 1) {
+                inner_base[i] = inner_total;
+                inner_n[i] = nb;
+                inner_total += nb;
+                ai.inner = reinterpret_cast<double *>((uintptr_t)(inner_base[i] + 1));  // marker, rebased below
+            }
+            ai.rows = In;
+            ai.first_block = blocks;
+            ai.ldm = ld;
+            ai.rank = R;
+            ap.push_back(ai);
+            GramItem g2{};
+            g2.C = m->F[n];
+            g2.rows = In;
+            g2.ld = R;
+            g2.rank = R;
+            g2.G = m->grams + (size_t)n * R * R;
+            gc.push_back(g2);
+            mi.member_idx.push_back(i);
+            tiles += (t->nnz + kBatchTile - 1) / kBatchTile;
+            recs += t->bseg_records[n];
+            rows += In;
+            blocks += nb;
+        }
+        mi.count = (int)seg.size();
+        mi.tiles = tiles;
+        mi.records = recs;
+        mi.rows = rows;
+        mi.blocks = blocks;
+        mi.ld = ld;
+        mi.rmax = rmax;
+        mi.vec4 = vec4;
+        M_need = std::max(M_need, sizeof(float) * (size_t)rows * std::max(ld, 1));
+        max_records = std::max(max_records, recs);
+        mi.seg_v = std::move(seg);
+        mi.gm_v = std::move(gm);
+        mi.sv_v = std::move(sv);
+        mi.ap_v = std::move(ap);
+        mi.gc_v = std::move(gc);
+    }
+    (void)max_records;
+    // device buffers that item pointers refer to
+    SPT_HIP(hipStreamSynchronize(s_));
+    if (M_need > M_bytes_) {
+        if (M_all_) (void)hipFree(M_all_);
+        M_all_ = nullptr;
+        M_bytes_ = 0;
+        SPT_HIP(hipMalloc(&M_all_, M_need));
+        M_bytes_ = M_need;
+    }
+    if ((size_t)A > fit_cap_) {
+        if (fit_all_) (void)hipFree(fit_all_);
+        if (status_all_) (void)hipFree(status_all_);
+        fit_all_ = nullptr;
+        status_all_ = nullptr;
+        SPT_HIP(hipMalloc(&fit_all_, sizeof(double) * 4 * A));
+        SPT_HIP(hipMalloc(&status_all_, sizeof(int) * kMaxModes * A));
+        fit_cap_ = A;
+    }
+    if ((size_t)inner_total > inner_cap_) {
+        if (inner_all_) (void)hipFree(inner_all_);
+        inner_all_ = nullptr;
+        SPT_HIP(hipMalloc(&inner_all_, sizeof(double) * std::max<int64_t>(inner_total, 1)));
+        inner_cap_ = inner_total;
+    }
+    // rebase offsets into real pointers and pack
+    std::vector<FitItem> fit(A);
+    for (int i = 0; i < A; ++i) {
+        Member *m = act[i];
+        FitItem f{};
+        f.grams = m->grams;
+        f.lambda = m->lambda;
+        f.inner = inner_all_ + inner_base[i];
+        f.nparts = (int)inner_n[i];
+        f.out = fit_all_ + 4 * i;
+        f.norm_x2 = m->t->norm_x2;
+        f.nmodes = m->t->nmodes;
+        f.rank = m->R;
+        fit[i] = f;
+    }
+    for (int n = 0; n < nmodes_max_; ++n) {
+        ModeItems &mi = modes_[n];
+        for (size_t k = 0; k < mi.gm_v.size(); ++k) {
+            mi.gm_v[k].C = M_all_ + (uintptr_t)mi.gm_v[k].C;
+            mi.ap_v[k].M = M_all_ + (uintptr_t)mi.ap_v[k].M;
+            if (mi.ap_v[k].inner) mi.ap_v[k].inner = inner_all_ + ((uintptr_t)mi.ap_v[k].inner - 1);
+            mi.sv_v[k].status = status_all_ + kMaxModes * mi.member_idx[k];
+        }
+        mi.seg_off = put(mi.seg_v.data(), sizeof(SegItem) * mi.seg_v.size());
+        mi.gm_off = put(mi.gm_v.data(), sizeof(GramItem) * mi.gm_v.size());
+        mi.sv_off = put(mi.sv_v.data(), sizeof(SolveItem) * mi.sv_v.size());
+        mi.ap_off = put(mi.ap_v.data(), sizeof(ApplyItem) * mi.ap_v.size());
+        mi.gc_off = put(mi.gc_v.data(), sizeof(GramItem) * mi.gc_v.size());
+    }
+    fit_off_ = put(fit.data(), sizeof(FitItem) * fit.size());
+    // initial Grams of the new members' factors
+    std::vector<GramItem> init;
+    int init_rmax = 0;
+    for (Member *m : act)
+        if (m->fresh) {
+            for (int k = 0; k < m->t->nmodes; ++k) {
+                GramItem g{};
+                g.C = m->F[k];
+                g.rows = m->t->dims[k];
+                g.ld = m->R;
+                g.rank = m->R;
+                g.G = m->grams + (size_t)k * m->R * m->R;
+                init.push_back(g);
+            }
+            init_rmax = std::max(init_rmax, m->R);
+            m->fresh = false;
+        }
+    init_off_ = put(init.data(), sizeof(GramItem) * init.size());
+    init_count_ = (int)init.size();
+    init_rmax_ = init_rmax;
+    if (blob.size() > items_bytes_) {
+        if (d_items_) (void)hipFree(d_items_);
+        d_items_ = nullptr;
+        items_bytes_ = 0;
+        SPT_HIP(hipMalloc(&d_items_, blob.size()));
+        items_bytes_ = blob.size();
+    }
+    if (!blob.empty()) SPT_HIP(hipMemcpy(d_items_, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    if (init_count_ > 0) {
+        spt_status st = launch_gram_batched((const GramItem *)(d_items_ + init_off_), init_count_, init_rmax_, s_);
+        if (st != SPT_OK) return st;
+    }
+    dirty_ = false;
+    return SPT_OK;
+}
+
+spt_status BatchEngine::step() {
+    if (dirty_) {
+        spt_status st = rebuild();
+        if (st != SPT_OK) return st;
+    }
+    const int A = (int)active_.size();
+    if (A == 0) return SPT_OK;
+    for (int n = 0; n < nmodes_max_; ++n) {
+        const ModeItems &mi = modes_[n];
+        if (mi.count == 0) continue;
+        spt_status st = run_mttkrp_batched_mode((const SegItem *)(d_items_ + mi.seg_off), mi.count, mi.tiles, nmodes_max_,
+                                                mi.records, mi.rows, mi.ld, mi.vec4, M_all_, ws_, s_);
+        if (st == SPT_OK) st = launch_gram_batched((const GramItem *)(d_items_ + mi.gm_off), mi.count, mi.rmax, s_);
+        if (st == SPT_OK) st = launch_solve_prep_batched((const SolveItem *)(d_items_ + mi.sv_off), mi.count, n, s_);
+        if (st == SPT_OK)
+            st = launch_apply_batched((const ApplyItem *)(d_items_ + mi.ap_off), mi.count, mi.blocks, mi.rmax, s_);
+        if (st == SPT_OK) st = launch_gram_batched((const GramItem *)(d_items_ + mi.gc_off), mi.count, mi.rmax, s_);
+        if (st != SPT_OK) return st;
+    }
+    spt_status st = launch_fit_batched((const FitItem *)(d_items_ + fit_off_), A, s_);
+    if (st != SPT_OK) return st;
+    hfit_.resize(4 * (size_t)A);
+    hstat_.resize((size_t)kMaxModes * A);
+    if (hipMemcpyAsync(hfit_.data(), fit_all_, sizeof(double) * 4 * A, hipMemcpyDeviceToHost, s_) != hipSuccess ||
+        hipMemcpyAsync(hstat_.data(), status_all_, sizeof(int) * kMaxModes * A, hipMemcpyDeviceToHost, s_) != hipSuccess ||
+        hipStreamSynchronize(s_) != hipSuccess)
+        return hip_fail(hipGetLastError(), "batch: fit readback");
+    // direct FP64 residual near convergence, as in the single-tensor driver
+    std::vector<int> direct;
+    for (int i = 0; i < A; ++i) {
+        Member *m = active_[i];
+        for (int n = 0; n < m->t->nmodes; ++n)
+            if (hstat_[(size_t)kMaxModes * i + n] < 0) {
+                m->err = fail(SPT_E_NOT_SPD, "cp_als: normal equations of mode " + std::to_string(n) +
+                                                 " not positive definite after ridge retries");
+                m->done = true;
+                dirty_ = true;
+            }
+        if (!m->done && 1.0 - hfit_[4 * i] < 1e-2 && m->t->nnz > 0) direct.push_back(i);
+    }
+    if (!direct.empty()) {
+        int64_t need = 0;
+        for (int i : direct) need = std::max<int64_t>(need, (active_[i]->t->nnz + 1023) / 1024);
+        if ((size_t)need > resid_cap_ || !resid_) {
+            if (resid_) (void)hipFree(resid_);
+            resid_ = nullptr;
+            SPT_HIP(hipMalloc(&resid_, sizeof(double) * 2 * need));
+            resid_cap_ = need;
+        }
+        for (int i : direct) {
+            Member *m = active_[i];
+            // each member's residual runs after the previous one (shared partials)
+            MttkrpArgs a = make_args(m->t, (const float *const *)m->F, m->R, -1, nullptr, 1024);
+            const int parts = (int)((m->t->nnz + 1023) / 1024);
+            st = launch_resid(a, m->lambda, resid_, parts, s_);
+            if (st == SPT_OK) st = launch_fit_direct(resid_, parts, m->t->norm_x2, fit_all_ + 4 * i, s_);
+            if (st != SPT_OK) return st;
+        }
+        if (hipMemcpyAsync(hfit_.data(), fit_all_, sizeof(double) * 4 * A, hipMemcpyDeviceToHost, s_) != hipSuccess ||
+            hipStreamSynchronize(s_) != hipSuccess)
+            return hip_fail(hipGetLastError(), "batch: direct fit readback");
+    }
+    for (int i = 0; i < A; ++i) {
+        Member *m = active_[i];
+        if (m->done) continue;
+        m->fit = hfit_[4 * i];
+        ++m->iters;
+        const bool conv = m->tol > 0.0 && std::fabs(m->fit - m->fit_prev) < m->tol;
+        m->fit_prev = m->fit;
+        if (conv || m->iters >= m->max_iters) {
+            m->done = true;
+            dirty_ = true;
+        }
+    }
+    return SPT_OK;
+}
+
+bool BatchEngine::any_active() const {
+    for (Member *m : members_)
+        if (!m->done) return true;
+    return false;
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" {
+
+spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *const *const *factors, const int *ranks,
+                              int mode, float *const *outs, void *stream) {
+    if (count < 0 || (count > 0 && (!ts || !factors || !ranks || !outs)))
+        return fail(SPT_E_INVALID_ARG, "mttkrp_batched: NULL argument");
+    if (mode < 0 || mode >= kMaxModes) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: mode out of range");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Tensor *> tv;
+    std::vector<int> idx;
+    int rmax = 0, nmax = 0;
+    bool vec4 = true;
+    for (int b = 0; b < count; ++b) {
+        Tensor *t = ts[b];
+        if (!t) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: NULL tensor " + std::to_string(b));
+        if (t->nmodes <= mode) continue;
+        if (ranks[b] < 1 || ranks[b] > 64) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: rank must be 1..64");
+        if (!outs[b]) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: NULL output " + std::to_string(b));
+        spt_status st = check_factors(t, factors[b], ranks[b], mode);
+        if (st != SPT_OK) return st;
+        tv.push_back(t);
+        idx.push_back(b);
+        rmax = std::max(rmax, ranks[b]);
+        nmax = std::max(nmax, t->nmodes);
+        vec4 = vec4 && ranks[b] % 4 == 0;
+    }
+    if (tv.empty()) return SPT_OK;
+    if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: too many modes");
+    spt_status st = ensure_batch_plans(tv, mode, s);
+    if (st != SPT_OK) return st;
+    const int ld = rmax;
+    std::vector<SegItem> items(tv.size());
+    int64_t tiles = 0, recs = 0, rows = 0;
+    std::vector<int64_t> row_base(tv.size());
+    for (size_t i = 0; i < tv.size(); ++i) {
+        Tensor *t = tv[i];
+        const int b = idx[i];
+        items[i] = SegItem{};
+        items[i].a = make_args(t, factors[b], ranks[b], mode, nullptr, kBatchTile);
+        items[i].a.rec_off = t->bseg_off[mode];
+        items[i].first_tile = tiles;
+        items[i].rec_base = recs;
+        items[i].row_base = rows;
+        row_base[i] = rows;
+        tiles += (t->nnz + kBatchTile - 1) / kBatchTile;
+        recs += t->bseg_records[mode];
+        rows += t->dims[mode];
+    }
+    SegItem *d_items = (SegItem *)dev_alloc(sizeof(SegItem) * items.size(), s);
+    float *M = (float *)dev_alloc(sizeof(float) * std::max<int64_t>(rows * ld, 1), s);
+    if (!d_items || !M) {
+        dev_free(d_items, s);
+        dev_free(M, s);
+        return fail(SPT_E_OOM, "mttkrp_batched: workspace");
+    }
+    BatchMttkrpWs ws;
+    if (hipMemcpyAsync(d_items, items.data(), sizeof(SegItem) * items.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "mttkrp_batched: upload");
+    if (st == SPT_OK) st = run_mttkrp_batched_mode(d_items, (int)items.size(), tiles, nmax, recs, rows, ld, vec4, M, ws, s);
+    for (size_t i = 0; st == SPT_OK && i < tv.size(); ++i) {
+        const int b = idx[i];
+        const int64_t In = tv[i]->dims[mode];
+        if (In == 0) continue;
+        if (hipMemcpy2DAsync(outs[b], sizeof(float) * ranks[b], M + row_base[i] * ld, sizeof(float) * ld,
+                             sizeof(float) * ranks[b], In, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            st = hip_fail(hipGetLastError(), "mttkrp_batched: output copy");
+    }
+    // the record buffers are freed only after the stream has consumed them
+    (void)hipStreamSynchronize(s);
+    ws.release();
+    dev_free(d_items, s);
+    dev_free(M, s);
+    return st;
+}
+
+spt_status spt_cp_als_batched(const spt_tensor *ts, int count, const int *ranks, int max_iters, double tol,
+                              float *const *const *factors, double *const *lambdas, double *fits, int *iters,
+                              void *stream) {
+    if (count < 0 || (count > 0 && (!ts || !ranks || !factors || !lambdas || !fits || !iters)))
+        return fail(SPT_E_INVALID_ARG, "cp_als_batched: NULL argument");
+    if (max_iters < 0) return fail(SPT_E_INVALID_ARG, "cp_als_batched: max_iters < 0");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Member> mem(count);
+    BatchEngine eng(s);
+    for (int b = 0; b < count; ++b) {
+        Member &m = mem[b];
+        if (!ts[b] || !factors[b] || !lambdas[b]) return fail(SPT_E_INVALID_ARG, "cp_als_batched: NULL member " + std::to_string(b));
+        m.t = ts[b];
+        m.R = ranks[b];
+        for (int k = 0; k < ts[b]->nmodes; ++k) m.F[k] = factors[b][k];
+        m.lambda = lambdas[b];
+        m.max_iters = max_iters;
+        m.tol = tol;
+        spt_status st = eng.add(&m);
+        if (st != SPT_OK) return st;
+        if (max_iters == 0) m.done = true;
+    }
+    while (eng.any_active()) {
+        spt_status st = eng.step();
+        if (st != SPT_OK) return st;
+        for (int b = 0; b < count; ++b)
+            if (mem[b].err != SPT_OK) return mem[b].err;
+    }
+    for (int b = 0; b < count; ++b) {
+        fits[b] = mem[b].fit;
+        iters[b] = mem[b].iters;
+    }
+    return SPT_OK;
+}
+
+}  // extern "C"

@@ -90,24 +90,113 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restri
             }
 }
 
-// G[p][q] = sum over chunks (upper block triangle mirrored), deterministic order.
-__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double *__restrict__ work, int nchunks, int R,
-                                                          double *__restrict__ G) {
-    const int nb = (R + 15) / 16, ld = nb * 16;
-    for (int e = blockIdx.x * kThreads + threadIdx.x; e < R * R; e += gridDim.x * kThreads) {
+// Batched Gram: one workgroup of 8 waves per item.  Wave w takes row groups
+// of 4 rows [4 (w UNR + 8 UNR j), ...), accumulates every 16x16 block tile
+// (pb <= qb) with FP64 MFMA, and the waves add their tiles into LDS in wave
+// order (deterministic); columns at or beyond the item's rank read as 0.
+constexpr int kGramBThreads = 512;
+template <int NB, int UNR>
+__global__ __launch_bounds__(kGramBThreads) void k_gram_batched(const GramItem *__restrict__ items) {
+    constexpr int NT = NB * (NB + 1) / 2, LDP = NB * 16, NWAVE = kGramBThreads / 64;
+    __shared__ double red[LDP * LDP];
+    const GramItem &it = items[blockIdx.x];
+    const float *__restrict__ C = it.C;
+    const int64_t rows = it.rows;
+    const int ld = it.ld, R = it.rank;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kr = lane >> 4, cc = lane & 15;
+    double4_t acc[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int64_t g0 = (int64_t)wave * UNR; g0 * 4 < rows; g0 += (int64_t)NWAVE * UNR) {
+        double v[UNR][NB];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t row = (g0 + u) * 4 + kr;
+            const bool rok = row < rows;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int c = b * 16 + cc;
+                v[u][b] = (rok && c < R) ? (double)C[row * ld + c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            int t = 0;
+#pragma unroll
+            for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+                for (int qb = pb; qb < NB; ++qb, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][pb], v[u][qb], acc[t], 0, 0, 0);
+        }
+    }
+    for (int w = 0; w < NWAVE; ++w) {
+        if (wave == w) {
+            int t = 0;
+#pragma unroll
+            for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+                for (int qb = pb; qb < NB; ++qb, ++t)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = 4 * e + (lane >> 4), n = lane & 15;
+                        double &d = red[(pb * 16 + m) * LDP + qb * 16 + n];
+                        d = (w == 0) ? acc[t][e] : d + acc[t][e];
+                    }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < R * R; e += kGramBThreads) {
         const int p = e / R, q = e % R;
         const int a = (p / 16 <= q / 16) ? p : q, b = (p / 16 <= q / 16) ? q : p;
-        double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += work[(size_t)c * ld * ld + (size_t)a * ld + b];
-        G[e] = s;
+        it.G[e] = red[a * LDP + b];
     }
+}
+
+// G[p][q] = sum over slices (upper block triangle mirrored), in two
+// deterministic stages: kGramSplit groups of slices, then the groups.
+constexpr int kGramSplit = 64;
+
+__device__ __forceinline__ size_t gram_upper(int e, int R, int ld) {
+    const int p = e / R, q = e % R;
+    const int a = (p / 16 <= q / 16) ? p : q, b = (p / 16 <= q / 16) ? q : p;
+    return (size_t)a * ld + b;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gram_reduce1(const double *__restrict__ work, int nslices, int R,
+                                                           double *__restrict__ w2) {
+    const int nb = (R + 15) / 16, ld = nb * 16;
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= R * R) return;
+    const int y = blockIdx.y, S = gridDim.y;
+    const int c0 = (int)((int64_t)nslices * y / S), c1 = (int)((int64_t)nslices * (y + 1) / S);
+    const size_t off = gram_upper(e, R, ld), stride = (size_t)ld * ld;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int c = c0;
+    for (; c + 4 <= c1; c += 4) {
+        s0 += work[(size_t)c * stride + off];
+        s1 += work[(size_t)(c + 1) * stride + off];
+        s2 += work[(size_t)(c + 2) * stride + off];
+        s3 += work[(size_t)(c + 3) * stride + off];
+    }
+    for (; c < c1; ++c) s0 += work[(size_t)c * stride + off];
+    w2[(size_t)y * R * R + e] = (s0 + s1) + (s2 + s3);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restrict__ w2, int S, int R,
+                                                           double *__restrict__ G) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= R * R) return;
+    double s = 0.0;
+    for (int y = 0; y < S; ++y) s += w2[(size_t)y * R * R + e];
+    G[e] = s;
 }
 
 // ------------------------------------------------------------------ solve preparation
 // One workgroup; R <= 64.  LDS: two R x R FP64 matrices.
-__global__ __launch_bounds__(kThreads) void k_solve_prep(const double *__restrict__ grams, int nmodes, int mode, int R,
-                                                         const double *__restrict__ gram_m, double *__restrict__ S,
-                                                         double *__restrict__ lambda, int *__restrict__ status) {
+__device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
+                                                const double *__restrict__ gram_m, double *__restrict__ S,
+                                                double *__restrict__ lambda, int *__restrict__ status) {
     __shared__ double A[64 * 64];
     __shared__ double B[64 * 64];
     __shared__ double sdiag;
@@ -201,13 +290,24 @@ __global__ __launch_bounds__(kThreads) void k_solve_prep(const double *__restric
     if (tid == 0) *status = attempt;
 }
 
+__global__ __launch_bounds__(kThreads) void k_solve_prep(const double *__restrict__ grams, int nmodes, int mode, int R,
+                                                         const double *__restrict__ gram_m, double *__restrict__ S,
+                                                         double *__restrict__ lambda, int *__restrict__ status) {
+    solve_prep_body(grams, nmodes, mode, R, gram_m, S, lambda, status);
+}
+
+__global__ __launch_bounds__(kThreads) void k_solve_prep_batched(const SolveItem *__restrict__ items, int mode) {
+    const SolveItem &it = items[blockIdx.x];
+    solve_prep_body(it.grams, it.nmodes, mode, it.rank, it.gram_m, it.S, it.lambda, it.status + mode);
+}
+
 // ------------------------------------------------------------------ apply
 // RP = R padded to 16/32/64; CG = RP/4 column groups of 4; RG = 256/CG row groups of 4 rows.
 template <int RP>
-__global__ __launch_bounds__(kThreads) void k_apply(const float *__restrict__ M, int64_t rows, int R,
-                                                    const double *__restrict__ S, float *__restrict__ C,
-                                                    const double *__restrict__ lambda,
-                                                    double *__restrict__ inner_partials) {
+__device__ __forceinline__ void apply_body(const float *__restrict__ M, int ldm, int64_t rows, int R,
+                                           const double *__restrict__ S, float *__restrict__ C,
+                                           const double *__restrict__ lambda, double *__restrict__ inner_partials,
+                                           int64_t blk) {
     constexpr int CG = RP / 4, RG = kThreads / CG, RW = RG * 4;
     __shared__ double sS[RP * RP];
     __shared__ float sM[RW * RP];
@@ -217,11 +317,11 @@ __global__ __launch_bounds__(kThreads) void k_apply(const float *__restrict__ M,
         const int p = e / RP, q = e % RP;
         sS[e] = (p < R && q < R) ? S[p * R + q] : 0.0;
     }
-    const int64_t row0 = (int64_t)blockIdx.x * RW;
+    const int64_t row0 = blk * RW;
     for (int e = tid; e < RW * RP; e += kThreads) {
         const int r = e / RP, c = e % RP;
         const int64_t row = row0 + r;
-        sM[e] = (row < rows && c < R) ? M[row * R + c] : 0.f;
+        sM[e] = (row < rows && c < R) ? M[row * ldm + c] : 0.f;
     }
     __syncthreads();
     const int cg = tid % CG, rg = tid / CG;
@@ -263,8 +363,30 @@ __global__ __launch_bounds__(kThreads) void k_apply(const float *__restrict__ M,
         for (int off = 32; off > 0; off >>= 1) inner += __shfl_down(inner, off, 64);
         if ((tid & 63) == 0) red[tid >> 6] = inner;
         __syncthreads();
-        if (tid == 0) inner_partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        if (tid == 0) inner_partials[blk] = red[0] + red[1] + red[2] + red[3];
     }
+}
+
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_apply(const float *__restrict__ M, int64_t rows, int R,
+                                                    const double *__restrict__ S, float *__restrict__ C,
+                                                    const double *__restrict__ lambda,
+                                                    double *__restrict__ inner_partials) {
+    apply_body<RP>(M, R, rows, R, S, C, lambda, inner_partials, blockIdx.x);
+}
+
+// Batched: block `g` belongs to the last item whose first_block <= g.
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_apply_batched(const ApplyItem *__restrict__ items, int count) {
+    const int64_t g = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_block <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const ApplyItem &it = items[__builtin_amdgcn_readfirstlane(lo)];
+    apply_body<RP>(it.M, it.ldm, it.rows, it.rank, it.S, it.C, it.lambda, it.inner, g - it.first_block);
 }
 
 template <int RP>
@@ -273,10 +395,10 @@ int apply_rows_per_block() { return (kThreads / (RP / 4)) * 4; }
 int apply_rp(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
 
 // ------------------------------------------------------------------ fit
-__global__ __launch_bounds__(kThreads) void k_fit(const double *__restrict__ grams, int nmodes, int R,
-                                                  const double *__restrict__ lambda,
-                                                  const double *__restrict__ inner_partials, int nparts,
-                                                  double norm_x2, double *__restrict__ out) {
+__device__ __forceinline__ void fit_body(const double *__restrict__ grams, int nmodes, int R,
+                                         const double *__restrict__ lambda,
+                                         const double *__restrict__ inner_partials, int nparts, double norm_x2,
+                                         double *__restrict__ out) {
     __shared__ double red[2][4];
     const int tid = threadIdx.x;
     const int RR = R * R;
@@ -307,6 +429,18 @@ __global__ __launch_bounds__(kThreads) void k_fit(const double *__restrict__ gra
         out[1] = nxh;
         out[2] = inner;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fit(const double *__restrict__ grams, int nmodes, int R,
+                                                  const double *__restrict__ lambda,
+                                                  const double *__restrict__ inner_partials, int nparts,
+                                                  double norm_x2, double *__restrict__ out) {
+    fit_body(grams, nmodes, R, lambda, inner_partials, nparts, norm_x2, out);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fit_batched(const FitItem *__restrict__ items) {
+    const FitItem &it = items[blockIdx.x];
+    fit_body(it.grams, it.nmodes, it.rank, it.lambda, it.inner, it.nparts, it.norm_x2, it.out);
 }
 
 // out[1] must hold |Xhat|^2 from k_fit; writes out[0] (fit) and out[3] (residual^2).
@@ -344,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void k_fit_direct(const double *__restric
 
 size_t gram_work_bytes(int64_t rows, int rank) {
     const int ld = gram_nb(rank) * 16;
-    return (size_t)gram_chunks(rows, rank) * 4 * ld * ld * sizeof(double);
+    return (size_t)gram_chunks(rows, rank) * 4 * ld * ld * sizeof(double) + (size_t)kGramSplit * rank * rank * sizeof(double);
 }
 
 spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double *work, size_t work_bytes,
@@ -352,13 +486,17 @@ spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double
     if (rank > 64) return fail(SPT_E_INVALID_ARG, "gram: rank above 64");
     const int chunks = gram_chunks(rows, rank);
     if (gram_work_bytes(rows, rank) > work_bytes) return fail(SPT_E_INVALID_ARG, "gram: workspace too small");
-    const int nb = gram_nb(rank);
+    const int nb = gram_nb(rank), ld = nb * 16;
     if (nb == 1) hipLaunchKernelGGL((k_gram_partial<1, 4>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
     else if (nb == 2) hipLaunchKernelGGL((k_gram_partial<2, 4>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
     else if (nb == 3) hipLaunchKernelGGL((k_gram_partial<3, 2>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
     else hipLaunchKernelGGL((k_gram_partial<4, 2>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
-    int rb = (rank * rank + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(rb), dim3(kThreads), 0, s, work, chunks * 4, rank, G);
+    const int nslices = chunks * 4;
+    const int S = std::min(kGramSplit, nslices);
+    double *w2 = work + (size_t)nslices * ld * ld;
+    const int rb = (rank * rank + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_gram_reduce1, dim3(rb, S), dim3(kThreads), 0, s, work, nslices, rank, w2);
+    hipLaunchKernelGGL(k_gram_reduce2, dim3(rb), dim3(kThreads), 0, s, w2, S, rank, G);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
@@ -404,6 +542,47 @@ spt_status launch_fit(const double *grams, int nmodes, int rank, const double *l
 
 spt_status launch_fit_direct(const double *resid_partials, int nparts, double norm_x2, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_fit_direct, dim3(1), dim3(kThreads), 0, s, resid_partials, nparts, norm_x2, out);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_gram_batched(const GramItem *items, int count, int rmax, hipStream_t s) {
+    if (count == 0) return SPT_OK;
+    if (rmax > 64) return fail(SPT_E_INVALID_ARG, "gram: rank above 64");
+    const int nb = gram_nb(rmax);
+    if (nb == 1) hipLaunchKernelGGL((k_gram_batched<1, 4>), dim3(count), dim3(kGramBThreads), 0, s, items);
+    else if (nb == 2) hipLaunchKernelGGL((k_gram_batched<2, 4>), dim3(count), dim3(kGramBThreads), 0, s, items);
+    else if (nb == 3) hipLaunchKernelGGL((k_gram_batched<3, 2>), dim3(count), dim3(kGramBThreads), 0, s, items);
+    else hipLaunchKernelGGL((k_gram_batched<4, 2>), dim3(count), dim3(kGramBThreads), 0, s, items);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_solve_prep_batched(const SolveItem *items, int count, int mode, hipStream_t s) {
+    if (count == 0) return SPT_OK;
+    hipLaunchKernelGGL(k_solve_prep_batched, dim3(count), dim3(kThreads), 0, s, items, mode);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+int apply_rows_per_launch_block(int rmax) {
+    const int rp = apply_rp(rmax);
+    return rp == 16 ? apply_rows_per_block<16>() : (rp == 32 ? apply_rows_per_block<32>() : apply_rows_per_block<64>());
+}
+
+spt_status launch_apply_batched(const ApplyItem *items, int count, int64_t total_blocks, int rmax, hipStream_t s) {
+    if (total_blocks == 0) return SPT_OK;
+    const int rp = apply_rp(rmax);
+    if (rp == 16) hipLaunchKernelGGL(k_apply_batched<16>, dim3((unsigned)total_blocks), dim3(kThreads), 0, s, items, count);
+    else if (rp == 32) hipLaunchKernelGGL(k_apply_batched<32>, dim3((unsigned)total_blocks), dim3(kThreads), 0, s, items, count);
+    else hipLaunchKernelGGL(k_apply_batched<64>, dim3((unsigned)total_blocks), dim3(kThreads), 0, s, items, count);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_fit_batched(const FitItem *items, int count, hipStream_t s) {
+    if (count == 0) return SPT_OK;
+    hipLaunchKernelGGL(k_fit_batched, dim3(count), dim3(kThreads), 0, s, items);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

@@ -297,59 +297,6 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs a, int64_t ntile
     walk_tile<G, VEC, NB, NMAX, REGROUP>(a, L, cnt);
 }
 
-// ------------------------------------------------------------------ batched
-// Walk variants a batched launch can meet (ranks <= 64).
-template <int NMAX, bool REGROUP>
-__device__ __forceinline__ void walk_any(const MttkrpArgs &a, const TileLds &L, int cnt) {
-    const int R = a.rank;
-    if ((R & 3) == 0) {
-        const int r4 = R >> 2;
-        if (r4 <= 1) walk_tile<1, 4, 1, NMAX, REGROUP>(a, L, cnt);
-        else if (r4 <= 2) walk_tile<2, 4, 1, NMAX, REGROUP>(a, L, cnt);
-        else if (r4 <= 4) walk_tile<4, 4, 1, NMAX, REGROUP>(a, L, cnt);
-        else if (r4 <= 8) walk_tile<8, 4, 1, NMAX, REGROUP>(a, L, cnt);
-        else walk_tile<16, 4, 1, NMAX, REGROUP>(a, L, cnt);
-    } else {
-        walk_tile<64, 1, 1, NMAX, REGROUP>(a, L, cnt);
-    }
-}
-
-template <int NMAX>
-__global__ __launch_bounds__(kThreads) void k_mttkrp_batched(const BatchItem *__restrict__ items, int count,
-                                                             int64_t total_tiles, unsigned long long *counter) {
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[4];
-    __shared__ long long s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
-        const int64_t it = s_item;
-        __syncthreads();
-        if (it >= total_tiles) break;  // every workgroup reaches this once the counter passes the end
-        // the tensor owning tile `it`: last item whose first_tile <= it
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].first_tile <= it) lo = mid;
-            else hi = mid - 1;
-        }
-        const int b = __builtin_amdgcn_readfirstlane(lo);
-        const MttkrpArgs &a = items[b].a;
-        const int strategy = items[b].strategy;
-        const int64_t tile = it - items[b].first_tile;
-        const TileLds L = carve(lds, a.tile, NMAX);
-        const CodecRegs cr = load_codec_regs(a.codec);
-        if (strategy == SPT_STRATEGY_REGROUP) {
-            const int cnt = stage_tile<NMAX, true>(a, tile, L, a.mode, wsum, cr);
-            walk_any<NMAX, true>(a, L, cnt);
-        } else {
-            const int cnt = stage_tile<NMAX, false>(a, tile, L, a.mode, wsum, cr);
-            walk_any<NMAX, false>(a, L, cnt);
-        }
-        __syncthreads();  // LDS is reused by the next item
-    }
-}
-
 // ------------------------------------------------------------------ direct residual
 // partials[2*b] = sum over the tile of (v - xhat)^2, partials[2*b+1] = sum xhat^2 (FP64),
 // xhat = sum_r lambda_r prod_k C^(k)[i_k, r].
@@ -508,24 +455,6 @@ spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s) {
     const bool regroup = strategy == SPT_STRATEGY_REGROUP;
     if (a.nmodes <= 4) return launch_nmax<4>(a, regroup, ntiles, s);
     return launch_nmax<8>(a, regroup, ntiles, s);
-}
-
-spt_status launch_mttkrp_batched(const BatchItem *items_dev, int count, int64_t total_tiles, int nmodes_max,
-                                 int *counter_dev, hipStream_t s) {
-    if (total_tiles == 0) return SPT_OK;
-    // enough resident workgroups to fill the chip; each loops until the counter passes the end
-    int64_t g = total_tiles < 2048 ? total_tiles : 2048;
-    if (nmodes_max <= 4) {
-        const size_t lds = tile_lds_bytes(1024, 4, true);
-        hipLaunchKernelGGL(k_mttkrp_batched<4>, dim3((unsigned)g), dim3(kThreads), lds, s, items_dev, count, total_tiles,
-                           (unsigned long long *)counter_dev);
-    } else {
-        const size_t lds = tile_lds_bytes(1024, 8, true);
-        hipLaunchKernelGGL(k_mttkrp_batched<8>, dim3((unsigned)g), dim3(kThreads), lds, s, items_dev, count, total_tiles,
-                           (unsigned long long *)counter_dev);
-    }
-    SPT_HIP(hipGetLastError());
-    return SPT_OK;
 }
 
 spt_status launch_resid(const MttkrpArgs &a, const double *lam, double *partials, int nparts, hipStream_t s) {

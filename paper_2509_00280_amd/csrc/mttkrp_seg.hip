@@ -185,19 +185,14 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
     __syncthreads();
 }
 
+// Walk the staged tile: every piece becomes record rbase + piece of
+// ld floats (columns R..ld-1 zero) whose row is row_base + the piece's row.
 template <int NT, int G, int VEC, int NB, int NMAX>
-__global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles) {
+__device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, uint64_t *__restrict__ rec_row,
+                                         float *__restrict__ rec_val, int64_t rbase, int ld, int64_t row_base) {
     constexpr int T = 4 * NT;
     constexpr int UB = kUnroll;
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[NT / 64];
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const SegLds L = seg_carve(lds, T, a.nmodes);
-    const CodecRegs cr = load_codec_regs(a.codec);
-    seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
     const int npieces = (int)(L.hcnt[T] & 0xFFFFu);
-    const int64_t rbase = a.rec_off[tile];
     const int j = threadIdx.x % G;
     const int R = a.rank, mode = a.mode, nm = a.nmodes;
     for (int k = threadIdx.x / G; k < npieces; k += NT / G) {
@@ -261,13 +256,14 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles)
                     for (int v = 0; v < VEC; ++v) acc[b][v] += p[u][b][v];
         }
         const int64_t pos = rbase + k;
-        if (j == 0) a.rec_row[pos] = (uint64_t)L.hkey[s];
-        float *o = a.rec_val + pos * R;
+        if (j == 0) rec_row[pos] = (uint64_t)(row_base + L.hkey[s]);
+        float *o = rec_val + pos * ld;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int c = (b * G + j) * VEC;
-            if (c < R) {
+            if (c < ld) {
                 if constexpr (VEC == 4) {
+                    // columns at or beyond R were loaded as zero factors, so acc is 0 there
                     *reinterpret_cast<float4 *>(o + c) = make_float4(acc[b][0], acc[b][1], acc[b][2], acc[b][3]);
                 } else {
 #pragma unroll
@@ -276,6 +272,50 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles)
             }
         }
     }
+}
+
+template <int NT, int G, int VEC, int NB, int NMAX>
+__global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles) {
+    constexpr int T = 4 * NT;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
+    seg_walk<NT, G, VEC, NB, NMAX>(a, L, a.rec_row, a.rec_val, a.rec_off[tile], a.rank, 0);
+}
+
+// Batched: tile `it` of the whole batch belongs to the last item whose
+// first_tile <= it; records go to the batch's arrays at the item's base.
+__device__ __forceinline__ int seg_item_of(const SegItem *__restrict__ items, int count, int64_t it) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_tile <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+template <int NT, int G, int VEC, int NB, int NMAX>
+__global__ __launch_bounds__(NT) void k_mttkrp_seg_batched(const SegItem *__restrict__ items, int count,
+                                                           int64_t total_tiles, uint64_t *__restrict__ rec_row,
+                                                           float *__restrict__ rec_val, int ld) {
+    constexpr int T = 4 * NT;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t it = xcd_remap(blockIdx.x, gridDim.x);
+    if (it >= total_tiles) return;
+    const int b = seg_item_of(items, count, it);
+    const SegItem &item = items[b];
+    const MttkrpArgs &a = item.a;
+    const int64_t tile = it - item.first_tile;
+    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
+    seg_walk<NT, G, VEC, NB, NMAX>(a, L, rec_row, rec_val, item.rec_base + a.rec_off[tile], ld, item.row_base);
 }
 
 // Pieces of every tile (the plan's counting pass).
@@ -289,6 +329,21 @@ __global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntile
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
     if (threadIdx.x == 0) out[tile] = L.hcnt[T] & 0xFFFFu;
+}
+
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__restrict__ items, int count,
+                                                             int64_t total_tiles, int64_t *__restrict__ out) {
+    constexpr int T = 4 * NT;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t it = blockIdx.x;
+    const int b = seg_item_of(items, count, it);
+    const MttkrpArgs &a = items[b].a;
+    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    seg_stage<NT, NMAX, false>(a, it - items[b].first_tile, L, cr, wsum);
+    if (threadIdx.x == 0) out[it] = L.hcnt[T] & 0xFFFFu;
 }
 
 template <int NT, int NMAX, int G, int VEC, int NB>
@@ -354,6 +409,57 @@ spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
     if (a.tile == 1024) return n4 ? launch_seg_nt<256, 4>(a, ntiles, s) : launch_seg_nt<256, 8>(a, ntiles, s);
     if (a.tile == 2048) return n4 ? launch_seg_nt<512, 4>(a, ntiles, s) : launch_seg_nt<512, 8>(a, ntiles, s);
     return n4 ? launch_seg_nt<1024, 4>(a, ntiles, s) : launch_seg_nt<1024, 8>(a, ntiles, s);
+}
+
+namespace {
+template <int NMAX, int G, int VEC, int NB>
+spt_status launch_segb_k(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
+                         int ld, hipStream_t s) {
+    constexpr int NT = kBatchTile / 4;
+    const size_t lds = seg_lds_bytes(kBatchTile, NMAX);
+    hipLaunchKernelGGL((k_mttkrp_seg_batched<NT, G, VEC, NB, NMAX>), dim3((unsigned)total_tiles), dim3(NT), lds, s,
+                       items, count, total_tiles, rec_row, rec_val, ld);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+template <int NMAX>
+spt_status launch_segb_n(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
+                         int ld, bool vec4, hipStream_t s) {
+    if (vec4) {
+        const int r4 = ld >> 2;
+        if (r4 <= 1) return launch_segb_k<NMAX, 1, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 2) return launch_segb_k<NMAX, 2, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 4) return launch_segb_k<NMAX, 4, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 8) return launch_segb_k<NMAX, 8, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        return launch_segb_k<NMAX, 16, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+    }
+    return launch_segb_k<NMAX, 64, 1, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+}
+}  // namespace
+
+bool seg_batch_fits(int nmodes_max) { return seg_lds_bytes(kBatchTile, nmodes_max) <= 160 * 1024 - 1024; }
+
+spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+                                       int64_t *counts, hipStream_t s) {
+    if (total_tiles == 0) return SPT_OK;
+    constexpr int NT = kBatchTile / 4;
+    if (nmodes_max <= 4)
+        hipLaunchKernelGGL((k_count_pieces_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT),
+                           seg_lds_bytes(kBatchTile, 4), s, items, count, total_tiles, counts);
+    else
+        hipLaunchKernelGGL((k_count_pieces_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
+                           seg_lds_bytes(kBatchTile, 8), s, items, count, total_tiles, counts);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int ld,
+                                     bool vec4, uint64_t *rec_row, float *rec_val, hipStream_t s) {
+    if (total_tiles == 0) return SPT_OK;
+    if (ld > 64 || (vec4 && (ld & 3))) return fail(SPT_E_INVALID_ARG, "batched MTTKRP: rank above 64");
+    if (nmodes_max <= 4) return launch_segb_n<4>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
+    return launch_segb_n<8>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
 }
 
 }  // namespace spt

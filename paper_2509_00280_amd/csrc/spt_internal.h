@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "spt.h"  // include/ is on the include path
 
@@ -83,6 +84,9 @@ struct Tensor {
     double norm_x2 = 0.0;
     spt_plan plan{};
     ModePlan mplan[kMaxModes];
+    // batched SEGMENT plan per mode (tiles of kBatchTile): per-tile record offsets
+    int64_t *bseg_off[kMaxModes] = {};
+    int64_t bseg_records[kMaxModes] = {};
     void *ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
 };
@@ -135,15 +139,167 @@ bool seg_tile_ok(int tile, int nmodes);
 spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 
-// Per-tensor descriptor of the batched persistent MTTKRP.
-struct BatchItem {
-    MttkrpArgs a;
-    int64_t first_tile;  // prefix sum of tiles over the batch
-    int strategy;
-    int pad;
+// Batched SEGMENT MTTKRP: every tensor's tiles of kBatchTile nonzeros in one
+// launch; records carry global rows (row_base + row) of the batch's
+// concatenated output and are written at rec_base + the tile's offset.
+constexpr int kBatchTile = 2048;
+struct SegItem {
+    MttkrpArgs a;        // a.rec_off: the tensor's per-tile record offsets for this mode
+    int64_t first_tile;  // prefix of tiles over the batch
+    int64_t rec_base;    // first record of this tensor
+    int64_t row_base;    // first row of this tensor in the concatenated output
 };
-spt_status launch_mttkrp_batched(const BatchItem *items_dev, int count, int64_t total_tiles,
-                                 int nmodes_max, int *counter_dev, hipStream_t s);
+bool seg_batch_fits(int nmodes_max);
+spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+                                       int64_t *counts, hipStream_t s);
+spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int ld,
+                                     bool vec4, uint64_t *rec_row, float *rec_val, hipStream_t s);
+
+// Batched dense steps (dense.hip): one workgroup per item, except apply
+// (a grid over the items' row blocks).
+struct GramItem {
+    const float *C;   // rows x rank, leading dimension ld
+    int64_t rows;
+    int ld, rank;
+    double *G;        // rank x rank (out)
+};
+struct SolveItem {
+    const double *grams;  // nmodes x rank x rank
+    const double *gram_m; // rank x rank Gram of the MTTKRP output
+    double *S, *lambda;
+    int *status;          // nmodes entries; entry `mode` is written
+    int nmodes, rank;
+};
+struct ApplyItem {
+    const float *M;       // rows x rank, leading dimension ldm
+    const double *S;
+    float *C;             // rows x rank (out)
+    const double *lambda;
+    double *inner;        // per-block inner-product partials, or null
+    int64_t rows, first_block;
+    int ldm, rank;
+};
+struct FitItem {
+    const double *grams, *lambda, *inner;
+    double *out;          // 4 doubles: fit, |Xhat|^2, <X, Xhat>, residual^2
+    double norm_x2;
+    int nmodes, rank, nparts, pad;
+};
+spt_status launch_gram_batched(const GramItem *items, int count, int rmax, hipStream_t s);
+spt_status launch_solve_prep_batched(const SolveItem *items, int count, int mode, hipStream_t s);
+int apply_rows_per_launch_block(int rmax);
+spt_status launch_apply_batched(const ApplyItem *items, int count, int64_t total_blocks, int rmax, hipStream_t s);
+spt_status launch_fit_batched(const FitItem *items, int count, hipStream_t s);
+
+// batch.cpp: lock-step CP-ALS of many tensors.
+struct Member {
+    Tensor *t = nullptr;
+    int R = 0;
+    float *F[kMaxModes] = {};   // device factors (in: initial, out: normalised)
+    double *lambda = nullptr;   // device, R doubles
+    int max_iters = 0;
+    double tol = 0.0;
+    // results
+    double fit = 0.0, fit_prev = 0.0;
+    int iters = 0;
+    bool done = false;
+    spt_status err = SPT_OK;
+    // engine-owned device state: Grams of every mode, Gram of M, solve matrix
+    bool fresh = true;
+    void *state = nullptr;
+    double *grams = nullptr, *gram_m = nullptr, *S = nullptr;
+    void *user = nullptr;
+};
+
+struct ModeItems {
+    int count = 0, ld = 0, rmax = 0;
+    bool vec4 = true;
+    int64_t tiles = 0, records = 0, rows = 0, blocks = 0;
+    size_t seg_off = 0, gm_off = 0, sv_off = 0, ap_off = 0, gc_off = 0;
+    std::vector<int> member_idx;
+    std::vector<SegItem> seg_v;
+    std::vector<GramItem> gm_v, gc_v;
+    std::vector<SolveItem> sv_v;
+    std::vector<ApplyItem> ap_v;
+};
+
+// Grow-only device buffer (synchronises the stream before replacing).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void *get(size_t need, hipStream_t s) {
+        if (need <= bytes && p) return p;
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        need = need < 256 ? 256 : need;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return nullptr;
+        }
+        bytes = need;
+        return p;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+// record and sort buffers of the batched MTTKRP
+struct BatchMttkrpWs {
+    DevBuf rec_row, rec_val, keys2, ia, ib, cnt;
+    void release() {
+        rec_row.release(); rec_val.release(); keys2.release(); ia.release(); ib.release(); cnt.release();
+    }
+};
+spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_max,
+                                   int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
+                                   BatchMttkrpWs &ws, hipStream_t s);
+spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s);
+
+class BatchEngine {
+public:
+    explicit BatchEngine(hipStream_t s);
+    ~BatchEngine();
+    BatchEngine(const BatchEngine &) = delete;
+    BatchEngine &operator=(const BatchEngine &) = delete;
+    // joins at the next step (computes the initial Grams then)
+    spt_status add(Member *m);
+    // leaves now (the stream is synchronised first)
+    void remove(Member *m);
+    // one CP-ALS iteration of every active member; synchronises the stream
+    spt_status step();
+    bool any_active() const;
+    const std::vector<Member *> &members() const { return members_; }
+
+private:
+    spt_status rebuild();
+    void release_buffers();
+    void free_member_state(Member *m);
+    hipStream_t s_;
+    std::vector<Member *> members_, active_;
+    bool dirty_ = true;
+    int nmodes_max_ = 0;
+    std::vector<ModeItems> modes_;
+    char *d_items_ = nullptr;
+    size_t items_bytes_ = 0, fit_off_ = 0, init_off_ = 0;
+    int init_count_ = 0, init_rmax_ = 0;
+    float *M_all_ = nullptr;
+    size_t M_bytes_ = 0;
+    double *fit_all_ = nullptr, *inner_all_ = nullptr, *resid_ = nullptr;
+    int *status_all_ = nullptr;
+    size_t fit_cap_ = 0, inner_cap_ = 0, resid_cap_ = 0;
+    std::vector<double> hfit_;
+    std::vector<int> hstat_;
+    BatchMttkrpWs ws_;
+};
+
 
 // mttkrp_table.hip: persistent-workgroup LDS accumulation (see that file).
 struct TableArgs {
@@ -191,3 +347,6 @@ spt_status launch_fit_direct(const double *resid_partials, int nparts, double no
 spt_status launch_sum_f64(const double *parts, int n, double *out, hipStream_t s);
 
 }  // namespace spt
+
+// The opaque handle of the C-ABI is the tensor itself.
+struct spt_tensor_s : spt::Tensor {};
