@@ -226,6 +226,13 @@ __global__ __launch_bounds__(kThreads) void k_gather_vals(const float *__restric
     if (threadIdx.x == 0) partials[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
+// out[j] = src[idx[j]] (32-bit words)
+__global__ __launch_bounds__(kThreads) void k_gather_u32(const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx,
+                                                         uint32_t *__restrict__ out, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads)
+        out[j] = src[idx[j]];
+}
+
 __global__ __launch_bounds__(kThreads) void k_decode(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
                                                      int64_t nnz, Codec codec, uint32_t *__restrict__ coords) {
     const CodecRegs cl = load_codec_regs(codec);
@@ -406,6 +413,13 @@ spt_status launch_decode(const Tensor *t, uint32_t *coords, hipStream_t s) {
     if (t->nnz == 0) return SPT_OK;
     hipLaunchKernelGGL(k_decode, dim3(grid_for(t->nnz, kThreads, 16384)), dim3(kThreads), 0, s, t->lo, t->hi, t->nnz,
                        t->codec, coords);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *out, int64_t n, hipStream_t s) {
+    if (n == 0) return SPT_OK;
+    hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(n, kThreads, 16384)), dim3(kThreads), 0, s, src, idx, out, n);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

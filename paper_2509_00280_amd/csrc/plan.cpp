@@ -65,6 +65,12 @@ bool priv_params(int nmodes, int64_t rows, int R, int max_pass, int *npass, int 
 
 }  // namespace
 
+// PRIV fits this mode with at most 2 column passes
+bool priv_feasible(const Tensor *t, int mode, int rank) {
+    int npass = 1, rs = rank, stride = rank + 1;
+    return priv_params(t->nmodes, t->dims[mode], rank, 2, &npass, &rs, &stride);
+}
+
 int device_cus() {
     static int cus[64] = {};
     int dev = 0;
@@ -102,6 +108,11 @@ void release_ws(Tensor *t) {
         t->ws[i] = nullptr;
         t->ws_bytes[i] = 0;
     }
+}
+
+void release_mode_plan(Tensor *t, int n) {
+    if (t->mplan[n].rec_off) (void)hipFree(t->mplan[n].rec_off);
+    t->mplan[n] = ModePlan{};
 }
 
 void release_plans(Tensor *t) {

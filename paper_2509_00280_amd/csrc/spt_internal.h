@@ -97,6 +97,10 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
 void release_plans(Tensor *t);
+// drop the cached plan of one mode (the next call at that mode plans again)
+void release_mode_plan(Tensor *t, int mode);
+bool seg_tile_ok(int tile, int nmodes);
+bool priv_feasible(const Tensor *t, int mode, int rank);
 // workspace slot of at least `bytes` (synchronises s before replacing a smaller buffer)
 void *tensor_ws(Tensor *t, int slot, size_t bytes, hipStream_t s);
 void release_ws(Tensor *t);
@@ -111,6 +115,7 @@ spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s);
 // Stable LSD radix sort of n 64-bit keys over their low nbits bits in
 // caller-owned buffers (see encode.hip).
 size_t sort_ws_counts(int64_t n);
+spt_status launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *out, int64_t n, hipStream_t s);
 spt_status sort_u64_keys_ws(uint64_t *keys, uint64_t *keys2, uint32_t *idx_a, uint32_t *idx_b, uint32_t *counts,
                             int64_t n, int nbits, uint64_t **sorted_out, uint32_t **idx_out, hipStream_t s);
 

@@ -276,6 +276,75 @@ def autotune(t: Tensor, factors, budget_ms: float = 2000.0, stream=None):
     return best.value
 
 
+class Server:
+    """Continuous-batching CP-ALS server (one per process and GPU is typical).
+
+    ``submit`` copies a COO tensor (host numpy arrays) and its initial factors
+    and returns a ticket; ``wait`` returns the result and, on success, the
+    normalised factors and lambda as numpy arrays.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        h = ctypes.c_void_p()
+        _check(lib().spt_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self._meta = {}
+
+    def submit(self, dims, coords, vals, init, max_iters: int, tol: float = 0.0) -> int:
+        import numpy as np
+        nm = len(dims)
+        coords = np.ascontiguousarray(coords, dtype=np.uint32)
+        vals = np.ascontiguousarray(vals, dtype=np.float32)
+        init = [np.ascontiguousarray(f, dtype=np.float32) for f in init]
+        rank = int(init[0].shape[1])
+        r = Request()
+        r.nmodes = nm
+        for k in range(nm):
+            r.dims[k] = int(dims[k])
+        r.nnz = int(vals.shape[0])
+        r.coords = coords.ctypes.data
+        r.vals = vals.ctypes.data
+        iptr = (ctypes.c_void_p * nm)(*[f.ctypes.data for f in init])
+        r.init = ctypes.cast(iptr, _PP)
+        r.rank = rank
+        r.max_iters = int(max_iters)
+        r.tol = float(tol)
+        ticket = ctypes.c_uint64()
+        _check(lib().spt_server_submit(self._h, ctypes.byref(r), ctypes.byref(ticket)))
+        self._meta[ticket.value] = (tuple(int(d) for d in dims), rank)
+        return ticket.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0, want_factors: bool = True):
+        import numpy as np
+        dims, rank = self._meta.get(ticket, ((), 0))
+        want_factors = want_factors and rank > 0
+        res = Result()
+        outs = [np.empty((d, rank), np.float32) for d in dims] if want_factors else None
+        lam = np.empty(rank, np.float64) if want_factors else None
+        fptr = (ctypes.c_void_p * len(dims))(*[o.ctypes.data for o in outs]) if want_factors else None
+        _check(lib().spt_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(res),
+                                     ctypes.cast(fptr, _PP) if fptr is not None else None,
+                                     lam.ctypes.data if lam is not None else None))
+        self._meta.pop(ticket, None)
+        out = {"status": res.status, "fit": res.fit, "iters": res.iters, "t_arrive": res.t_arrive,
+               "t_admit": res.t_admit, "t_done": res.t_done}
+        return out, outs, lam
+
+    def now(self) -> float:
+        return lib().spt_server_now(self._h)
+
+    def close(self):
+        if self._h is not None:
+            lib().spt_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def profile_reset(on: bool = True):
     """Clear recorded MTTKRP timings and (re)enable event timing."""
     _check(lib().spt_profile_enable(1 if on else 0))
