@@ -176,6 +176,138 @@ def summarize_profiles(d: str):
     print("\n".join(lines + [""] + out))
 
 
+def _upload(t):
+    import torch
+    c = torch.from_numpy(np.ascontiguousarray(t.coords).view(np.int32)).cuda()
+    v = torch.from_numpy(np.ascontiguousarray(t.vals)).cuda()
+    return c, v
+
+
+def bench_batch(args):
+    """256 independent tensors (3 or 4 modes, 1e4..5e6 nonzeros, Zipf(1.2)
+    labels, ranks 16/32): lock-step batched CP-ALS against the plain
+    per-tensor GPU CP-ALS, same iterations, same inputs."""
+    import torch
+    from paper_2509_00280_amd import spt, synth
+    t0 = time.time()
+    members = synth.batch_config(seed=4, count=args.batch_count)
+    log(f"generated {len(members)} tensors, {sum(t.nnz for t, _, _ in members)} nonzeros in {time.time() - t0:.1f} s")
+    hs = []
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    for t, F, R in members:
+        c, v = _upload(t)
+        hs.append(spt.encode(t.dims, c, v))
+    torch.cuda.synchronize()
+    t_enc = time.perf_counter() - te
+    iters = args.batch_iters
+    F0 = [[torch.from_numpy(f).cuda() for f in F] for _, F, _ in members]
+
+    def fresh():
+        return [[f.clone() for f in fl] for fl in F0]
+
+    # warm-up of both paths (plans, pools) on the first tensors
+    spt.cp_als_batched(hs[:4], fresh()[:4], 1)
+    for h, fl in zip(hs[:4], fresh()[:4]):
+        spt.cp_als(h, fl, 1)
+    torch.cuda.synchronize()
+    Fs = fresh()
+    ts = time.perf_counter()
+    fits_s = [spt.cp_als(h, fl, iters)[1] for h, fl in zip(hs, Fs)]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - ts
+    Fb = fresh()
+    tb = time.perf_counter()
+    _, fits_b, its_b = spt.cp_als_batched(hs, Fb, iters)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - tb
+    dfit = max(abs(a - b) for a, b in zip(fits_s, fits_b))
+    n = len(members)
+    out = {"metric": "CP-ALS solves/s (batched vs per-tensor)", "value": round(n / t_batch, 3), "unit": "solves/s",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32 MTTKRP, f64 solve",
+           "data": "synthetic",
+           "config": {"workload": f"{n} independent tensors, 3 or 4 modes, 1e4..5e6 nonzeros (log-uniform), "
+                                  f"Zipf(1.2) labels, ranks 16/32, {iters} CP-ALS iterations each",
+                      "total_nnz": int(sum(t.nnz for t, _, _ in members)), "iters": iters},
+           "batched_s": round(t_batch, 4), "per_tensor_s": round(t_single, 4),
+           "per_tensor_solves_per_s": round(n / t_single, 3), "speedup": round(t_single / t_batch, 3),
+           "encode_s": round(t_enc, 4), "max_abs_fit_diff": dfit}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Continuous batching: Poisson arrivals of CP-ALS requests (3 or 4 modes,
+    1e4..5e6 nonzeros, ranks 16..64, <= 50 iterations or |dfit| < 1e-4) at a
+    fraction of the saturated throughput; p50/p99 of done - arrive, against
+    the plain per-tensor GPU CP-ALS of the same requests."""
+    import threading
+    import torch
+    from paper_2509_00280_amd import spt, synth
+    t0 = time.time()
+    reqs = synth.serving_requests(seed=5, count=args.serve_count)
+    mats = [synth.materialize(r) for r in reqs]
+    log(f"generated {len(mats)} requests, {sum(t.nnz for t, _, _ in mats)} nonzeros in {time.time() - t0:.1f} s")
+    iters, tol = 50, 1e-4
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.5)
+    # plain per-tensor GPU CP-ALS (encode + solve, one request after another)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for t, F, R in mats:
+        c, v = _upload(t)
+        h = spt.encode(t.dims, c, v)
+        spt.cp_als(h, [torch.from_numpy(f).cuda() for f in F], iters, tol=tol)
+        h.free()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - tp
+    # saturated server throughput: every request submitted at once
+    srv = spt.Server(budget, args.serve_slots)
+    ts = time.perf_counter()
+    tickets = [srv.submit(t.dims, t.coords, t.vals, F, iters, tol) for t, F, R in mats]
+    res = [srv.wait(k, want_factors=False)[0] for k in tickets]
+    t_sat = time.perf_counter() - ts
+    srv.close()
+    sat = len(mats) / t_sat
+    bad = sum(r["status"] != 0 for r in res)
+    # open loop: Poisson arrivals at `load` x the saturated rate
+    lat = {}
+    for load in args.serve_loads:
+        rate = load * sat
+        gaps = np.random.default_rng(55).exponential(1.0 / rate, size=len(mats))
+        arrive = np.cumsum(gaps)
+        srv = spt.Server(budget, args.serve_slots)
+        tks = [None] * len(mats)
+
+        def submitter():
+            base = srv.now()
+            for i, (t, F, R) in enumerate(mats):
+                d = base + arrive[i] - srv.now()
+                if d > 0:
+                    time.sleep(d)
+                tks[i] = srv.submit(t.dims, t.coords, t.vals, F, iters, tol)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        rs = [srv.wait(k, want_factors=False)[0] for k in tks]
+        srv.close()
+        d = np.array([r["t_done"] - r["t_arrive"] for r in rs])
+        q = np.array([r["t_admit"] - r["t_arrive"] for r in rs])
+        span = max(r["t_done"] for r in rs) - min(r["t_arrive"] for r in rs)
+        lat[str(load)] = {"p50_s": round(float(np.percentile(d, 50)), 4), "p99_s": round(float(np.percentile(d, 99)), 4),
+                          "queue_p50_s": round(float(np.percentile(q, 50)), 4), "solves_per_s": round(len(rs) / span, 3),
+                          "errors": int(sum(r["status"] != 0 for r in rs))}
+    out = {"metric": "served CP-ALS solves/s and latency", "value": round(sat, 3), "unit": "solves/s",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32 MTTKRP, f64 solve",
+           "data": "synthetic",
+           "config": {"workload": f"{len(mats)} requests, 3 or 4 modes, 1e4..5e6 nonzeros (log-uniform), Zipf(1.2), "
+                                  f"ranks 16/32/48/64, <= {iters} iterations or |dfit| < {tol}",
+                      "hbm_budget_bytes": budget, "slots": args.serve_slots},
+           "saturated_solves_per_s": round(sat, 3), "plain_per_tensor_solves_per_s": round(len(mats) / t_plain, 3),
+           "speedup_vs_plain": round(t_plain / t_sat, 3), "errors": bad, "open_loop": lat}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +315,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nnz", type=float, default=None, help="scale the tensor down (debug only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("ratings", "batch", "serve"), default="ratings",
+                    help="ratings: the headline MTTKRP benchmark; batch: batched vs per-tensor CP-ALS; "
+                         "serve: continuous-batching server latency")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-iters", type=int, default=10)
+    ap.add_argument("--serve-count", type=int, default=120)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-loads", type=float, nargs="*", default=[0.5, 0.8])
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 CSV output under DIR (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -205,6 +345,12 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
+        return
 
     import torch
     from paper_2509_00280_amd import spt, synth

@@ -284,6 +284,35 @@ spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
     return SPT_OK;
 }
 
+}  // extern "C"
+
+namespace spt {
+// Release a handle after its last use on stream s without a device-wide
+// sync: the encoding and batched plans are stream-ordered allocations.
+void tensor_release(Tensor *t, hipStream_t s) {
+    if (!t) return;
+    bool host_sync = false;
+    for (int n = 0; n < kMaxModes; ++n) host_sync |= t->mplan[n].rec_off != nullptr;
+    for (int i = 0; i < WS_NSLOTS; ++i) host_sync |= t->ws[i] != nullptr;
+    if (host_sync) {
+        (void)hipStreamSynchronize(s);
+        for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n);
+        release_ws(t);
+    }
+    for (int n = 0; n < kMaxModes; ++n) {
+        dev_free(t->bseg_off[n], s);
+        t->bseg_off[n] = nullptr;
+    }
+    dev_free(t->lo, s);
+    dev_free(t->hi, s);
+    dev_free(t->vals, s);
+    dev_free(t->perm, s);
+    delete static_cast<spt_tensor_s *>(t);
+}
+}  // namespace spt
+
+extern "C" {
+
 void spt_tensor_free(spt_tensor t) {
     if (!t) return;
     // the handle's buffers were allocated stream-ordered; release them on the null

@@ -56,12 +56,12 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         nmax = std::max(nmax, need[i]->nmodes);
     }
     if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "batch: too many modes for the batched tile");
-    SegItem *d_items = nullptr;
-    int64_t *d_cnt = nullptr;
-    SPT_HIP(hipMalloc(&d_items, sizeof(SegItem) * items.size()));
-    if (hipMalloc(&d_cnt, sizeof(int64_t) * std::max<int64_t>(tiles, 1)) != hipSuccess) {
-        (void)hipFree(d_items);
-        return hip_fail(hipGetLastError(), "batch plan: counts");
+    SegItem *d_items = (SegItem *)dev_alloc(sizeof(SegItem) * items.size(), s);
+    int64_t *d_cnt = (int64_t *)dev_alloc(sizeof(int64_t) * std::max<int64_t>(tiles, 1), s);
+    if (!d_items || !d_cnt) {
+        dev_free(d_items, s);
+        dev_free(d_cnt, s);
+        return fail(SPT_E_OOM, "batch plan: counts");
     }
     std::vector<int64_t> h(std::max<int64_t>(tiles, 1), 0);
     spt_status st = SPT_OK;
@@ -72,28 +72,32 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         hipMemcpyAsync(h.data(), d_cnt, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s) != hipSuccess)
         st = hip_fail(hipGetLastError(), "batch plan: readback");
     if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "batch plan: sync");
-    (void)hipFree(d_items);
-    (void)hipFree(d_cnt);
+    dev_free(d_items, s);
+    dev_free(d_cnt, s);
     if (st != SPT_OK) return st;
+    std::vector<std::vector<int64_t>> offs(need.size());
     for (size_t i = 0; i < need.size(); ++i) {
         Tensor *t = need[i];
         const int64_t nt = (t->nnz + kBatchTile - 1) / kBatchTile;
-        std::vector<int64_t> off(nt + 1, 0);
+        std::vector<int64_t> &off = offs[i];
+        off.assign(nt + 1, 0);
         int64_t run = 0;
         for (int64_t k = 0; k < nt; ++k) {
             off[k] = run;
             run += h[items[i].first_tile + k];
         }
         off[nt] = run;
-        int64_t *d = nullptr;
-        SPT_HIP(hipMalloc(&d, sizeof(int64_t) * (nt + 1)));
-        if (hipMemcpy(d, off.data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(d);
+        // stream-ordered, so releasing the tensor later needs no device-wide sync
+        int64_t *d = (int64_t *)dev_alloc(sizeof(int64_t) * (nt + 1), s);
+        if (!d) return fail(SPT_E_OOM, "batch plan: offsets");
+        if (hipMemcpyAsync(d, off.data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, s) != hipSuccess) {
+            dev_free(d, s);
             return hip_fail(hipGetLastError(), "batch plan: offsets");
         }
         t->bseg_off[mode] = d;
         t->bseg_records[mode] = run;
     }
+    SPT_HIP(hipStreamSynchronize(s));  // host offsets are read by the copies above
     return SPT_OK;
 }
 
@@ -144,7 +148,7 @@ void BatchEngine::release_buffers() {
 }
 
 void BatchEngine::free_member_state(Member *m) {
-    if (m->state) (void)hipFree(m->state);
+    dev_free(m->state, s_);  // stream-ordered after the member's last kernels
     m->state = nullptr;
 }
 
@@ -156,7 +160,8 @@ spt_status BatchEngine::add(Member *m) {
     if (st != SPT_OK) return st;
     const int N = t->nmodes, R = m->R;
     const size_t bytes = sizeof(double) * ((size_t)N * R * R + 2 * (size_t)R * R);
-    SPT_HIP(hipMalloc(&m->state, bytes));
+    m->state = dev_alloc(bytes, s_);
+    if (!m->state) return fail(SPT_E_OOM, "batch: member state");
     m->grams = (double *)m->state;
     m->gram_m = m->grams + (size_t)N * R * R;
     m->S = m->gram_m + (size_t)R * R;
@@ -173,7 +178,6 @@ spt_status BatchEngine::add(Member *m) {
 void BatchEngine::remove(Member *m) {
     auto it = std::find(members_.begin(), members_.end(), m);
     if (it == members_.end()) return;
-    (void)hipStreamSynchronize(s_);
     free_member_state(m);
     members_.erase(it);
     dirty_ = true;

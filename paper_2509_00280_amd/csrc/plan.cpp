@@ -119,7 +119,7 @@ void release_plans(Tensor *t) {
     for (int n = 0; n < kMaxModes; ++n) {
         if (t->mplan[n].rec_off) (void)hipFree(t->mplan[n].rec_off);
         t->mplan[n] = ModePlan{};
-        if (t->bseg_off[n]) (void)hipFree(t->bseg_off[n]);
+        dev_free(t->bseg_off[n], nullptr);  // callers order this after the tensor's last use
         t->bseg_off[n] = nullptr;
         t->bseg_records[n] = 0;
     }

@@ -103,13 +103,13 @@ struct spt_server_s {
         cv_done.notify_all();
     }
 
-    void release_device(Job &j) {
-        if (j.t) spt_tensor_free(j.t);
+    // stream-ordered frees after the job's last use on stream s (no device-wide sync)
+    void release_device(Job &j, hipStream_t s) {
+        tensor_release(j.t, s);
         j.t = nullptr;
-        for (float *p : j.F)
-            if (p) (void)hipFree(p);
+        for (float *p : j.F) dev_free(p, s);
         j.F.clear();
-        if (j.lambda) (void)hipFree(j.lambda);
+        dev_free(j.lambda, s);
         j.lambda = nullptr;
     }
 
@@ -120,35 +120,31 @@ struct spt_server_s {
         const size_t nnz = (size_t)r.nnz;
         spt_status st = SPT_OK;
         if (nnz > 0) {
-            if (hipMalloc(&dc, sizeof(uint32_t) * nnz * r.nmodes) != hipSuccess ||
-                hipMalloc(&dv, sizeof(float) * nnz) != hipSuccess) {
-                (void)hipGetLastError();
-                st = fail(SPT_E_OOM, "server: staging buffers");
-            }
+            dc = (uint32_t *)dev_alloc(sizeof(uint32_t) * nnz * r.nmodes, side);
+            dv = (float *)dev_alloc(sizeof(float) * nnz, side);
+            if (!dc || !dv) st = fail(SPT_E_OOM, "server: staging buffers");
             if (st == SPT_OK &&
                 (hipMemcpyAsync(dc, j.coords.data(), sizeof(uint32_t) * nnz * r.nmodes, hipMemcpyHostToDevice, side) != hipSuccess ||
                  hipMemcpyAsync(dv, j.vals.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, side) != hipSuccess))
                 st = hip_fail(hipGetLastError(), "server: upload");
         }
         if (st == SPT_OK) st = spt_encode(r.dims, r.nmodes, dc, dv, r.nnz, nullptr, 0, side, &j.t);
-        if (dc) (void)hipFree(dc);
-        if (dv) (void)hipFree(dv);
+        dev_free(dc, side);
+        dev_free(dv, side);
         if (st != SPT_OK) return st;
         j.F.assign(r.nmodes, nullptr);
         for (int n = 0; n < r.nmodes && st == SPT_OK; ++n) {
             const size_t e = (size_t)r.dims[n] * r.rank;
-            if (hipMalloc(&j.F[n], sizeof(float) * e) != hipSuccess) {
-                (void)hipGetLastError();
+            j.F[n] = (float *)dev_alloc(sizeof(float) * e, side);
+            if (!j.F[n]) {
                 st = fail(SPT_E_OOM, "server: factors");
                 break;
             }
             if (hipMemcpyAsync(j.F[n], j.init[n].data(), sizeof(float) * e, hipMemcpyHostToDevice, side) != hipSuccess)
                 st = hip_fail(hipGetLastError(), "server: factor upload");
         }
-        if (st == SPT_OK && hipMalloc(&j.lambda, sizeof(double) * r.rank) != hipSuccess) {
-            (void)hipGetLastError();
+        if (st == SPT_OK && !(j.lambda = (double *)dev_alloc(sizeof(double) * r.rank, side)))
             st = fail(SPT_E_OOM, "server: lambda");
-        }
         if (st == SPT_OK && hipStreamSynchronize(side) != hipSuccess) st = hip_fail(hipGetLastError(), "server: stage sync");
         // the host copies are no longer needed
         std::vector<uint32_t>().swap(j.coords);
@@ -184,7 +180,8 @@ struct spt_server_s {
             j->res.t_admit = now();
             spt_status st = stage(*j);
             if (st != SPT_OK) {
-                release_device(*j);
+                (void)hipStreamSynchronize(side);
+                release_device(*j, side);
                 {
                     std::lock_guard<std::mutex> lk(mu);
                     used -= j->bytes;
@@ -272,7 +269,7 @@ struct spt_server_s {
             j.res.fit = j.m.fit;
             j.res.iters = j.m.iters;
         }
-        release_device(j);
+        release_device(j, compute);
         {
             std::lock_guard<std::mutex> lk(mu);
             used -= j.bytes;

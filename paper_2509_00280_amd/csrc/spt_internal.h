@@ -97,6 +97,8 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
 void release_plans(Tensor *t);
+// release a handle after its last use on stream s (stream-ordered frees)
+void tensor_release(Tensor *t, hipStream_t s);
 // drop the cached plan of one mode (the next call at that mode plans again)
 void release_mode_plan(Tensor *t, int mode);
 bool seg_tile_ok(int tile, int nmodes);

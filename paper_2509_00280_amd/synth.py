@@ -124,6 +124,39 @@ def _linear(coords: np.ndarray, dims) -> np.ndarray:
     return lin
 
 
+def _mode_groups(dims, limit: int = 2 ** 63) -> list:
+    """Consecutive runs of modes whose box size stays below ``limit``."""
+    groups, cur, prod = [], [], 1
+    for n, d in enumerate(dims):
+        if cur and prod * int(d) >= limit:
+            groups.append(cur)
+            cur, prod = [], 1
+        cur.append(n)
+        prod *= int(d)
+    groups.append(cur)
+    return groups
+
+
+def _cell_words(coords: np.ndarray, dims, groups) -> list:
+    """C-order cell number of each coordinate as one int64 word per mode group."""
+    return [_linear(coords[g], [dims[n] for n in g]) for g in groups]
+
+
+def _first_occurrences_words(words: list) -> np.ndarray:
+    """``_first_occurrences`` for keys made of several int64 words (first word most significant)."""
+    if len(words) == 1:
+        return _first_occurrences(words[0])
+    order = np.lexsort(tuple(reversed(words)))  # stable: equal keys keep index order
+    head = np.ones(order.shape[0], dtype=bool)
+    if order.shape[0] > 1:
+        diff = np.zeros(order.shape[0] - 1, dtype=bool)
+        for w in words:
+            ws = w[order]
+            diff |= ws[1:] != ws[:-1]
+        head[1:] = diff
+    return np.sort(order[head])
+
+
 def distinct_coo(seed: int, dims, nnz: int, mode_dists, vdist, max_rounds: int = 40) -> SparseCOO:
     """Draw coordinate+value pairs until ``nnz`` distinct coordinates exist.
 
@@ -133,8 +166,8 @@ def distinct_coo(seed: int, dims, nnz: int, mode_dists, vdist, max_rounds: int =
     the realized count is smaller and recorded in ``meta['realized_nnz']``.
     """
     dims = tuple(int(d) for d in dims)
-    if math.prod(dims) >= 2 ** 63:
-        raise ValueError("box too large for the 63-bit cell numbering used to deduplicate")
+    # boxes of 2^63 cells or more are numbered with one word per group of modes
+    groups = _mode_groups(dims)
     nm = len(dims)
     ss = np.random.SeedSequence(seed)
     s_coord, s_val = ss.spawn(2)
@@ -142,20 +175,20 @@ def distinct_coo(seed: int, dims, nnz: int, mode_dists, vdist, max_rounds: int =
     rv = np.random.default_rng(s_val)
     kept_c = np.zeros((nm, 0), dtype=np.uint32)
     kept_v = np.zeros(0, dtype=np.float32)
-    kept_lin = np.zeros(0, dtype=np.int64)
+    kept_w = [np.zeros(0, dtype=np.int64) for _ in groups]
     rounds = 0
     while kept_v.shape[0] < nnz and rounds < max_rounds:
         deficit = nnz - kept_v.shape[0]
         m = int(math.ceil(1.5 * deficit))
         c = np.stack([draw_labels(rc, dims[n], m, mode_dists[n]) for n in range(nm)])
         v = _draw_values(rv, m, vdist)
-        lin = _linear(c, dims)
-        all_lin = np.concatenate([kept_lin, lin])
-        first = _first_occurrences(all_lin)
-        first = first[first >= kept_lin.shape[0]] - kept_lin.shape[0]
+        w = _cell_words(c, dims, groups)
+        nk = kept_v.shape[0]
+        first = _first_occurrences_words([np.concatenate([a, b]) for a, b in zip(kept_w, w)])
+        first = first[first >= nk] - nk
         kept_c = np.concatenate([kept_c, c[:, first]], axis=1)
         kept_v = np.concatenate([kept_v, v[first]])
-        kept_lin = np.concatenate([kept_lin, lin[first]])
+        kept_w = [np.concatenate([a, b[first]]) for a, b in zip(kept_w, w)]
         rounds += 1
     kept_c = np.ascontiguousarray(kept_c[:, :nnz])
     kept_v = np.ascontiguousarray(kept_v[:nnz])

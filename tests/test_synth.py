@@ -57,3 +57,20 @@ def test_batch_members_shapes():
         assert t.nmodes in (3, 4) and r in (16, 32)
         assert len(f) == t.nmodes and all(ff.shape == (d, r) for ff, d in zip(f, t.dims))
         assert 1000 * 0.5 <= t.nnz <= 5000
+
+
+def test_multiword_dedup_matches_single_word():
+    rng = np.random.default_rng(3)
+    dims = (50, 40, 30, 20)
+    c = np.stack([rng.integers(0, d, 5000) for d in dims]).astype(np.uint32)
+    one = synth._first_occurrences(synth._linear(c, dims))
+    words = synth._cell_words(c, dims, [[0, 1], [2, 3]])
+    np.testing.assert_array_equal(synth._first_occurrences_words(words), one)
+
+
+def test_distinct_coo_huge_box():
+    dims = (200_000, 150_000, 190_000, 170_000)  # more than 2^63 cells
+    assert len(synth._mode_groups(dims)) == 2
+    t = synth.distinct_coo(3, dims, 20_000, [("zipf", 1.2)] * 4, "u01")
+    assert t.nnz == 20_000
+    assert len(set(map(tuple, t.coords.T))) == 20_000
