@@ -25,7 +25,7 @@
 #include "tile_common.h"
 
 #ifndef SPT_SEG_UB
-#define SPT_SEG_UB 4
+#define SPT_SEG_UB 2
 #endif
 #ifndef SPT_SEG_PIECE
 #define SPT_SEG_PIECE 32
@@ -187,14 +187,24 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 
 // Walk the staged tile: every piece becomes record rbase + piece of
 // ld floats (columns R..ld-1 zero) whose row is row_base + the piece's row.
-template <int NT, int G, int VEC, int NB, int NMAX>
+// EXACT: the lane groups cover exactly R columns (no column mask).
+// With at most 4 modes every nonzero slot of an unrolled step reads all its
+// coordinates from LDS first, then issues every factor-row gather, then waits
+// once; with more modes the gathers go mode by mode.
+template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, uint64_t *__restrict__ rec_row,
                                          float *__restrict__ rec_val, int64_t rbase, int ld, int64_t row_base) {
     constexpr int T = 4 * NT;
     constexpr int UB = kUnroll;
+    constexpr int NO = NMAX - 1;  // non-output modes at most
     const int npieces = (int)(L.hcnt[T] & 0xFFFFu);
     const int j = threadIdx.x % G;
-    const int R = a.rank, mode = a.mode, nm = a.nmodes;
+    const int R = a.rank, mode = a.mode, no = a.nmodes - 1;
+    const uint32_t Ru = (uint32_t)R;
+    // factor of the o-th non-output mode
+    const float *fo[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) fo[o] = o < no ? a.f[o + (o >= mode)] : nullptr;
     for (int k = threadIdx.x / G; k < npieces; k += NT / G) {
         const int s = L.ptab[k];
         const uint32_t pk = L.hcnt[s];
@@ -209,43 +219,83 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
             for (int v = 0; v < VEC; ++v) acc[b][v] = 0.f;
         for (int q = p0; q < p1; q += UB) {
             int pp[UB];
-            float p[UB][NB][VEC];
+            float x[UB];
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
                 const bool ok = q + u < p1;
-                pp[u] = ok ? q + u : p0;
-                const float x = ok ? L.valg[pp[u]] : 0.f;
+                pp[u] = ok ? q + u : p1 - 1;  // in range either way; the value is zeroed
+                const float v = L.valg[pp[u]];
+                x[u] = ok ? v : 0.f;
+            }
+            float p[UB][NB][VEC];
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) p[u][b][v] = x;
-            }
+                    for (int v = 0; v < VEC; ++v) p[u][b][v] = x[u];
+            if constexpr (NO <= 3) {
+                uint32_t row[NO][UB];
 #pragma unroll
-            for (int kk = 0; kk < NMAX; ++kk) {
-                if (kk < nm && kk != mode) {
-                    const float *__restrict__ F = a.f[kk];
-                    const uint32_t *cg = L.crdg + (kk - (kk > mode)) * T;
-                    float xv[UB][NB][VEC];
+                for (int o = 0; o < NO; ++o)
+                    if (o < no)
 #pragma unroll
-                    for (int u = 0; u < UB; ++u) {
-                        const float *fr = F + (int64_t)cg[pp[u]] * R;
+                        for (int u = 0; u < UB; ++u) row[o][u] = L.crdg[o * T + pp[u]];
+                float xv[NO][UB][NB][VEC];
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) {
-                            const int c = (b * G + j) * VEC;
-                            if (c < R) {
-                                load_vec<VEC>(fr + c, xv[u][b]);
-                            } else {
+                for (int o = 0; o < NO; ++o) {
+                    if (o < no) {
 #pragma unroll
-                                for (int v = 0; v < VEC; ++v) xv[u][b][v] = 0.f;
+                        for (int u = 0; u < UB; ++u) {
+                            const float *fr = fo[o] + (uint64_t)row[o][u] * Ru;
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) {
+                                const int c = (b * G + j) * VEC;
+                                if (EXACT || c < R) {
+                                    load_vec<VEC>(fr + c, xv[o][u][b]);
+                                } else {
+#pragma unroll
+                                    for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
+                                }
                             }
                         }
                     }
+                }
 #pragma unroll
-                    for (int u = 0; u < UB; ++u)
+                for (int o = 0; o < NO; ++o)
+                    if (o < no)
 #pragma unroll
-                        for (int b = 0; b < NB; ++b)
+                        for (int u = 0; u < UB; ++u)
 #pragma unroll
-                            for (int v = 0; v < VEC; ++v) p[u][b][v] *= xv[u][b][v];
+                            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                                for (int v = 0; v < VEC; ++v) p[u][b][v] *= xv[o][u][b][v];
+            } else {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    if (o < no) {
+                        float xv[UB][NB][VEC];
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            const float *fr = fo[o] + (uint64_t)L.crdg[o * T + pp[u]] * Ru;
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) {
+                                const int c = (b * G + j) * VEC;
+                                if (EXACT || c < R) {
+                                    load_vec<VEC>(fr + c, xv[u][b]);
+                                } else {
+#pragma unroll
+                                    for (int v = 0; v < VEC; ++v) xv[u][b][v] = 0.f;
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < UB; ++u)
+#pragma unroll
+                            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                                for (int v = 0; v < VEC; ++v) p[u][b][v] *= xv[u][b][v];
+                    }
                 }
             }
 #pragma unroll
@@ -261,7 +311,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int c = (b * G + j) * VEC;
-            if (c < ld) {
+            if (EXACT || c < ld) {
                 if constexpr (VEC == 4) {
                     // columns at or beyond R were loaded as zero factors, so acc is 0 there
                     *reinterpret_cast<float4 *>(o + c) = make_float4(acc[b][0], acc[b][1], acc[b][2], acc[b][3]);
@@ -274,7 +324,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
     }
 }
 
-template <int NT, int G, int VEC, int NB, int NMAX>
+template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
 __global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles) {
     constexpr int T = 4 * NT;
     extern __shared__ __align__(16) char lds[];
@@ -284,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles)
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
-    seg_walk<NT, G, VEC, NB, NMAX>(a, L, a.rec_row, a.rec_val, a.rec_off[tile], a.rank, 0);
+    seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, L, a.rec_row, a.rec_val, a.rec_off[tile], a.rank, 0);
 }
 
 // Batched: tile `it` of the whole batch belongs to the last item whose
@@ -315,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg_batched(const SegItem *__rest
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
-    seg_walk<NT, G, VEC, NB, NMAX>(a, L, rec_row, rec_val, item.rec_base + a.rec_off[tile], ld, item.row_base);
+    seg_walk<NT, G, VEC, NB, NMAX, false>(a, L, rec_row, rec_val, item.rec_base + a.rec_off[tile], ld, item.row_base);
 }
 
 // Pieces of every tile (the plan's counting pass).
@@ -349,7 +399,10 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
 template <int NT, int NMAX, int G, int VEC, int NB>
 spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
     const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
-    hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+    if (a.rank == G * VEC * NB)
+        hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+    else
+        hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX, false>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
@@ -405,10 +458,15 @@ spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
     if (ntiles == 0) return SPT_OK;
     if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
-    const bool n4 = a.nmodes <= 4;
-    if (a.tile == 1024) return n4 ? launch_seg_nt<256, 4>(a, ntiles, s) : launch_seg_nt<256, 8>(a, ntiles, s);
-    if (a.tile == 2048) return n4 ? launch_seg_nt<512, 4>(a, ntiles, s) : launch_seg_nt<512, 8>(a, ntiles, s);
-    return n4 ? launch_seg_nt<1024, 4>(a, ntiles, s) : launch_seg_nt<1024, 8>(a, ntiles, s);
+    const int nm = a.nmodes;
+    if (a.tile == 1024)
+        return nm <= 3 ? launch_seg_nt<256, 3>(a, ntiles, s)
+                       : (nm <= 4 ? launch_seg_nt<256, 4>(a, ntiles, s) : launch_seg_nt<256, 8>(a, ntiles, s));
+    if (a.tile == 2048)
+        return nm <= 3 ? launch_seg_nt<512, 3>(a, ntiles, s)
+                       : (nm <= 4 ? launch_seg_nt<512, 4>(a, ntiles, s) : launch_seg_nt<512, 8>(a, ntiles, s));
+    return nm <= 3 ? launch_seg_nt<1024, 3>(a, ntiles, s)
+                   : (nm <= 4 ? launch_seg_nt<1024, 4>(a, ntiles, s) : launch_seg_nt<1024, 8>(a, ntiles, s));
 }
 
 namespace {
