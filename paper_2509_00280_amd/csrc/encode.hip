@@ -233,6 +233,74 @@ __global__ __launch_bounds__(kThreads) void k_gather_u32(const uint32_t *__restr
         out[j] = src[idx[j]];
 }
 
+// dst[idx[j]] = src[j] (32-bit words)
+__global__ __launch_bounds__(kThreads) void k_scatter_u32(const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx,
+                                                          uint32_t *__restrict__ dst, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads)
+        dst[idx[j]] = src[j];
+}
+
+// Exclusive prefix sum in three launches: per-block local scans of
+// kScanItems values per thread, one block scanning the block totals
+// (chunk by chunk with a running carry), then the block offsets added.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__global__ __launch_bounds__(kThreads) void k_scan_local(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                         int64_t n, uint32_t *__restrict__ sums) {
+    __shared__ uint32_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t local = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0u;
+        local += v[i];
+    }
+    uint32_t run = block_scan_256(local, wsum);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == kThreads - 1) sums[blockIdx.x] = run;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_sums(uint32_t *__restrict__ sums, int64_t nb) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += kScanTile) {
+        const int64_t base = c0 + (int64_t)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t local = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            v[i] = base + i < nb ? sums[base + i] : 0u;
+            local += v[i];
+        }
+        const uint32_t c = carry;
+        uint32_t run = c + block_scan_256(local, wsum);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < nb) sums[base + i] = run;
+            run += v[i];
+        }
+        __syncthreads();  // every thread has read carry
+        if (threadIdx.x == kThreads - 1) carry = run;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t *__restrict__ out, int64_t n,
+                                                       const uint32_t *__restrict__ sums) {
+    const uint32_t add = sums[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int i = threadIdx.x; i < kScanTile; i += kThreads)
+        if (base + i < n) out[base + i] += add;
+}
+
 __global__ __launch_bounds__(kThreads) void k_decode(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
                                                      int64_t nnz, Codec codec, uint32_t *__restrict__ coords) {
     const CodecRegs cl = load_codec_regs(codec);
@@ -420,6 +488,25 @@ spt_status launch_decode(const Tensor *t, uint32_t *coords, hipStream_t s) {
 spt_status launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *out, int64_t n, hipStream_t s) {
     if (n == 0) return SPT_OK;
     hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(n, kThreads, 16384)), dim3(kThreads), 0, s, src, idx, out, n);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_scatter_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, int64_t n, hipStream_t s) {
+    if (n == 0) return SPT_OK;
+    hipLaunchKernelGGL(k_scatter_u32, dim3(grid_for(n, kThreads, 16384)), dim3(kThreads), 0, s, src, idx, dst, n);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+size_t exclusive_scan_ws(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+spt_status launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *ws, hipStream_t s) {
+    if (n == 0) return SPT_OK;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n, ws);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, s, ws, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kThreads), 0, s, out, n, ws);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

@@ -40,9 +40,11 @@ constexpr int kUnroll = SPT_SEG_UB;    // nonzeros in flight per lane group
 
 // LDS: crdg[nm - 1][T] u32 (non-output coordinates, row-grouped), valg[T] f32,
 // hkey[T] u32 (slot -> row), hcnt[T + 4] u32 (packed counts, then prefixes;
-// entry T holds the totals), ptab[T] u16 (piece -> slot).
-__host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes) {
-    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2;
+// entry T holds the totals), ptab[T] u16 (piece -> slot), and with row-grouped
+// records sdest[T] u32 (slot -> first record of the slot's pieces).
+__host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes, bool dest = false) {
+    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2 +
+           (dest ? (size_t)T * 4 : 0);
 }
 
 struct SegLds {
@@ -51,6 +53,7 @@ struct SegLds {
     uint32_t *hkey;
     uint32_t *hcnt;
     uint16_t *ptab;
+    uint32_t *sdest;
 };
 
 __device__ __forceinline__ SegLds seg_carve(char *p, int T, int nmodes) {
@@ -60,7 +63,21 @@ __device__ __forceinline__ SegLds seg_carve(char *p, int T, int nmodes) {
     L.hkey = (uint32_t *)(L.valg + T);
     L.hcnt = L.hkey + T;
     L.ptab = (uint16_t *)(L.hcnt + T + 4);
+    L.sdest = (uint32_t *)(L.ptab + T);
     return L;
+}
+
+// slot of `row` in the tile's hash, or T if it is absent (bounded probe)
+template <int T>
+__device__ __forceinline__ uint32_t seg_find(const uint32_t *hkey, uint32_t row) {
+    uint32_t s = mix_hash(row) & (uint32_t)(T - 1);
+    for (int n = 0; n < T; ++n) {
+        const uint32_t h = hkey[s];
+        if (h == row) return s;
+        if (h == kNoRow) return T;
+        s = (s + 1) & (uint32_t)(T - 1);
+    }
+    return T;
 }
 
 // Stage and regroup one tile.  After return: hcnt[s] = (first position of
@@ -191,7 +208,9 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 // With at most 4 modes every nonzero slot of an unrolled step reads all its
 // coordinates from LDS first, then issues every factor-row gather, then waits
 // once; with more modes the gathers go mode by mode.
-template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
+// DEST: piece i of slot s goes to record sdest[s] + i (records grouped by
+// row); otherwise piece k of the tile goes to record rbase + k.
+template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT, bool DEST = false>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, uint64_t *__restrict__ rec_row,
                                          float *__restrict__ rec_val, int64_t rbase, int ld, int64_t row_base) {
     constexpr int T = 4 * NT;
@@ -305,7 +324,9 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) acc[b][v] += p[u][b][v];
         }
-        const int64_t pos = rbase + k;
+        const int64_t pos = DEST ? (int64_t)L.sdest[s] + (k - (int)(pk & 0xFFFFu)) : rbase + k;
+        // with plan-given slots, a record outside the plan's range is never written
+        if (DEST && (L.sdest[s] == kNoRow || pos >= a.rec_cap)) continue;
         if (j == 0) rec_row[pos] = (uint64_t)(row_base + L.hkey[s]);
         float *o = rec_val + pos * ld;
 #pragma unroll
@@ -333,8 +354,28 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles)
     if (tile >= ntiles) return;
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
+    // the plan's (row, first record) pairs of this tile (at most T), loaded
+    // before the stage so their latency hides behind it
+    const int64_t q0 = a.pair_off[tile], q1 = a.pair_off[tile + 1];
+    uint32_t prow[4], pdst[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t q = q0 + threadIdx.x + u * NT;
+        prow[u] = q < q1 ? a.pair_row[q] : kNoRow;
+        pdst[u] = q < q1 ? a.pair_dest[q] : kNoRow;
+    }
+    for (int i = threadIdx.x; i < T; i += NT) L.sdest[i] = kNoRow;  // ordered by the stage's barriers
     seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
-    seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, L, a.rec_row, a.rec_val, a.rec_off[tile], a.rank, 0);
+    // first record of every slot; a slot the plan does not name keeps the marker
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (prow[u] != kNoRow) {
+            const uint32_t slot = seg_find<T>(L.hkey, prow[u]);
+            if (slot < (uint32_t)T) L.sdest[slot] = pdst[u];
+        }
+    }
+    __syncthreads();
+    seg_walk<NT, G, VEC, NB, NMAX, EXACT, true>(a, L, a.rec_row, a.rec_val, 0, a.rank, 0);
 }
 
 // Batched: tile `it` of the whole batch belongs to the last item whose
@@ -378,7 +419,46 @@ __global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntile
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
-    if (threadIdx.x == 0) out[tile] = L.hcnt[T] & 0xFFFFu;
+    // distinct rows: slots whose element range is not empty
+    __shared__ uint32_t s_distinct;
+    if (threadIdx.x == 0) s_distinct = 0;
+    __syncthreads();
+    uint32_t d = 0;
+    for (int i = threadIdx.x; i < T; i += NT) {
+        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
+        d += (nx >> 16) != (L.hcnt[i] >> 16);
+    }
+    atomicAdd(&s_distinct, d);
+    __syncthreads();
+    if (threadIdx.x == 0) out[tile] = (int64_t)(L.hcnt[T] & 0xFFFFu) | ((int64_t)s_distinct << 32);
+}
+
+// The (row, pieces) pair of every distinct row of every tile, written at
+// a.pair_off[tile] in the tile's slot order.
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_emit_pairs(MttkrpArgs a, int64_t ntiles, uint32_t *__restrict__ rows,
+                                                   uint64_t *__restrict__ keys, uint32_t *__restrict__ pieces) {
+    constexpr int T = 4 * NT;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t s_n;
+    const int64_t tile = blockIdx.x;
+    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const CodecRegs cr = load_codec_regs(a.codec);
+    if (threadIdx.x == 0) s_n = 0;
+    seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
+    const int64_t base = a.pair_off[tile];
+    for (int i = threadIdx.x; i < T; i += NT) {
+        const uint32_t pk = L.hcnt[i];
+        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
+        const uint32_t c = (nx >> 16) - (pk >> 16);
+        if (c > 0) {
+            const uint32_t q = atomicAdd(&s_n, 1u);
+            rows[base + q] = L.hkey[i];
+            keys[base + q] = L.hkey[i];
+            pieces[base + q] = (c + kPiece - 1) / kPiece;
+        }
+    }
 }
 
 template <int NT, int NMAX>
@@ -398,7 +478,7 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
 
 template <int NT, int NMAX, int G, int VEC, int NB>
 spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
-    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
+    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes, true);
     if (a.rank == G * VEC * NB)
         hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
     else
@@ -427,6 +507,18 @@ spt_status launch_seg_nt(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
 }
 
 template <int NT>
+spt_status launch_emit_nt(const MttkrpArgs &a, int64_t ntiles, uint32_t *rows, uint64_t *keys, uint32_t *pieces,
+                          hipStream_t s) {
+    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
+    if (a.nmodes <= 4)
+        hipLaunchKernelGGL((k_emit_pairs<NT, 4>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, rows, keys, pieces);
+    else
+        hipLaunchKernelGGL((k_emit_pairs<NT, 8>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, rows, keys, pieces);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+template <int NT>
 spt_status launch_count_nt(const MttkrpArgs &a, int64_t ntiles, int64_t *out, hipStream_t s) {
     const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
     if (a.nmodes <= 4)
@@ -442,7 +534,16 @@ spt_status launch_count_nt(const MttkrpArgs &a, int64_t ntiles, int64_t *out, hi
 // tile sizes served: 1024 (256 threads), 2048 (512), 4096 (1024 threads)
 bool seg_tile_ok(int tile, int nmodes) {
     if (tile != 1024 && tile != 2048 && tile != 4096) return false;
-    return seg_lds_bytes(tile, nmodes) <= 160 * 1024 - 1024;
+    return seg_lds_bytes(tile, nmodes, true) <= 160 * 1024 - 1024;
+}
+
+spt_status launch_emit_pairs(const MttkrpArgs &a, uint32_t *rows, uint64_t *keys, uint32_t *pieces, hipStream_t s) {
+    const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
+    if (ntiles == 0) return SPT_OK;
+    if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
+    if (a.tile == 1024) return launch_emit_nt<256>(a, ntiles, rows, keys, pieces, s);
+    if (a.tile == 2048) return launch_emit_nt<512>(a, ntiles, rows, keys, pieces, s);
+    return launch_emit_nt<1024>(a, ntiles, rows, keys, pieces, s);
 }
 
 spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s) {

@@ -387,13 +387,20 @@ __global__ __launch_bounds__(256) void k_reduce_priv(const float *__restrict__ p
 // Records sorted by row: lane groups sum runs of equal row over a chunk of
 // records (8 record loads in flight per lane); a run wholly inside the chunk
 // is stored, a run crossing a chunk edge is added atomically (out was zeroed).
+#ifndef SPT_RED_UB
+#define SPT_RED_UB 8
+#endif
+#ifndef SPT_RED_CHUNK
+#define SPT_RED_CHUNK 64
+#endif
+
 template <int G, int VEC, int NB>
 __global__ __launch_bounds__(256) void k_reduce_records(const uint64_t *__restrict__ srow,
                                                         const uint32_t *__restrict__ sidx,
                                                         const float *__restrict__ rec_val, int64_t P, int R,
                                                         int chunk, int64_t rows, float *__restrict__ out) {
     constexpr int GROUPS = 256 / G;
-    constexpr int UB = 8;
+    constexpr int UB = SPT_RED_UB;
     const int g = threadIdx.x / G, j = threadIdx.x % G;
     const int64_t c0 = ((int64_t)blockIdx.x * GROUPS + g) * chunk;
     if (c0 >= P) return;
@@ -429,7 +436,9 @@ __global__ __launch_bounds__(256) void k_reduce_records(const uint64_t *__restri
         for (int u = 0; u < UB; ++u) {
             const bool ok = q + u < c1;
             r[u] = ok ? srow[q + u] : ~0ull;
-            const float *src = rec_val + (int64_t)(ok ? sidx[q + u] : 0) * R;
+            // sidx null: the records are already grouped by row (identity order)
+            const int64_t ri = ok ? (sidx ? (int64_t)sidx[q + u] : q + u) : 0;
+            const float *src = rec_val + ri * R;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int c = (b * G + j) * VEC;
@@ -532,7 +541,7 @@ spt_status launch_reduce_priv(const float *part, int nwg, int64_t rows, int R, f
 spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, const float *rec_val, int64_t P, int R,
                                  int64_t rows, float *out, hipStream_t s) {
     if (P <= 0) return SPT_OK;
-    constexpr int chunk = 64;
+    constexpr int chunk = SPT_RED_CHUNK;
     auto go = [&](auto kern, int G) -> spt_status {
         const int groups = 256 / G;
         const int64_t blocks = (P + (int64_t)groups * chunk - 1) / ((int64_t)groups * chunk);

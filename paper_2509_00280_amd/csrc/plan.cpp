@@ -111,14 +111,15 @@ void release_ws(Tensor *t) {
 }
 
 void release_mode_plan(Tensor *t, int n) {
-    if (t->mplan[n].rec_off) (void)hipFree(t->mplan[n].rec_off);
-    t->mplan[n] = ModePlan{};
+    ModePlan &p = t->mplan[n];
+    for (void *q : {(void *)p.rec_off, (void *)p.pair_row, (void *)p.pair_dest, (void *)p.pair_off})
+        if (q) (void)hipFree(q);
+    p = ModePlan{};
 }
 
 void release_plans(Tensor *t) {
     for (int n = 0; n < kMaxModes; ++n) {
-        if (t->mplan[n].rec_off) (void)hipFree(t->mplan[n].rec_off);
-        t->mplan[n] = ModePlan{};
+        release_mode_plan(t, n);
         dev_free(t->bseg_off[n], nullptr);  // callers order this after the tensor's last use
         t->bseg_off[n] = nullptr;
         t->bseg_records[n] = 0;
@@ -131,6 +132,68 @@ int segment_tile(const Tensor *t, int mode) {
     const int want = t->plan.tile[mode];
     if (want >= 1024 && seg_tile_ok(want, t->nmodes)) return want;
     return seg_tile_ok(2048, t->nmodes) ? 2048 : 1024;
+}
+
+// SEGMENT plan (once per tensor and mode; synchronises s once).  A tile's
+// records are its pieces (runs of at most L nonzeros of one row), so
+//  1. a counting pass gives every tile's pieces and distinct rows;
+//  2. every distinct (tile, row) pair is emitted with its piece count, tile-major;
+//  3. a stable sort of the pairs by row (tile order kept within a row) and an
+//     exclusive scan of their piece counts give each pair its first record,
+//     so the records of one row come out contiguous and need no sort per call.
+spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan &p) {
+    p.ts = segment_tile(t, mode);
+    const int64_t ntiles = (t->nnz + p.ts - 1) / p.ts;
+    std::vector<int64_t> h(ntiles + 1, 0);
+    SPT_HIP(hipMalloc(&p.pair_off, sizeof(int64_t) * (ntiles + 1)));
+    if (ntiles > 0) {
+        spt_status st = launch_count_pieces(make_args(t, nullptr, rank, mode, nullptr, p.ts), p.pair_off, s);
+        if (st != SPT_OK) return st;
+        SPT_HIP(hipMemcpyAsync(h.data(), p.pair_off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s));
+        SPT_HIP(hipStreamSynchronize(s));
+    }
+    int64_t pieces = 0, pairs = 0;
+    for (int64_t i = 0; i < ntiles; ++i) {
+        const int64_t c = h[i];
+        pieces += c & 0xFFFFFFFFll;
+        h[i] = pairs;
+        pairs += c >> 32;
+    }
+    h[ntiles] = pairs;
+    p.records = pieces;
+    if (pieces >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "plan: more than 2^32 records");
+    SPT_HIP(hipMemcpy(p.pair_off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice));
+    const size_t q1 = (size_t)std::max<int64_t>(pairs, 1);
+    SPT_HIP(hipMalloc(&p.pair_row, sizeof(uint32_t) * q1));
+    SPT_HIP(hipMalloc(&p.pair_dest, sizeof(uint32_t) * q1));
+    if (pairs == 0) return SPT_OK;
+    uint64_t *keys = (uint64_t *)dev_alloc(sizeof(uint64_t) * q1, s);
+    uint64_t *keys2 = (uint64_t *)dev_alloc(sizeof(uint64_t) * q1, s);
+    uint32_t *np = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
+    uint32_t *ia = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
+    uint32_t *ib = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
+    uint32_t *cnt = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max(sort_ws_counts(pairs), exclusive_scan_ws(pairs)), s);
+    spt_status st = (keys && keys2 && np && ia && ib && cnt) ? SPT_OK : fail(SPT_E_OOM, "plan: pair workspace");
+    MttkrpArgs a = make_args(t, nullptr, rank, mode, nullptr, p.ts);
+    a.pair_off = p.pair_off;
+    if (st == SPT_OK) st = launch_emit_pairs(a, p.pair_row, keys, np, s);
+    uint64_t *sk = nullptr;
+    uint32_t *sidx = nullptr;
+    if (st == SPT_OK) st = sort_u64_keys_ws(keys, keys2, ia, ib, cnt, pairs, t->lbits[mode], &sk, &sidx, s);
+    // pieces in row order -> their exclusive prefix -> back to emission order
+    uint32_t *np_sorted = (sidx == ia) ? ib : ia;
+    uint32_t *first = (uint32_t *)keys2;  // free once the sort is done (its keys are not needed)
+    if (sk == keys2) first = (uint32_t *)keys;
+    if (st == SPT_OK) st = launch_gather_u32(np, sidx, np_sorted, pairs, s);
+    if (st == SPT_OK) st = launch_exclusive_scan_u32(np_sorted, first, pairs, cnt, s);
+    if (st == SPT_OK) st = launch_scatter_u32(first, sidx, p.pair_dest, pairs, s);
+    dev_free(keys, s);
+    dev_free(keys2, s);
+    dev_free(np, s);
+    dev_free(ia, s);
+    dev_free(ib, s);
+    dev_free(cnt, s);
+    return st;
 }
 
 spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out) {
@@ -146,9 +209,9 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
         *out = &p;
         return SPT_OK;
     }
-    if (p.rec_off) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(p.rec_off);
+    if (p.rec_off || p.pair_off || p.pair_row || p.pair_dest) {
+        (void)hipStreamSynchronize(s);  // the previous plan's arrays may still be in use
+        release_mode_plan(t, mode);
     }
     p = ModePlan{};
     p.rank = rank;
@@ -208,37 +271,11 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
         }
         p.rec_off = cnt;
     } else if (want == SPT_STRATEGY_SEGMENT) {
-        // counting pass: pieces (runs of at most 32 nonzeros of one row) of every
-        // tile; a tile's records are exactly its pieces
-        p.ts = segment_tile(t, mode);
-        const int64_t ntiles = (t->nnz + p.ts - 1) / p.ts;
-        int64_t *off = nullptr;
-        SPT_HIP(hipMalloc(&off, sizeof(int64_t) * (ntiles + 1)));
-        std::vector<int64_t> h(ntiles + 1, 0);
-        spt_status st = SPT_OK;
-        if (ntiles > 0) {
-            st = launch_count_pieces(make_args(t, nullptr, rank, mode, nullptr, p.ts), off, s);
-            if (st == SPT_OK && (hipMemcpyAsync(h.data(), off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                                 hipStreamSynchronize(s) != hipSuccess))
-                st = hip_fail(hipGetLastError(), "plan: distinct rows per tile");
-        }
+        spt_status st = build_segment_plan(t, mode, rank, s, p);
         if (st != SPT_OK) {
-            (void)hipFree(off);
+            release_mode_plan(t, mode);
             return st;
         }
-        int64_t run = 0;
-        for (int64_t i = 0; i < ntiles; ++i) {
-            const int64_t c = h[i];
-            h[i] = run;
-            run += c;
-        }
-        h[ntiles] = run;
-        p.records = run;
-        if (hipMemcpy(off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(off);
-            return hip_fail(hipGetLastError(), "plan: record offsets");
-        }
-        p.rec_off = off;
     } else {
         p.ts = t->plan.tile[mode];
     }
@@ -315,32 +352,35 @@ spt_status profile_read(double *ms, int64_t *launches) {
 }
 
 // Records path shared by SEGMENT and TABLE: the main kernel writes P
-// records, which are radix-sorted by row (rows + 1 bits, so the sentinel of
-// unused slots sorts last) and summed per row into out.
+// records (row, R floats) and the reducer sums them per row into out.
+// SEGMENT records come out grouped by row (the plan laid them out); TABLE
+// records are radix-sorted by row first.
 spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int64_t rows, float *out, hipStream_t s,
                               bool segment, TableArgs *ta = nullptr, int nwg = 0) {
     const size_t n1 = (size_t)std::max<int64_t>(P, 1);
     uint64_t *rrow = (uint64_t *)tensor_ws(t, WS_REC_ROW, sizeof(uint64_t) * n1, s);
     float *rval = (float *)tensor_ws(t, WS_REC_VAL, sizeof(float) * n1 * rank, s);
-    uint64_t *keys2 = (uint64_t *)tensor_ws(t, WS_KEYS2, sizeof(uint64_t) * n1, s);
-    uint32_t *ia = (uint32_t *)tensor_ws(t, WS_IDX_A, sizeof(uint32_t) * n1, s);
-    uint32_t *ib = (uint32_t *)tensor_ws(t, WS_IDX_B, sizeof(uint32_t) * n1, s);
-    uint32_t *cnt = (uint32_t *)tensor_ws(t, WS_COUNTS, sizeof(uint32_t) * sort_ws_counts((int64_t)n1), s);
-    if (!rrow || !rval || !keys2 || !ia || !ib || !cnt) return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
-    const int mode = a.mode;
+    if (!rrow || !rval) return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
     spt_status st;
     if (segment) {
         a.rec_row = rrow;
         a.rec_val = rval;
         st = launch_mttkrp_seg(a, s);
-    } else {
-        ta->rec_row = rrow;
-        ta->rec_val = rval;
-        st = launch_table(*ta, nwg, s);
+        if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
+        if (st == SPT_OK) st = launch_reduce_records(rrow, nullptr, rval, P, rank, rows, out, s);
+        return st;
     }
+    uint64_t *keys2 = (uint64_t *)tensor_ws(t, WS_KEYS2, sizeof(uint64_t) * n1, s);
+    uint32_t *ia = (uint32_t *)tensor_ws(t, WS_IDX_A, sizeof(uint32_t) * n1, s);
+    uint32_t *ib = (uint32_t *)tensor_ws(t, WS_IDX_B, sizeof(uint32_t) * n1, s);
+    uint32_t *cnt = (uint32_t *)tensor_ws(t, WS_COUNTS, sizeof(uint32_t) * sort_ws_counts((int64_t)n1), s);
+    if (!keys2 || !ia || !ib || !cnt) return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
+    ta->rec_row = rrow;
+    ta->rec_val = rval;
+    st = launch_table(*ta, nwg, s);
     uint64_t *srow = nullptr;
     uint32_t *sidx = nullptr;
-    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, keys2, ia, ib, cnt, P, t->lbits[mode], &srow, &sidx, s);
+    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, keys2, ia, ib, cnt, P, t->lbits[a.mode], &srow, &sidx, s);
     if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
     if (st == SPT_OK) st = launch_reduce_records(srow, sidx, rval, P, rank, rows, out, s);
     return st;
@@ -352,10 +392,12 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
     if (st != SPT_OK) return st;
     const int64_t rows = t->dims[mode];
     if (p->strategy == SPT_STRATEGY_SEGMENT && t->nnz > 0) {
-        const int64_t P = p->records;
         MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
-        a.rec_off = p->rec_off;
-        return reduce_via_records(t, a, P, rank, rows, out, s, /*segment=*/true);
+        a.pair_row = p->pair_row;
+        a.pair_dest = p->pair_dest;
+        a.pair_off = p->pair_off;
+        a.rec_cap = p->records;
+        return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/true);
     }
     if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
         st = launch_fill_zero(out, rows * (int64_t)rank, s);

@@ -60,8 +60,13 @@ struct ModePlan {
     int strategy = -1;       // resolved: DIRECT, REGROUP, TABLE or PRIV
     int cap = 0, hbits = 0, stride = 0, rs = 0, npass = 1, ts = 512, nwg = 0;
     int64_t sub_per_wg = 0;
-    int64_t records = 0;     // TABLE: records written per call
+    int64_t records = 0;     // TABLE / SEGMENT: records written per call
     int64_t *rec_off = nullptr;  // TABLE: device, nwg offsets
+    // SEGMENT: the distinct (tile, row) pairs of every tile (tile-major,
+    // pair_off[tile] .. pair_off[tile + 1]), each with the first record slot
+    // of its pieces; slots are laid out so that records are grouped by row
+    uint32_t *pair_row = nullptr, *pair_dest = nullptr;
+    int64_t *pair_off = nullptr;
 };
 
 // Grow-only device buffers owned by a tensor handle and reused by its MTTKRP
@@ -118,6 +123,11 @@ spt_status launch_export(const Tensor *t, uint64_t *keys, hipStream_t s);
 // caller-owned buffers (see encode.hip).
 size_t sort_ws_counts(int64_t n);
 spt_status launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *out, int64_t n, hipStream_t s);
+// dst[idx[j]] = src[j]
+spt_status launch_scatter_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, int64_t n, hipStream_t s);
+// exclusive prefix sum of n u32 values (totals below 2^32); ws of exclusive_scan_ws(n) u32
+size_t exclusive_scan_ws(int64_t n);
+spt_status launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *ws, hipStream_t s);
 spt_status sort_u64_keys_ws(uint64_t *keys, uint64_t *keys2, uint32_t *idx_a, uint32_t *idx_b, uint32_t *counts,
                             int64_t n, int nbits, uint64_t **sorted_out, uint32_t **idx_out, hipStream_t s);
 
@@ -137,13 +147,22 @@ struct MttkrpArgs {
     uint64_t *rec_row;
     float *rec_val;
     const int64_t *rec_off;   // per tile, ntiles + 1 entries
+    // SEGMENT with row-grouped records: per-tile (row, first record) pairs
+    const uint32_t *pair_row;
+    const uint32_t *pair_dest;
+    const int64_t *pair_off;
+    int64_t rec_cap;          // records the plan laid out (writes beyond are dropped)
     Codec codec;
 };
 spt_status launch_fill_zero(float *p, int64_t n, hipStream_t s);
 MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int mode, float *out, int tile);
 spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s);
 bool seg_tile_ok(int tile, int nmodes);
+// per tile: pieces | distinct rows << 32
 spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s);
+// per tile, at a.pair_off[tile]: row of every distinct (tile, row) pair (also as
+// a u64 sort key) and its pieces
+spt_status launch_emit_pairs(const MttkrpArgs &a, uint32_t *rows, uint64_t *keys, uint32_t *pieces, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 
 // Batched SEGMENT MTTKRP: every tensor's tiles of kBatchTile nonzeros in one
