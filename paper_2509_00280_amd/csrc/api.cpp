@@ -293,7 +293,7 @@ void tensor_release(Tensor *t, hipStream_t s) {
     if (!t) return;
     bool host_sync = false;
     for (int n = 0; n < kMaxModes; ++n)
-        host_sync |= t->mplan[n].rec_off || t->mplan[n].pair_off || t->mplan[n].pair_row || t->mplan[n].pair_dest;
+        host_sync |= t->mplan[n].rec_off || t->mplan[n].pl_off || t->mplan[n].pl_pos;
     for (int i = 0; i < WS_NSLOTS; ++i) host_sync |= t->ws[i] != nullptr;
     if (host_sync) {
         (void)hipStreamSynchronize(s);

@@ -38,13 +38,18 @@ namespace {
 constexpr int kPiece = SPT_SEG_PIECE;  // nonzeros per piece (L)
 constexpr int kUnroll = SPT_SEG_UB;    // nonzeros in flight per lane group
 
-// LDS: crdg[nm - 1][T] u32 (non-output coordinates, row-grouped), valg[T] f32,
-// hkey[T] u32 (slot -> row), hcnt[T + 4] u32 (packed counts, then prefixes;
-// entry T holds the totals), ptab[T] u16 (piece -> slot), and with row-grouped
-// records sdest[T] u32 (slot -> first record of the slot's pieces).
-__host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes, bool dest = false) {
-    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2 +
-           (dest ? (size_t)T * 4 : 0);
+// LDS of the hashing stage: crdg[nm - 1][T] u32 (non-output coordinates,
+// row-grouped), valg[T] f32, hkey[T] u32 (slot -> row), hcnt[T + 4] u32
+// (packed counts, then prefixes; entry T holds the totals), ptab[T] u16
+// (piece -> slot).
+__host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes) {
+    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2;
+}
+
+// LDS of the planned kernel: crdg[nm - 1][T], valg[T], and the tile's pieces
+// (at most T): pdesc (start | length << 16), prow, pdst (record).
+__host__ __device__ inline size_t segp_lds_bytes(int T, int nmodes) {
+    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + 3 * (size_t)T * 4;
 }
 
 struct SegLds {
@@ -53,7 +58,6 @@ struct SegLds {
     uint32_t *hkey;
     uint32_t *hcnt;
     uint16_t *ptab;
-    uint32_t *sdest;
 };
 
 __device__ __forceinline__ SegLds seg_carve(char *p, int T, int nmodes) {
@@ -63,30 +67,18 @@ __device__ __forceinline__ SegLds seg_carve(char *p, int T, int nmodes) {
     L.hkey = (uint32_t *)(L.valg + T);
     L.hcnt = L.hkey + T;
     L.ptab = (uint16_t *)(L.hcnt + T + 4);
-    L.sdest = (uint32_t *)(L.ptab + T);
     return L;
-}
-
-// slot of `row` in the tile's hash, or T if it is absent (bounded probe)
-template <int T>
-__device__ __forceinline__ uint32_t seg_find(const uint32_t *hkey, uint32_t row) {
-    uint32_t s = mix_hash(row) & (uint32_t)(T - 1);
-    for (int n = 0; n < T; ++n) {
-        const uint32_t h = hkey[s];
-        if (h == row) return s;
-        if (h == kNoRow) return T;
-        s = (s + 1) & (uint32_t)(T - 1);
-    }
-    return T;
 }
 
 // Stage and regroup one tile.  After return: hcnt[s] = (first position of
 // slot s) << 16 | (first piece of slot s); hcnt[T] = (cnt << 16) | pieces;
 // crdg/valg hold the tile in row-grouped order and ptab maps pieces to slots.
 // With SCATTER false only the counts are formed (the plan's counting pass).
+// With pos_out (counting mode only) the row-grouped position of every element
+// is written to pos_out[tile * T + e] and the piece table is built as well.
 template <int NT, int NMAX, bool SCATTER>
 __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, const SegLds &L, const CodecRegs &cr,
-                                          uint32_t *wsum) {
+                                          uint32_t *wsum, uint16_t *__restrict__ pos_out = nullptr) {
     constexpr int T = 4 * NT;
     const int tid = threadIdx.x;
     const int64_t base = tile * (int64_t)T;
@@ -177,17 +169,21 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
         const uint32_t own = (uint32_t)cnt - el;
         L.hcnt[T] = ((uint32_t)cnt << 16) | (pl + (own + kPiece - 1) / kPiece);
     }
-    if constexpr (SCATTER) {
+    if (SCATTER || pos_out) {
         const int nm = a.nmodes, mode = a.mode;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = tid + u * NT;
             if (e < cnt) {
                 const int pos = (int)(L.hcnt[sr[u] >> 16] >> 16) + (int)(sr[u] & 0xFFFFu);
-                L.valg[pos] = v[u];
+                if constexpr (SCATTER) {
+                    L.valg[pos] = v[u];
 #pragma unroll
-                for (int k = 0; k < NMAX; ++k)
-                    if (k < nm && k != mode) L.crdg[(k - (k > mode)) * T + pos] = xc[k][u];
+                    for (int k = 0; k < NMAX; ++k)
+                        if (k < nm && k != mode) L.crdg[(k - (k > mode)) * T + pos] = xc[k][u];
+                } else {
+                    pos_out[base + e] = (uint16_t)pos;
+                }
             }
         }
         __syncthreads();  // totals visible
@@ -202,21 +198,21 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
     __syncthreads();
 }
 
-// Walk the staged tile: every piece becomes record rbase + piece of
-// ld floats (columns R..ld-1 zero) whose row is row_base + the piece's row.
+// Walk the staged tile: every piece (nonzeros [p0, p1) of the row-grouped
+// tile, one output row) becomes one record of ld floats (columns R..ld-1
+// zero) at the position the piece source gives, with row row_base + its row.
 // EXACT: the lane groups cover exactly R columns (no column mask).
 // With at most 4 modes every nonzero slot of an unrolled step reads all its
 // coordinates from LDS first, then issues every factor-row gather, then waits
 // once; with more modes the gathers go mode by mode.
-// DEST: piece i of slot s goes to record sdest[s] + i (records grouped by
-// row); otherwise piece k of the tile goes to record rbase + k.
-template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT, bool DEST = false>
-__device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, uint64_t *__restrict__ rec_row,
-                                         float *__restrict__ rec_val, int64_t rbase, int ld, int64_t row_base) {
+template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT, class Pieces>
+__device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__restrict__ crdg,
+                                         const float *__restrict__ valg, int npieces, const Pieces &pieces,
+                                         uint64_t *__restrict__ rec_row, float *__restrict__ rec_val, int ld,
+                                         int64_t row_base) {
     constexpr int T = 4 * NT;
     constexpr int UB = kUnroll;
     constexpr int NO = NMAX - 1;  // non-output modes at most
-    const int npieces = (int)(L.hcnt[T] & 0xFFFFu);
     const int j = threadIdx.x % G;
     const int R = a.rank, mode = a.mode, no = a.nmodes - 1;
     const uint32_t Ru = (uint32_t)R;
@@ -225,12 +221,10 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
 #pragma unroll
     for (int o = 0; o < NO; ++o) fo[o] = o < no ? a.f[o + (o >= mode)] : nullptr;
     for (int k = threadIdx.x / G; k < npieces; k += NT / G) {
-        const int s = L.ptab[k];
-        const uint32_t pk = L.hcnt[s];
-        const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
-        const int first = (int)(pk >> 16), last = (int)(pn >> 16);
-        const int p0 = first + (k - (int)(pk & 0xFFFFu)) * kPiece;
-        const int p1 = min(p0 + kPiece, last);
+        int p0, p1;
+        uint32_t prow;
+        int64_t pos;
+        if (!pieces(k, p0, p1, prow, pos)) continue;
         float acc[NB][VEC];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -243,7 +237,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
             for (int u = 0; u < UB; ++u) {
                 const bool ok = q + u < p1;
                 pp[u] = ok ? q + u : p1 - 1;  // in range either way; the value is zeroed
-                const float v = L.valg[pp[u]];
+                const float v = valg[pp[u]];
                 x[u] = ok ? v : 0.f;
             }
             float p[UB][NB][VEC];
@@ -259,7 +253,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
                 for (int o = 0; o < NO; ++o)
                     if (o < no)
 #pragma unroll
-                        for (int u = 0; u < UB; ++u) row[o][u] = L.crdg[o * T + pp[u]];
+                        for (int u = 0; u < UB; ++u) row[o][u] = crdg[o * T + pp[u]];
                 float xv[NO][UB][NB][VEC];
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
@@ -296,7 +290,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
                         float xv[UB][NB][VEC];
 #pragma unroll
                         for (int u = 0; u < UB; ++u) {
-                            const float *fr = fo[o] + (uint64_t)L.crdg[o * T + pp[u]] * Ru;
+                            const float *fr = fo[o] + (uint64_t)crdg[o * T + pp[u]] * Ru;
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 const int c = (b * G + j) * VEC;
@@ -324,10 +318,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) acc[b][v] += p[u][b][v];
         }
-        const int64_t pos = DEST ? (int64_t)L.sdest[s] + (k - (int)(pk & 0xFFFFu)) : rbase + k;
-        // with plan-given slots, a record outside the plan's range is never written
-        if (DEST && (L.sdest[s] == kNoRow || pos >= a.rec_cap)) continue;
-        if (j == 0) rec_row[pos] = (uint64_t)(row_base + L.hkey[s]);
+        if (j == 0) rec_row[pos] = (uint64_t)(row_base + prow);
         float *o = rec_val + pos * ld;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -345,37 +336,193 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const SegLds &L, u
     }
 }
 
+// Pieces of a tile regrouped by the hashing stage: piece k is the
+// (k - first piece)-th run of L nonzeros of slot ptab[k]; record rbase + k.
+template <int T>
+struct HashPieces {
+    const SegLds L;
+    int64_t rbase;
+    __device__ __forceinline__ bool operator()(int k, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
+        const int s = L.ptab[k];
+        const uint32_t pk = L.hcnt[s];
+        const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
+        const int first = (int)(pk >> 16), last = (int)(pn >> 16);
+        p0 = first + (k - (int)(pk & 0xFFFFu)) * kPiece;
+        p1 = min(p0 + kPiece, last);
+        row = L.hkey[s];
+        pos = rbase + k;
+        return true;
+    }
+};
+
+// Pieces given by the plan (staged in LDS).  Reads stay inside the tile and
+// a record outside the plan's range is never written, whatever the plan holds.
+template <int T>
+struct PlanPieces {
+    const uint32_t *pdesc, *prow, *pdst;
+    int64_t cap;
+    __device__ __forceinline__ bool operator()(int k, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
+        const uint32_t d = pdesc[k];
+        p0 = (int)(d & 0xFFFFu);
+        p1 = min(p0 + (int)(d >> 16), T);
+        row = prow[k];
+        pos = pdst[k];
+        return pos < cap && p0 < p1;
+    }
+};
+
+// Planned SEGMENT kernel.  The plan holds, per nonzero, its position in the
+// tile's row-grouped order (u16) and, per piece, (start | length << 16, row,
+// record), with the records of one row contiguous.  A tile is staged by one
+// scatter of values and non-output coordinates to their positions; there is
+// no hashing, no atomic and no scan at run time.
 template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
-__global__ __launch_bounds__(NT) void k_mttkrp_seg(MttkrpArgs a, int64_t ntiles) {
+__global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles) {
+    constexpr int T = 4 * NT;
+    extern __shared__ __align__(16) char lds[];
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int nm = a.nmodes, mode = a.mode, tid = threadIdx.x;
+    uint32_t *crdg = (uint32_t *)lds;
+    float *valg = (float *)(crdg + (size_t)(nm - 1) * T);
+    uint32_t *pdesc = (uint32_t *)(valg + T);
+    uint32_t *prow = pdesc + T;
+    uint32_t *pdst = prow + T;
+    const CodecRegs cr = load_codec_regs(a.codec);
+    // the tile's pieces (at most T) and its nonzeros, all loads issued first
+    const int64_t k0 = a.pl_off[tile], k1 = min(a.pl_off[tile + 1], k0 + T);  // a tile has at most T pieces
+    const int npieces = (int)(k1 - k0);
+    uint32_t qd[4], qr[4], qx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + tid + u * NT;
+        const bool ok = k < k1;
+        qd[u] = ok ? a.pl_desc[k] : 0u;
+        qr[u] = ok ? a.pl_row[k] : 0u;
+        qx[u] = ok ? a.pl_dest[k] : 0u;
+    }
+    const int64_t base = tile * (int64_t)T;
+    const int64_t rem = a.nnz - base;
+    const int cnt = rem < T ? (int)rem : T;
+    const int nwords = 2 * a.codec.key_words;
+    uint32_t w[4][4];
+    float v[4];
+    int ps[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT;
+        uint64_t klo = 0, khi = 0;
+        float x = 0.f;
+        int q = 0;
+        if (e < cnt) {
+            klo = __builtin_nontemporal_load(a.lo + base + e);
+            if (nwords == 4) khi = __builtin_nontemporal_load(a.hi + base + e);
+            x = __builtin_nontemporal_load(a.vals + base + e);
+            q = a.pl_pos[base + e] & (T - 1);  // a position inside the tile
+        }
+        w[u][0] = (uint32_t)klo;
+        w[u][1] = (uint32_t)(klo >> 32);
+        w[u][2] = (uint32_t)khi;
+        w[u][3] = (uint32_t)(khi >> 32);
+        v[u] = x;
+        ps[u] = q;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (tid + u * NT < npieces) {
+            pdesc[tid + u * NT] = qd[u];
+            prow[tid + u * NT] = qr[u];
+            pdst[tid + u * NT] = qx[u];
+        }
+    }
+    // decode the non-output coordinates and scatter them with the values
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+        if (k < nm && k != mode) {
+            uint32_t x[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int word = 0; word < 4; ++word) {
+                if (word < nwords) {
+                    const int r0 = __builtin_amdgcn_readlane(cr.rb, k * 5 + word);
+                    const int r1 = __builtin_amdgcn_readlane(cr.rb, k * 5 + word + 1);
+                    for (int r = r0; r < r1; ++r) {
+                        const uint32_t d = run_desc(cr, r);
+                        const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) x[u] |= __builtin_amdgcn_ubfe(w[u][word], kpos, len) << cpos;
+                    }
+                }
+            }
+            const int o = k - (k > mode);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (tid + u * NT < cnt) crdg[o * T + ps[u]] = x[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (tid + u * NT < cnt) valg[ps[u]] = v[u];
+    __syncthreads();
+    seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, crdg, valg, npieces, PlanPieces<T>{pdesc, prow, pdst, a.rec_cap},
+                                          a.rec_row, a.rec_val, a.rank, 0);
+}
+
+// The plan of one mode: positions of every nonzero, and per piece its
+// (start | length << 16), row, and (for the record layout) its pair and index
+// within the pair; per distinct (tile, row) pair its row (sort key) and pieces.
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_emit_plan(MttkrpArgs a, int64_t ntiles, const int64_t *__restrict__ pair_off,
+                                                  uint16_t *__restrict__ pos, uint32_t *__restrict__ desc,
+                                                  uint32_t *__restrict__ prow, uint32_t *__restrict__ ppair,
+                                                  uint32_t *__restrict__ psub, uint64_t *__restrict__ pair_key,
+                                                  uint32_t *__restrict__ pair_np) {
     constexpr int T = 4 * NT;
     extern __shared__ __align__(16) char lds[];
     __shared__ uint32_t wsum[NT / 64];
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
+    const int64_t tile = blockIdx.x;
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
-    // the plan's (row, first record) pairs of this tile (at most T), loaded
-    // before the stage so their latency hides behind it
-    const int64_t q0 = a.pair_off[tile], q1 = a.pair_off[tile + 1];
-    uint32_t prow[4], pdst[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t q = q0 + threadIdx.x + u * NT;
-        prow[u] = q < q1 ? a.pair_row[q] : kNoRow;
-        pdst[u] = q < q1 ? a.pair_dest[q] : kNoRow;
-    }
-    for (int i = threadIdx.x; i < T; i += NT) L.sdest[i] = kNoRow;  // ordered by the stage's barriers
-    seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
-    // first record of every slot; a slot the plan does not name keeps the marker
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        if (prow[u] != kNoRow) {
-            const uint32_t slot = seg_find<T>(L.hkey, prow[u]);
-            if (slot < (uint32_t)T) L.sdest[slot] = pdst[u];
-        }
+    seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum, pos);
+    // pair index of every occupied slot: exclusive count of occupied slots before it
+    uint32_t *occ = (uint32_t *)L.valg;  // free in counting mode; T entries
+    for (int i = threadIdx.x; i < T; i += NT) {
+        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
+        occ[i] = (nx >> 16) != (L.hcnt[i] >> 16) ? 1u : 0u;
     }
     __syncthreads();
-    seg_walk<NT, G, VEC, NB, NMAX, EXACT, true>(a, L, a.rec_row, a.rec_val, 0, a.rank, 0);
+    block_scan_lds(occ, T, NT, wsum);
+    const int64_t pbase = a.pl_off[tile], qbase = pair_off[tile];
+    for (int i = threadIdx.x; i < T; i += NT) {
+        const uint32_t pk = L.hcnt[i];
+        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
+        const uint32_t c = (nx >> 16) - (pk >> 16);
+        if (c > 0) {
+            pair_key[qbase + occ[i]] = L.hkey[i];
+            pair_np[qbase + occ[i]] = (c + kPiece - 1) / kPiece;
+        }
+    }
+    const int npieces = (int)(L.hcnt[T] & 0xFFFFu);
+    for (int k = threadIdx.x; k < npieces; k += NT) {
+        const int s = L.ptab[k];
+        const uint32_t pk = L.hcnt[s];
+        const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
+        const int first = (int)(pk >> 16), last = (int)(pn >> 16);
+        const int i = k - (int)(pk & 0xFFFFu);
+        const int p0 = first + i * kPiece;
+        const int p1 = min(p0 + kPiece, last);
+        desc[pbase + k] = (uint32_t)p0 | ((uint32_t)(p1 - p0) << 16);
+        prow[pbase + k] = L.hkey[s];
+        ppair[pbase + k] = (uint32_t)(qbase + occ[s]);
+        psub[pbase + k] = (uint32_t)i;
+    }
+}
+
+// dest[k] = first record of piece k's pair + its index within the pair
+__global__ __launch_bounds__(256) void k_piece_dest(const uint32_t *__restrict__ ppair, const uint32_t *__restrict__ psub,
+                                                    const uint32_t *__restrict__ pair_first, uint32_t *__restrict__ dest,
+                                                    int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+        dest[k] = pair_first[ppair[k]] + psub[k];
 }
 
 // Batched: tile `it` of the whole batch belongs to the last item whose
@@ -406,7 +553,9 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg_batched(const SegItem *__rest
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
-    seg_walk<NT, G, VEC, NB, NMAX, false>(a, L, rec_row, rec_val, item.rec_base + a.rec_off[tile], ld, item.row_base);
+    seg_walk<NT, G, VEC, NB, NMAX, false>(a, L.crdg, L.valg, (int)(L.hcnt[T] & 0xFFFFu),
+                                          HashPieces<T>{L, item.rec_base + a.rec_off[tile]}, rec_row, rec_val, ld,
+                                          item.row_base);
 }
 
 // Pieces of every tile (the plan's counting pass).
@@ -433,34 +582,6 @@ __global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntile
     if (threadIdx.x == 0) out[tile] = (int64_t)(L.hcnt[T] & 0xFFFFu) | ((int64_t)s_distinct << 32);
 }
 
-// The (row, pieces) pair of every distinct row of every tile, written at
-// a.pair_off[tile] in the tile's slot order.
-template <int NT, int NMAX>
-__global__ __launch_bounds__(NT) void k_emit_pairs(MttkrpArgs a, int64_t ntiles, uint32_t *__restrict__ rows,
-                                                   uint64_t *__restrict__ keys, uint32_t *__restrict__ pieces) {
-    constexpr int T = 4 * NT;
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[NT / 64];
-    __shared__ uint32_t s_n;
-    const int64_t tile = blockIdx.x;
-    const SegLds L = seg_carve(lds, T, a.nmodes);
-    const CodecRegs cr = load_codec_regs(a.codec);
-    if (threadIdx.x == 0) s_n = 0;
-    seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
-    const int64_t base = a.pair_off[tile];
-    for (int i = threadIdx.x; i < T; i += NT) {
-        const uint32_t pk = L.hcnt[i];
-        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
-        const uint32_t c = (nx >> 16) - (pk >> 16);
-        if (c > 0) {
-            const uint32_t q = atomicAdd(&s_n, 1u);
-            rows[base + q] = L.hkey[i];
-            keys[base + q] = L.hkey[i];
-            pieces[base + q] = (c + kPiece - 1) / kPiece;
-        }
-    }
-}
-
 template <int NT, int NMAX>
 __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__restrict__ items, int count,
                                                              int64_t total_tiles, int64_t *__restrict__ out) {
@@ -478,11 +599,11 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
 
 template <int NT, int NMAX, int G, int VEC, int NB>
 spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
-    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes, true);
+    const size_t lds = segp_lds_bytes(4 * NT, a.nmodes);
     if (a.rank == G * VEC * NB)
-        hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
     else
-        hipLaunchKernelGGL((k_mttkrp_seg<NT, G, VEC, NB, NMAX, false>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, false>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
@@ -507,13 +628,14 @@ spt_status launch_seg_nt(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
 }
 
 template <int NT>
-spt_status launch_emit_nt(const MttkrpArgs &a, int64_t ntiles, uint32_t *rows, uint64_t *keys, uint32_t *pieces,
-                          hipStream_t s) {
+spt_status launch_emit_nt(const MttkrpArgs &a, int64_t ntiles, const PlanOut &o, hipStream_t s) {
     const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
     if (a.nmodes <= 4)
-        hipLaunchKernelGGL((k_emit_pairs<NT, 4>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, rows, keys, pieces);
+        hipLaunchKernelGGL((k_emit_plan<NT, 4>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, o.pair_off, o.pos,
+                           o.desc, o.prow, o.ppair, o.psub, o.pair_key, o.pair_np);
     else
-        hipLaunchKernelGGL((k_emit_pairs<NT, 8>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, rows, keys, pieces);
+        hipLaunchKernelGGL((k_emit_plan<NT, 8>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, o.pair_off, o.pos,
+                           o.desc, o.prow, o.ppair, o.psub, o.pair_key, o.pair_np);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
@@ -534,16 +656,25 @@ spt_status launch_count_nt(const MttkrpArgs &a, int64_t ntiles, int64_t *out, hi
 // tile sizes served: 1024 (256 threads), 2048 (512), 4096 (1024 threads)
 bool seg_tile_ok(int tile, int nmodes) {
     if (tile != 1024 && tile != 2048 && tile != 4096) return false;
-    return seg_lds_bytes(tile, nmodes, true) <= 160 * 1024 - 1024;
+    return seg_lds_bytes(tile, nmodes) <= 160 * 1024 - 1024 && segp_lds_bytes(tile, nmodes) <= 160 * 1024 - 1024;
 }
 
-spt_status launch_emit_pairs(const MttkrpArgs &a, uint32_t *rows, uint64_t *keys, uint32_t *pieces, hipStream_t s) {
+spt_status launch_emit_plan(const MttkrpArgs &a, const PlanOut &o, hipStream_t s) {
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
     if (ntiles == 0) return SPT_OK;
     if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
-    if (a.tile == 1024) return launch_emit_nt<256>(a, ntiles, rows, keys, pieces, s);
-    if (a.tile == 2048) return launch_emit_nt<512>(a, ntiles, rows, keys, pieces, s);
-    return launch_emit_nt<1024>(a, ntiles, rows, keys, pieces, s);
+    if (a.tile == 1024) return launch_emit_nt<256>(a, ntiles, o, s);
+    if (a.tile == 2048) return launch_emit_nt<512>(a, ntiles, o, s);
+    return launch_emit_nt<1024>(a, ntiles, o, s);
+}
+
+spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first, uint32_t *dest,
+                             int64_t n, hipStream_t s) {
+    if (n == 0) return SPT_OK;
+    const int64_t g = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_piece_dest, dim3((unsigned)g), dim3(256), 0, s, ppair, psub, pair_first, dest, n);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
 }
 
 spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s) {

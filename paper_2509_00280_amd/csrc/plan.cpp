@@ -112,7 +112,8 @@ void release_ws(Tensor *t) {
 
 void release_mode_plan(Tensor *t, int n) {
     ModePlan &p = t->mplan[n];
-    for (void *q : {(void *)p.rec_off, (void *)p.pair_row, (void *)p.pair_dest, (void *)p.pair_off})
+    for (void *q : {(void *)p.rec_off, (void *)p.pl_pos, (void *)p.pl_off, (void *)p.pl_desc, (void *)p.pl_row,
+                    (void *)p.pl_dest})
         if (q) (void)hipFree(q);
     p = ModePlan{};
 }
@@ -135,64 +136,80 @@ int segment_tile(const Tensor *t, int mode) {
 }
 
 // SEGMENT plan (once per tensor and mode; synchronises s once).  A tile's
-// records are its pieces (runs of at most L nonzeros of one row), so
+// records are its pieces (runs of at most L nonzeros of one row).
 //  1. a counting pass gives every tile's pieces and distinct rows;
-//  2. every distinct (tile, row) pair is emitted with its piece count, tile-major;
+//  2. the emission pass (same regrouping) writes every nonzero's position in
+//     its tile's row-grouped order, every piece's start, length and row, and
+//     every distinct (tile, row) pair with its piece count, tile-major;
 //  3. a stable sort of the pairs by row (tile order kept within a row) and an
 //     exclusive scan of their piece counts give each pair its first record,
-//     so the records of one row come out contiguous and need no sort per call.
+//     so the records of one row are contiguous; each piece's record follows.
+// Calls then stage a tile with one scatter and write records in row order.
 spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan &p) {
     p.ts = segment_tile(t, mode);
     const int64_t ntiles = (t->nnz + p.ts - 1) / p.ts;
-    std::vector<int64_t> h(ntiles + 1, 0);
-    SPT_HIP(hipMalloc(&p.pair_off, sizeof(int64_t) * (ntiles + 1)));
+    std::vector<int64_t> h(ntiles + 1, 0), hq(ntiles + 1, 0);
+    SPT_HIP(hipMalloc(&p.pl_off, sizeof(int64_t) * (ntiles + 1)));
     if (ntiles > 0) {
-        spt_status st = launch_count_pieces(make_args(t, nullptr, rank, mode, nullptr, p.ts), p.pair_off, s);
+        spt_status st = launch_count_pieces(make_args(t, nullptr, rank, mode, nullptr, p.ts), p.pl_off, s);
         if (st != SPT_OK) return st;
-        SPT_HIP(hipMemcpyAsync(h.data(), p.pair_off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s));
+        SPT_HIP(hipMemcpyAsync(h.data(), p.pl_off, sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s));
         SPT_HIP(hipStreamSynchronize(s));
     }
     int64_t pieces = 0, pairs = 0;
     for (int64_t i = 0; i < ntiles; ++i) {
         const int64_t c = h[i];
+        h[i] = pieces;
+        hq[i] = pairs;
         pieces += c & 0xFFFFFFFFll;
-        h[i] = pairs;
         pairs += c >> 32;
     }
-    h[ntiles] = pairs;
+    h[ntiles] = pieces;
+    hq[ntiles] = pairs;
     p.records = pieces;
     if (pieces >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "plan: more than 2^32 records");
-    SPT_HIP(hipMemcpy(p.pair_off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice));
-    const size_t q1 = (size_t)std::max<int64_t>(pairs, 1);
-    SPT_HIP(hipMalloc(&p.pair_row, sizeof(uint32_t) * q1));
-    SPT_HIP(hipMalloc(&p.pair_dest, sizeof(uint32_t) * q1));
-    if (pairs == 0) return SPT_OK;
+    SPT_HIP(hipMemcpy(p.pl_off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice));
+    const size_t n1 = (size_t)std::max<int64_t>(t->nnz, 1), k1 = (size_t)std::max<int64_t>(pieces, 1),
+                 q1 = (size_t)std::max<int64_t>(pairs, 1);
+    SPT_HIP(hipMalloc(&p.pl_pos, sizeof(uint16_t) * n1));
+    SPT_HIP(hipMalloc(&p.pl_desc, sizeof(uint32_t) * k1));
+    SPT_HIP(hipMalloc(&p.pl_row, sizeof(uint32_t) * k1));
+    SPT_HIP(hipMalloc(&p.pl_dest, sizeof(uint32_t) * k1));
+    if (pieces == 0) return SPT_OK;
+    int64_t *pair_off = (int64_t *)dev_alloc(sizeof(int64_t) * (ntiles + 1), s);
+    uint32_t *ppair = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
+    uint32_t *psub = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
     uint64_t *keys = (uint64_t *)dev_alloc(sizeof(uint64_t) * q1, s);
     uint64_t *keys2 = (uint64_t *)dev_alloc(sizeof(uint64_t) * q1, s);
     uint32_t *np = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
     uint32_t *ia = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
     uint32_t *ib = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
     uint32_t *cnt = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max(sort_ws_counts(pairs), exclusive_scan_ws(pairs)), s);
-    spt_status st = (keys && keys2 && np && ia && ib && cnt) ? SPT_OK : fail(SPT_E_OOM, "plan: pair workspace");
+    spt_status st = (pair_off && ppair && psub && keys && keys2 && np && ia && ib && cnt)
+                        ? SPT_OK
+                        : fail(SPT_E_OOM, "plan: workspace");
+    if (st == SPT_OK &&
+        hipMemcpyAsync(pair_off, hq.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "plan: pair offsets");
     MttkrpArgs a = make_args(t, nullptr, rank, mode, nullptr, p.ts);
-    a.pair_off = p.pair_off;
-    if (st == SPT_OK) st = launch_emit_pairs(a, p.pair_row, keys, np, s);
+    a.pl_off = p.pl_off;
+    PlanOut o{pair_off, p.pl_pos, p.pl_desc, p.pl_row, ppair, psub, keys, np};
+    if (st == SPT_OK) st = launch_emit_plan(a, o, s);
     uint64_t *sk = nullptr;
     uint32_t *sidx = nullptr;
     if (st == SPT_OK) st = sort_u64_keys_ws(keys, keys2, ia, ib, cnt, pairs, t->lbits[mode], &sk, &sidx, s);
-    // pieces in row order -> their exclusive prefix -> back to emission order
+    // pair pieces in row order -> exclusive prefix -> first record of each pair (emission order)
     uint32_t *np_sorted = (sidx == ia) ? ib : ia;
-    uint32_t *first = (uint32_t *)keys2;  // free once the sort is done (its keys are not needed)
-    if (sk == keys2) first = (uint32_t *)keys;
+    uint32_t *tmp = (uint32_t *)((sk == keys2) ? keys : keys2);  // the unsorted key buffer is free now
+    uint32_t *pair_first = tmp + q1;                               // second half of that buffer
     if (st == SPT_OK) st = launch_gather_u32(np, sidx, np_sorted, pairs, s);
-    if (st == SPT_OK) st = launch_exclusive_scan_u32(np_sorted, first, pairs, cnt, s);
-    if (st == SPT_OK) st = launch_scatter_u32(first, sidx, p.pair_dest, pairs, s);
-    dev_free(keys, s);
-    dev_free(keys2, s);
-    dev_free(np, s);
-    dev_free(ia, s);
-    dev_free(ib, s);
-    dev_free(cnt, s);
+    if (st == SPT_OK) st = launch_exclusive_scan_u32(np_sorted, tmp, pairs, cnt, s);
+    if (st == SPT_OK) st = launch_scatter_u32(tmp, sidx, pair_first, pairs, s);
+    if (st == SPT_OK) st = launch_piece_dest(ppair, psub, pair_first, p.pl_dest, pieces, s);
+    if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "plan: build");
+    for (void *q : {(void *)pair_off, (void *)ppair, (void *)psub, (void *)keys, (void *)keys2, (void *)np, (void *)ia,
+                    (void *)ib, (void *)cnt})
+        dev_free(q, s);
     return st;
 }
 
@@ -209,7 +226,7 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
         *out = &p;
         return SPT_OK;
     }
-    if (p.rec_off || p.pair_off || p.pair_row || p.pair_dest) {
+    if (p.rec_off || p.pl_off || p.pl_pos || p.pl_desc || p.pl_row || p.pl_dest) {
         (void)hipStreamSynchronize(s);  // the previous plan's arrays may still be in use
         release_mode_plan(t, mode);
     }
@@ -393,9 +410,11 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
     const int64_t rows = t->dims[mode];
     if (p->strategy == SPT_STRATEGY_SEGMENT && t->nnz > 0) {
         MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
-        a.pair_row = p->pair_row;
-        a.pair_dest = p->pair_dest;
-        a.pair_off = p->pair_off;
+        a.pl_pos = p->pl_pos;
+        a.pl_off = p->pl_off;
+        a.pl_desc = p->pl_desc;
+        a.pl_row = p->pl_row;
+        a.pl_dest = p->pl_dest;
         a.rec_cap = p->records;
         return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/true);
     }

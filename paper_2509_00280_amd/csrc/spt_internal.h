@@ -62,11 +62,12 @@ struct ModePlan {
     int64_t sub_per_wg = 0;
     int64_t records = 0;     // TABLE / SEGMENT: records written per call
     int64_t *rec_off = nullptr;  // TABLE: device, nwg offsets
-    // SEGMENT: the distinct (tile, row) pairs of every tile (tile-major,
-    // pair_off[tile] .. pair_off[tile + 1]), each with the first record slot
-    // of its pieces; slots are laid out so that records are grouped by row
-    uint32_t *pair_row = nullptr, *pair_dest = nullptr;
-    int64_t *pair_off = nullptr;
+    // SEGMENT plan: per nonzero its position in the tile's row-grouped order;
+    // per piece (tile-major, pl_off[tile] .. pl_off[tile + 1]) its
+    // start | length << 16, row and record (records of one row contiguous)
+    uint16_t *pl_pos = nullptr;
+    int64_t *pl_off = nullptr;
+    uint32_t *pl_desc = nullptr, *pl_row = nullptr, *pl_dest = nullptr;
 };
 
 // Grow-only device buffers owned by a tensor handle and reused by its MTTKRP
@@ -147,10 +148,10 @@ struct MttkrpArgs {
     uint64_t *rec_row;
     float *rec_val;
     const int64_t *rec_off;   // per tile, ntiles + 1 entries
-    // SEGMENT with row-grouped records: per-tile (row, first record) pairs
-    const uint32_t *pair_row;
-    const uint32_t *pair_dest;
-    const int64_t *pair_off;
+    // SEGMENT plan (see ModePlan)
+    const uint16_t *pl_pos;
+    const int64_t *pl_off;
+    const uint32_t *pl_desc, *pl_row, *pl_dest;
     int64_t rec_cap;          // records the plan laid out (writes beyond are dropped)
     Codec codec;
 };
@@ -160,9 +161,17 @@ spt_status launch_mttkrp(const MttkrpArgs &a, int strategy, hipStream_t s);
 bool seg_tile_ok(int tile, int nmodes);
 // per tile: pieces | distinct rows << 32
 spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t s);
-// per tile, at a.pair_off[tile]: row of every distinct (tile, row) pair (also as
-// a u64 sort key) and its pieces
-spt_status launch_emit_pairs(const MttkrpArgs &a, uint32_t *rows, uint64_t *keys, uint32_t *pieces, hipStream_t s);
+// outputs of the plan-emission pass (a.pl_off must hold the piece offsets)
+struct PlanOut {
+    const int64_t *pair_off;  // per tile, distinct (tile, row) pairs
+    uint16_t *pos;            // nnz
+    uint32_t *desc, *prow, *ppair, *psub;  // per piece
+    uint64_t *pair_key;       // per pair: its row (sort key)
+    uint32_t *pair_np;        // per pair: its pieces
+};
+spt_status launch_emit_plan(const MttkrpArgs &a, const PlanOut &o, hipStream_t s);
+spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first, uint32_t *dest,
+                             int64_t n, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 
 // Batched SEGMENT MTTKRP: every tensor's tiles of kBatchTile nonzeros in one
