@@ -87,8 +87,8 @@ typedef struct {
 typedef struct {
     int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256..1024 for DIRECT/REGROUP (larger
                                      values act as 1024), 1024/2048/4096 for SEGMENT (smaller values,
-                                     and 4096 when it does not fit LDS for this mode count, act as
-                                     2048); default 2048 */
+                                     or a tile that does not fit LDS for this mode count, act as the
+                                     largest that fits); default 4096 */
     int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
 } spt_plan;
 

@@ -103,7 +103,7 @@ static int bit_length(int64_t d) {  // ceil(log2 d) for d >= 1
 
 static void default_plan(const Tensor *t, spt_plan *p) {
     for (int n = 0; n < kMaxModes; ++n) {
-        p->tile[n] = 2048;
+        p->tile[n] = 4096;
         p->strategy[n] = SPT_STRATEGY_AUTO;
     }
     (void)t;

@@ -46,10 +46,9 @@ __host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes) {
     return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2;
 }
 
-// LDS of the planned kernel: crdg[nm - 1][T], valg[T], and the tile's pieces
-// (at most T): pdesc (start | length << 16), prow, pdst (record).
+// LDS of the planned kernel: crdg[nm - 1][T] and valg[T].
 __host__ __device__ inline size_t segp_lds_bytes(int T, int nmodes) {
-    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + 3 * (size_t)T * 4;
+    return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4;
 }
 
 struct SegLds {
@@ -220,11 +219,19 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
     const float *fo[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) fo[o] = o < no ? a.f[o + (o >= mode)] : nullptr;
-    for (int k = threadIdx.x / G; k < npieces; k += NT / G) {
+    constexpr int NG = NT / G;
+    if (npieces <= 0) return;
+    int k = threadIdx.x / G;
+    typename Pieces::Raw cur = pieces.fetch(k < npieces ? k : 0);
+    for (; k < npieces; k += NG) {
+        // the next piece's descriptor is fetched while this one is walked
+        const typename Pieces::Raw nxt = pieces.fetch(k + NG < npieces ? k + NG : k);
         int p0, p1;
         uint32_t prow;
         int64_t pos;
-        if (!pieces(k, p0, p1, prow, pos)) continue;
+        const bool live = pieces.decode(k, cur, p0, p1, prow, pos);
+        cur = nxt;
+        if (!live) continue;
         float acc[NB][VEC];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -342,7 +349,9 @@ template <int T>
 struct HashPieces {
     const SegLds L;
     int64_t rbase;
-    __device__ __forceinline__ bool operator()(int k, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
+    struct Raw {};
+    __device__ __forceinline__ Raw fetch(int) const { return Raw{}; }
+    __device__ __forceinline__ bool decode(int k, const Raw &, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
         const int s = L.ptab[k];
         const uint32_t pk = L.hcnt[s];
         const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
@@ -355,18 +364,22 @@ struct HashPieces {
     }
 };
 
-// Pieces given by the plan (staged in LDS).  Reads stay inside the tile and
-// a record outside the plan's range is never written, whatever the plan holds.
+// Pieces given by the plan, read from global memory (the tile's range
+// starts at k0).  Reads stay inside the tile and a record outside the plan's
+// range is never written, whatever the plan holds.
 template <int T>
 struct PlanPieces {
-    const uint32_t *pdesc, *prow, *pdst;
-    int64_t cap;
-    __device__ __forceinline__ bool operator()(int k, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
-        const uint32_t d = pdesc[k];
-        p0 = (int)(d & 0xFFFFu);
-        p1 = min(p0 + (int)(d >> 16), T);
-        row = prow[k];
-        pos = pdst[k];
+    const uint32_t *__restrict__ pdesc, *__restrict__ prow, *__restrict__ pdst;
+    int64_t k0, cap;
+    struct Raw {
+        uint32_t d, r, x;
+    };
+    __device__ __forceinline__ Raw fetch(int k) const { return Raw{pdesc[k0 + k], prow[k0 + k], pdst[k0 + k]}; }
+    __device__ __forceinline__ bool decode(int, const Raw &q, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
+        p0 = (int)(q.d & 0xFFFFu);
+        p1 = min(p0 + (int)(q.d >> 16), T);
+        row = q.r;
+        pos = q.x;
         return pos < cap && p0 < p1;
     }
 };
@@ -385,22 +398,9 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles
     const int nm = a.nmodes, mode = a.mode, tid = threadIdx.x;
     uint32_t *crdg = (uint32_t *)lds;
     float *valg = (float *)(crdg + (size_t)(nm - 1) * T);
-    uint32_t *pdesc = (uint32_t *)(valg + T);
-    uint32_t *prow = pdesc + T;
-    uint32_t *pdst = prow + T;
     const CodecRegs cr = load_codec_regs(a.codec);
-    // the tile's pieces (at most T) and its nonzeros, all loads issued first
     const int64_t k0 = a.pl_off[tile], k1 = min(a.pl_off[tile + 1], k0 + T);  // a tile has at most T pieces
     const int npieces = (int)(k1 - k0);
-    uint32_t qd[4], qr[4], qx[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t k = k0 + tid + u * NT;
-        const bool ok = k < k1;
-        qd[u] = ok ? a.pl_desc[k] : 0u;
-        qr[u] = ok ? a.pl_row[k] : 0u;
-        qx[u] = ok ? a.pl_dest[k] : 0u;
-    }
     const int64_t base = tile * (int64_t)T;
     const int64_t rem = a.nnz - base;
     const int cnt = rem < T ? (int)rem : T;
@@ -426,14 +426,6 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles
         w[u][3] = (uint32_t)(khi >> 32);
         v[u] = x;
         ps[u] = q;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        if (tid + u * NT < npieces) {
-            pdesc[tid + u * NT] = qd[u];
-            prow[tid + u * NT] = qr[u];
-            pdst[tid + u * NT] = qx[u];
-        }
     }
     // decode the non-output coordinates and scatter them with the values
 #pragma unroll
@@ -463,8 +455,9 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles
     for (int u = 0; u < 4; ++u)
         if (tid + u * NT < cnt) valg[ps[u]] = v[u];
     __syncthreads();
-    seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, crdg, valg, npieces, PlanPieces<T>{pdesc, prow, pdst, a.rec_cap},
-                                          a.rec_row, a.rec_val, a.rank, 0);
+    seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, crdg, valg, npieces,
+                                          PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap}, a.rec_row,
+                                          a.rec_val, a.rank, 0);
 }
 
 // The plan of one mode: positions of every nonzero, and per piece its

@@ -128,11 +128,11 @@ void release_plans(Tensor *t) {
 }
 
 // SEGMENT tile: the plan's tile if it is one the kernel serves and it fits
-// LDS, else 2048 (fits every mode count up to 8)
+// LDS, else the largest that fits (4096 up to 5 modes, 2048 beyond)
 int segment_tile(const Tensor *t, int mode) {
     const int want = t->plan.tile[mode];
     if (want >= 1024 && seg_tile_ok(want, t->nmodes)) return want;
-    return seg_tile_ok(2048, t->nmodes) ? 2048 : 1024;
+    return seg_tile_ok(4096, t->nmodes) ? 4096 : (seg_tile_ok(2048, t->nmodes) ? 2048 : 1024);
 }
 
 // SEGMENT plan (once per tensor and mode; synchronises s once).  A tile's
