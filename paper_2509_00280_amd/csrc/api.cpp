@@ -301,8 +301,7 @@ void tensor_release(Tensor *t, hipStream_t s) {
         release_ws(t);
     }
     for (int n = 0; n < kMaxModes; ++n) {
-        dev_free(t->bseg_off[n], s);
-        t->bseg_off[n] = nullptr;
+        release_batch_plan(t, n, s);
     }
     dev_free(t->lo, s);
     dev_free(t->hi, s);

@@ -36,69 +36,153 @@ int bit_len(int64_t x) {  // bits to hold values 0..x-1
     return b;
 }
 
+// give every Gram item its row slices in the launch; returns the total
+int64_t assign_slices(std::vector<GramItem> &v) {
+    int64_t run = 0;
+    for (GramItem &g : v) {
+        g.first_slice = run;
+        g.nslices = gram_slices(g.rows);
+        run += g.nslices;
+    }
+    return run;
+}
+
+void set_batch_plan_args(MttkrpArgs &a, const ModePlan &p) {
+    a.pl_off = p.pl_off;
+    a.pl_pos = p.pl_pos;
+    a.pl_desc = p.pl_desc;
+    a.pl_row = p.pl_row;
+    a.pl_dest = p.pl_dest;
+    a.rec_cap = p.records;
+}
+
 }  // namespace
 
-// Builds the batched SEGMENT plan of `mode` for every tensor that lacks it:
-// one counting launch over all their tiles and one readback.
+// Builds the batched SEGMENT plan of `mode` for every tensor that lacks it,
+// for all of them at once: one counting launch and readback, one emission
+// launch, one sort of all distinct (tile, row) pairs by row of the
+// concatenated output (tensors in order, tile order kept within a row), one
+// scan of their piece counts.  Each tensor's records come out grouped by row,
+// numbered from 0 within the tensor.
 spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s) {
     std::vector<Tensor *> need;
     for (Tensor *t : ts)
-        if (t->nmodes > mode && !t->bseg_off[mode]) need.push_back(t);
+        if (t->nmodes > mode && !t->bplan[mode].pl_off) need.push_back(t);
     if (need.empty()) return SPT_OK;
+    const int n = (int)need.size();
     int nmax = 0;
-    std::vector<SegItem> items(need.size());
-    int64_t tiles = 0;
-    for (size_t i = 0; i < need.size(); ++i) {
+    std::vector<SegItem> items(n);
+    int64_t tiles = 0, rows = 0;
+    for (int i = 0; i < n; ++i) {
         items[i] = SegItem{};
         items[i].a = make_args(need[i], nullptr, 1, mode, nullptr, kBatchTile);
         items[i].first_tile = tiles;
+        items[i].row_base = rows;
         tiles += (need[i]->nnz + kBatchTile - 1) / kBatchTile;
+        rows += need[i]->dims[mode];
         nmax = std::max(nmax, need[i]->nmodes);
     }
     if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "batch: too many modes for the batched tile");
-    SegItem *d_items = (SegItem *)dev_alloc(sizeof(SegItem) * items.size(), s);
-    int64_t *d_cnt = (int64_t *)dev_alloc(sizeof(int64_t) * std::max<int64_t>(tiles, 1), s);
-    if (!d_items || !d_cnt) {
-        dev_free(d_items, s);
-        dev_free(d_cnt, s);
+    if (tiles == 0) return SPT_OK;
+    DevBuf d_items, d_cnt;
+    std::vector<int64_t> h(tiles, 0);
+    if (!d_items.get(sizeof(SegItem) * n, s) || !d_cnt.get(sizeof(int64_t) * tiles, s))
         return fail(SPT_E_OOM, "batch plan: counts");
-    }
-    std::vector<int64_t> h(std::max<int64_t>(tiles, 1), 0);
-    spt_status st = SPT_OK;
-    if (hipMemcpyAsync(d_items, items.data(), sizeof(SegItem) * items.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-        st = hip_fail(hipGetLastError(), "batch plan: upload");
-    if (st == SPT_OK) st = launch_count_pieces_batched(d_items, (int)items.size(), tiles, nmax, d_cnt, s);
-    if (st == SPT_OK && tiles > 0 &&
-        hipMemcpyAsync(h.data(), d_cnt, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s) != hipSuccess)
-        st = hip_fail(hipGetLastError(), "batch plan: readback");
-    if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "batch plan: sync");
-    dev_free(d_items, s);
-    dev_free(d_cnt, s);
+    SPT_HIP(hipMemcpy(d_items.p, items.data(), sizeof(SegItem) * n, hipMemcpyHostToDevice));
+    spt_status st = launch_count_pieces_batched((SegItem *)d_items.p, n, tiles, nmax, (int64_t *)d_cnt.p, s);
     if (st != SPT_OK) return st;
-    std::vector<std::vector<int64_t>> offs(need.size());
-    for (size_t i = 0; i < need.size(); ++i) {
-        Tensor *t = need[i];
-        const int64_t nt = (t->nnz + kBatchTile - 1) / kBatchTile;
-        std::vector<int64_t> &off = offs[i];
-        off.assign(nt + 1, 0);
-        int64_t run = 0;
+    SPT_HIP(hipMemcpyAsync(h.data(), d_cnt.p, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    // offsets: per tensor (local pieces per tile) and batch-wide (pieces, pairs)
+    std::vector<std::vector<int64_t>> loff(n);
+    std::vector<int64_t> gpiece(tiles), gpair(tiles), piece_base(n + 1, 0);
+    int64_t G = 0, Q = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t nt = (need[i]->nnz + kBatchTile - 1) / kBatchTile;
+        loff[i].assign(nt + 1, 0);
+        piece_base[i] = G;
+        int64_t local = 0;
         for (int64_t k = 0; k < nt; ++k) {
-            off[k] = run;
-            run += h[items[i].first_tile + k];
+            const int64_t it = items[i].first_tile + k, c = h[it];
+            loff[i][k] = local;
+            gpiece[it] = G + local;
+            gpair[it] = Q;
+            local += c & 0xFFFFFFFFll;
+            Q += c >> 32;
         }
-        off[nt] = run;
-        // stream-ordered, so releasing the tensor later needs no device-wide sync
-        int64_t *d = (int64_t *)dev_alloc(sizeof(int64_t) * (nt + 1), s);
-        if (!d) return fail(SPT_E_OOM, "batch plan: offsets");
-        if (hipMemcpyAsync(d, off.data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, s) != hipSuccess) {
-            dev_free(d, s);
-            return hip_fail(hipGetLastError(), "batch plan: offsets");
-        }
-        t->bseg_off[mode] = d;
-        t->bseg_records[mode] = run;
+        loff[i][nt] = local;
+        G += local;
     }
-    SPT_HIP(hipStreamSynchronize(s));  // host offsets are read by the copies above
-    return SPT_OK;
+    piece_base[n] = G;
+    if (G >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "batch plan: more than 2^32 records");
+    // the tensors' plan arrays (stream-ordered: released without a device-wide sync)
+    for (int i = 0; i < n; ++i) {
+        Tensor *t = need[i];
+        ModePlan &p = t->bplan[mode];
+        const int64_t nt = (int64_t)loff[i].size() - 1, P = loff[i][nt];
+        p.pl_off = (int64_t *)dev_alloc(sizeof(int64_t) * (nt + 1), s);
+        p.pl_pos = (uint16_t *)dev_alloc(sizeof(uint16_t) * std::max<int64_t>(t->nnz, 1), s);
+        p.pl_desc = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max<int64_t>(P, 1), s);
+        p.pl_row = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max<int64_t>(P, 1), s);
+        p.pl_dest = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max<int64_t>(P, 1), s);
+        if (!p.pl_off || !p.pl_pos || !p.pl_desc || !p.pl_row || !p.pl_dest) {
+            (void)hipStreamSynchronize(s);  // copies from host vectors may be in flight
+            for (int k = 0; k <= i; ++k) release_batch_plan(need[k], mode, s);
+            return fail(SPT_E_OOM, "batch plan: arrays");
+        }
+        SPT_HIP(hipMemcpyAsync(p.pl_off, loff[i].data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, s));
+        p.ts = kBatchTile;
+        p.records = P;
+        p.strategy = SPT_STRATEGY_SEGMENT;
+        p.valid = 1;
+        SegItem &it = items[i];
+        it.a.pl_off = p.pl_off;
+        it.a.pl_pos = p.pl_pos;
+        it.a.pl_desc = p.pl_desc;
+        it.a.pl_row = p.pl_row;
+        it.a.pl_dest = p.pl_dest;
+        it.a.rec_cap = P;
+    }
+    SPT_HIP(hipMemcpyAsync(d_items.p, items.data(), sizeof(SegItem) * n, hipMemcpyHostToDevice, s));
+    const size_t g1 = (size_t)std::max<int64_t>(G, 1), q1 = (size_t)std::max<int64_t>(Q, 1);
+    DevBuf d_gpiece, d_gpair, d_base, ppair, psub, keys, keys2, np, ia, ib, cnt;
+    if (!d_gpiece.get(sizeof(int64_t) * tiles, s) || !d_gpair.get(sizeof(int64_t) * tiles, s) ||
+        !d_base.get(sizeof(int64_t) * (n + 1), s) || !ppair.get(sizeof(uint32_t) * g1, s) ||
+        !psub.get(sizeof(uint32_t) * g1, s) || !keys.get(sizeof(uint64_t) * q1, s) ||
+        !keys2.get(sizeof(uint64_t) * q1, s) || !np.get(sizeof(uint32_t) * q1, s) || !ia.get(sizeof(uint32_t) * q1, s) ||
+        !ib.get(sizeof(uint32_t) * q1, s) ||
+        !cnt.get(sizeof(uint32_t) * std::max(sort_ws_counts(Q), exclusive_scan_ws(Q)), s)) {
+        (void)hipStreamSynchronize(s);
+        for (Tensor *t : need) release_batch_plan(t, mode, s);
+        return fail(SPT_E_OOM, "batch plan: workspace");
+    }
+    SPT_HIP(hipMemcpyAsync(d_gpiece.p, gpiece.data(), sizeof(int64_t) * tiles, hipMemcpyHostToDevice, s));
+    SPT_HIP(hipMemcpyAsync(d_gpair.p, gpair.data(), sizeof(int64_t) * tiles, hipMemcpyHostToDevice, s));
+    SPT_HIP(hipMemcpyAsync(d_base.p, piece_base.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    st = launch_emit_plan_batched((SegItem *)d_items.p, n, tiles, nmax, (int64_t *)d_gpiece.p, (int64_t *)d_gpair.p,
+                                  (uint32_t *)ppair.p, (uint32_t *)psub.p, (uint64_t *)keys.p, (uint32_t *)np.p, s);
+    uint64_t *sk = nullptr;
+    uint32_t *sidx = nullptr;
+    if (st == SPT_OK)
+        st = sort_u64_keys_ws((uint64_t *)keys.p, (uint64_t *)keys2.p, (uint32_t *)ia.p, (uint32_t *)ib.p,
+                              (uint32_t *)cnt.p, Q, bit_len(rows), &sk, &sidx, s);
+    uint32_t *np_sorted = (sidx == (uint32_t *)ia.p) ? (uint32_t *)ib.p : (uint32_t *)ia.p;
+    uint32_t *tmp = (uint32_t *)((sk == (uint64_t *)keys2.p) ? keys.p : keys2.p);  // free after the sort
+    uint32_t *pair_first = tmp + q1;
+    if (st == SPT_OK) st = launch_gather_u32((uint32_t *)np.p, sidx, np_sorted, Q, s);
+    if (st == SPT_OK) st = launch_exclusive_scan_u32(np_sorted, tmp, Q, (uint32_t *)cnt.p, s);
+    if (st == SPT_OK) st = launch_scatter_u32(tmp, sidx, pair_first, Q, s);
+    if (st == SPT_OK)
+        st = launch_piece_dest_batched((SegItem *)d_items.p, n, (int64_t *)d_base.p, (uint32_t *)ppair.p,
+                                       (uint32_t *)psub.p, pair_first, G, s);
+    if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "batch plan: build");
+    if (st != SPT_OK) {
+        (void)hipStreamSynchronize(s);
+        for (Tensor *t : need) release_batch_plan(t, mode, s);
+    }
+    for (DevBuf *b : {&d_items, &d_cnt, &d_gpiece, &d_gpair, &d_base, &ppair, &psub, &keys, &keys2, &np, &ia, &ib, &cnt})
+        b->release();
+    return st;
 }
 
 // The batched MTTKRP pipeline of one mode into M_all (rows x ld, overwritten).
@@ -111,17 +195,11 @@ spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t to
     const size_t n1 = (size_t)records;
     uint64_t *rrow = (uint64_t *)ws.rec_row.get(sizeof(uint64_t) * n1, s);
     float *rval = (float *)ws.rec_val.get(sizeof(float) * n1 * ld, s);
-    uint64_t *k2 = (uint64_t *)ws.keys2.get(sizeof(uint64_t) * n1, s);
-    uint32_t *ia = (uint32_t *)ws.ia.get(sizeof(uint32_t) * n1, s);
-    uint32_t *ib = (uint32_t *)ws.ib.get(sizeof(uint32_t) * n1, s);
-    uint32_t *cnt = (uint32_t *)ws.cnt.get(sizeof(uint32_t) * sort_ws_counts(records), s);
-    if (!rrow || !rval || !k2 || !ia || !ib || !cnt) return fail(SPT_E_OOM, "batch: record workspace");
+    if (!rrow || !rval) return fail(SPT_E_OOM, "batch: record workspace");
+    // the batch's records come out grouped by row: no sort
     spt_status st = launch_mttkrp_seg_batched(d_items, count, total_tiles, nmodes_max, ld, vec4, rrow, rval, s);
-    uint64_t *srow = nullptr;
-    uint32_t *sidx = nullptr;
-    if (st == SPT_OK) st = sort_u64_keys_ws(rrow, k2, ia, ib, cnt, records, bit_len(rows), &srow, &sidx, s);
     if (st == SPT_OK) st = launch_fill_zero(M_all, rows * (int64_t)ld, s);
-    if (st == SPT_OK) st = launch_reduce_records(srow, sidx, rval, records, ld, rows, M_all, s);
+    if (st == SPT_OK) st = launch_reduce_records(rrow, nullptr, rval, records, ld, rows, M_all, s);
     return st;
 }
 
@@ -145,6 +223,7 @@ void BatchEngine::release_buffers() {
     resid_ = nullptr;
     items_bytes_ = M_bytes_ = fit_cap_ = inner_cap_ = resid_cap_ = 0;
     ws_.release();
+    gram_ws_.release();
 }
 
 void BatchEngine::free_member_state(Member *m) {
@@ -211,7 +290,7 @@ spt_status BatchEngine::rebuild() {
     std::vector<int64_t> inner_base(A, 0), inner_n(A, 0);
     int64_t inner_total = 0;
     modes_.assign(nmodes_max_, ModeItems{});
-    size_t M_need = 0;
+    size_t M_need = 0, gram_need = 0;
     int64_t max_records = 0;
     for (int n = 0; n < nmodes_max_; ++n) {
         ModeItems &mi = modes_[n];
@@ -236,7 +315,7 @@ spt_status BatchEngine::rebuild() {
             const int R = m->R;
             SegItem si{};
             si.a = make_args(t, (const float *const *)m->F, R, n, nullptr, kBatchTile);
-            si.a.rec_off = t->bseg_off[n];
+            set_batch_plan_args(si.a, t->bplan[n]);
             si.first_tile = tiles;
             si.rec_base = recs;
             si.row_base = rows;
@@ -285,7 +364,7 @@ spt_status BatchEngine::rebuild() {
             gc.push_back(g2);
             mi.member_idx.push_back(i);
             tiles += (t->nnz + kBatchTile - 1) / kBatchTile;
-            recs += t->bseg_records[n];
+            recs += t->bplan[n].records;
             rows += In;
             blocks += nb;
         }
@@ -300,6 +379,10 @@ spt_status BatchEngine::rebuild() {
         M_need = std::max(M_need, sizeof(float) * (size_t)rows * std::max(ld, 1));
         max_records = std::max(max_records, recs);
         mi.seg_v = std::move(seg);
+        mi.gm_slices = assign_slices(gm);
+        mi.gc_slices = assign_slices(gc);
+        gram_need = std::max(gram_need, std::max(gram_batched_ws_bytes(mi.gm_slices, rmax),
+                                                 gram_batched_ws_bytes(mi.gc_slices, rmax)));
         mi.gm_v = std::move(gm);
         mi.sv_v = std::move(sv);
         mi.ap_v = std::move(ap);
@@ -377,6 +460,9 @@ spt_status BatchEngine::rebuild() {
             init_rmax = std::max(init_rmax, m->R);
             m->fresh = false;
         }
+    init_slices_ = assign_slices(init);
+    gram_need = std::max(gram_need, gram_batched_ws_bytes(init_slices_, std::max(init_rmax, 1)));
+    if (!gram_ws_.get(gram_need, s_)) return fail(SPT_E_OOM, "batch: Gram workspace");
     init_off_ = put(init.data(), sizeof(GramItem) * init.size());
     init_count_ = (int)init.size();
     init_rmax_ = init_rmax;
@@ -389,7 +475,8 @@ spt_status BatchEngine::rebuild() {
     }
     if (!blob.empty()) SPT_HIP(hipMemcpy(d_items_, blob.data(), blob.size(), hipMemcpyHostToDevice));
     if (init_count_ > 0) {
-        spt_status st = launch_gram_batched((const GramItem *)(d_items_ + init_off_), init_count_, init_rmax_, s_);
+        spt_status st = launch_gram_batched((const GramItem *)(d_items_ + init_off_), init_count_, init_slices_,
+                                            init_rmax_, (double *)gram_ws_.p, s_);
         if (st != SPT_OK) return st;
     }
     dirty_ = false;
@@ -408,11 +495,15 @@ spt_status BatchEngine::step() {
         if (mi.count == 0) continue;
         spt_status st = run_mttkrp_batched_mode((const SegItem *)(d_items_ + mi.seg_off), mi.count, mi.tiles, nmodes_max_,
                                                 mi.records, mi.rows, mi.ld, mi.vec4, M_all_, ws_, s_);
-        if (st == SPT_OK) st = launch_gram_batched((const GramItem *)(d_items_ + mi.gm_off), mi.count, mi.rmax, s_);
+        if (st == SPT_OK)
+            st = launch_gram_batched((const GramItem *)(d_items_ + mi.gm_off), mi.count, mi.gm_slices, mi.rmax,
+                                     (double *)gram_ws_.p, s_);
         if (st == SPT_OK) st = launch_solve_prep_batched((const SolveItem *)(d_items_ + mi.sv_off), mi.count, n, s_);
         if (st == SPT_OK)
             st = launch_apply_batched((const ApplyItem *)(d_items_ + mi.ap_off), mi.count, mi.blocks, mi.rmax, s_);
-        if (st == SPT_OK) st = launch_gram_batched((const GramItem *)(d_items_ + mi.gc_off), mi.count, mi.rmax, s_);
+        if (st == SPT_OK)
+            st = launch_gram_batched((const GramItem *)(d_items_ + mi.gc_off), mi.count, mi.gc_slices, mi.rmax,
+                                     (double *)gram_ws_.p, s_);
         if (st != SPT_OK) return st;
     }
     spt_status st = launch_fit_batched((const FitItem *)(d_items_ + fit_off_), A, s_);
@@ -522,13 +613,13 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         const int b = idx[i];
         items[i] = SegItem{};
         items[i].a = make_args(t, factors[b], ranks[b], mode, nullptr, kBatchTile);
-        items[i].a.rec_off = t->bseg_off[mode];
+        set_batch_plan_args(items[i].a, t->bplan[mode]);
         items[i].first_tile = tiles;
         items[i].rec_base = recs;
         items[i].row_base = rows;
         row_base[i] = rows;
         tiles += (t->nnz + kBatchTile - 1) / kBatchTile;
-        recs += t->bseg_records[mode];
+        recs += t->bplan[mode].records;
         rows += t->dims[mode];
     }
     SegItem *d_items = (SegItem *)dev_alloc(sizeof(SegItem) * items.size(), s);

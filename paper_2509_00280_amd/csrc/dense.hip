@@ -90,25 +90,37 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restri
             }
 }
 
-// Batched Gram: one workgroup of 8 waves per item.  Wave w takes row groups
-// of 4 rows [4 (w UNR + 8 UNR j), ...), accumulates every 16x16 block tile
-// (pb <= qb) with FP64 MFMA, and the waves add their tiles into LDS in wave
-// order (deterministic); columns at or beyond the item's rank read as 0.
+// Batched Gram in two launches.  (1) One workgroup of 8 waves per row slice
+// of kGramSliceRows rows of an item: wave w takes row groups of 4 rows
+// [4 (w UNR + 8 UNR j), ...) of the slice, accumulates every 16x16 block tile
+// (pb <= qb) with FP64 MFMA, the waves add their tiles in LDS in wave order,
+// and the slice's partial goes to work[first_slice + slice].  (2) One
+// workgroup per item sums its slices in order (deterministic).  Columns at or
+// beyond the item's rank read as 0.
 constexpr int kGramBThreads = 512;
 template <int NB, int UNR>
-__global__ __launch_bounds__(kGramBThreads) void k_gram_batched(const GramItem *__restrict__ items) {
+__global__ __launch_bounds__(kGramBThreads) void k_gram_batched_partial(const GramItem *__restrict__ items, int count,
+                                                                       double *__restrict__ work) {
     constexpr int NT = NB * (NB + 1) / 2, LDP = NB * 16, NWAVE = kGramBThreads / 64;
     __shared__ double red[LDP * LDP];
-    const GramItem &it = items[blockIdx.x];
+    const int64_t gs = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_slice <= gs) lo = mid;
+        else hi = mid - 1;
+    }
+    const GramItem &it = items[__builtin_amdgcn_readfirstlane(lo)];
     const float *__restrict__ C = it.C;
-    const int64_t rows = it.rows;
+    const int64_t r0 = (gs - it.first_slice) * kGramSliceRows;
+    const int64_t rows = min(it.rows, r0 + kGramSliceRows);
     const int ld = it.ld, R = it.rank;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kr = lane >> 4, cc = lane & 15;
     double4_t acc[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[i] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    for (int64_t g0 = (int64_t)wave * UNR; g0 * 4 < rows; g0 += (int64_t)NWAVE * UNR) {
+    for (int64_t g0 = r0 / 4 + (int64_t)wave * UNR; g0 * 4 < rows; g0 += (int64_t)NWAVE * UNR) {
         double v[UNR][NB];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
@@ -146,10 +158,22 @@ __global__ __launch_bounds__(kGramBThreads) void k_gram_batched(const GramItem *
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < R * R; e += kGramBThreads) {
+    double *wb = work + (size_t)gs * LDP * LDP;
+    for (int e = threadIdx.x; e < LDP * LDP; e += kGramBThreads) wb[e] = red[e];
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_gram_batched_reduce(const GramItem *__restrict__ items,
+                                                             const double *__restrict__ work) {
+    constexpr int LDP = NB * 16;
+    const GramItem &it = items[blockIdx.x];
+    const int R = it.rank;
+    for (int e = threadIdx.x; e < R * R; e += 256) {
         const int p = e / R, q = e % R;
         const int a = (p / 16 <= q / 16) ? p : q, b = (p / 16 <= q / 16) ? q : p;
-        it.G[e] = red[a * LDP + b];
+        double s = 0.0;
+        for (int64_t k = 0; k < it.nslices; ++k) s += work[(size_t)(it.first_slice + k) * LDP * LDP + a * LDP + b];
+        it.G[e] = s;
     }
 }
 
@@ -546,14 +570,32 @@ spt_status launch_fit_direct(const double *resid_partials, int nparts, double no
     return SPT_OK;
 }
 
-spt_status launch_gram_batched(const GramItem *items, int count, int rmax, hipStream_t s) {
-    if (count == 0) return SPT_OK;
+int64_t gram_slices(int64_t rows) { return std::max<int64_t>(1, (rows + kGramSliceRows - 1) / kGramSliceRows); }
+
+size_t gram_batched_ws_bytes(int64_t total_slices, int rmax) {
+    const size_t ldp = (size_t)gram_nb(rmax) * 16;
+    return (size_t)std::max<int64_t>(total_slices, 1) * ldp * ldp * sizeof(double);
+}
+
+spt_status launch_gram_batched(const GramItem *items, int count, int64_t total_slices, int rmax, double *work,
+                               hipStream_t s) {
+    if (count == 0 || total_slices == 0) return SPT_OK;
     if (rmax > 64) return fail(SPT_E_INVALID_ARG, "gram: rank above 64");
     const int nb = gram_nb(rmax);
-    if (nb == 1) hipLaunchKernelGGL((k_gram_batched<1, 4>), dim3(count), dim3(kGramBThreads), 0, s, items);
-    else if (nb == 2) hipLaunchKernelGGL((k_gram_batched<2, 4>), dim3(count), dim3(kGramBThreads), 0, s, items);
-    else if (nb == 3) hipLaunchKernelGGL((k_gram_batched<3, 2>), dim3(count), dim3(kGramBThreads), 0, s, items);
-    else hipLaunchKernelGGL((k_gram_batched<4, 2>), dim3(count), dim3(kGramBThreads), 0, s, items);
+    const dim3 g((unsigned)total_slices), b(kGramBThreads);
+    if (nb == 1) {
+        hipLaunchKernelGGL((k_gram_batched_partial<1, 4>), g, b, 0, s, items, count, work);
+        hipLaunchKernelGGL(k_gram_batched_reduce<1>, dim3(count), dim3(256), 0, s, items, work);
+    } else if (nb == 2) {
+        hipLaunchKernelGGL((k_gram_batched_partial<2, 4>), g, b, 0, s, items, count, work);
+        hipLaunchKernelGGL(k_gram_batched_reduce<2>, dim3(count), dim3(256), 0, s, items, work);
+    } else if (nb == 3) {
+        hipLaunchKernelGGL((k_gram_batched_partial<3, 2>), g, b, 0, s, items, count, work);
+        hipLaunchKernelGGL(k_gram_batched_reduce<3>, dim3(count), dim3(256), 0, s, items, work);
+    } else {
+        hipLaunchKernelGGL((k_gram_batched_partial<4, 2>), g, b, 0, s, items, count, work);
+        hipLaunchKernelGGL(k_gram_batched_reduce<4>, dim3(count), dim3(256), 0, s, items, work);
+    }
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

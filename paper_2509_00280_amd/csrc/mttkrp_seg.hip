@@ -1,27 +1,27 @@
 // SEGMENT strategy of mode-n MTTKRP (Section II-B, Fig. 2) on gfx950.
 //
 // A workgroup of NT threads owns a tile of T = 4 NT consecutive nonzeros of
-// the key-ordered stream.
-//  1. Stage: coalesced non-temporal loads of keys and values; every thread
-//     decodes the coordinates of its four nonzeros into registers from the bit
-//     runs held in VGPRs.
-//  2. Regroup by output row: LDS hash (T slots, linear probing, CAS) of the
-//     mode-n coordinate; an LDS counter per slot gives each nonzero its rank
-//     (kept in registers with the slot).  One block scan of packed
-//     (nonzeros << 16 | pieces) per slot yields the position of every nonzero
-//     in row-grouped order and the first piece of every slot, where a row with
-//     c nonzeros in the tile is cut into ceil(c / L) pieces of at most L.
-//     The nonzeros' values and non-output coordinates are scattered straight
-//     into row-grouped order; a piece table maps piece -> slot.
-//  3. Walk: lane groups (G lanes x VEC columns) take pieces round-robin (every
-//     piece is at most L nonzeros, so the static deal is balanced), gather the
-//     N-1 factor rows of the piece's nonzeros with vector loads (UB nonzeros in
-//     flight), form v * Hadamard, sum the piece in registers (a segmented
-//     reduction over equal output index) and write one record (row, R floats)
-//     with plain stores at the tile's record base plus the piece index.  The
-//     number of pieces depends only on the tile's multiset of rows, so a
-//     counting pass fixes every tile's record range: no atomics, no padding.
-//  4. Records are radix-sorted by row and summed per row (mttkrp_table.hip).
+// the key-ordered stream.  Conflicts on output rows are resolved by
+// regrouping the tile by output row and cutting every row's run into pieces
+// of at most L nonzeros; each piece is summed in registers (a segmented
+// reduction over equal output index) and written as one record (row, R
+// floats) with plain stores; the records are summed per row afterwards
+// (mttkrp_table.hip).  No atomics on the main path.
+//
+// Plan (once per tensor and mode, the hashing stage below): an LDS hash of
+// the tile's output rows (T slots, linear probing, CAS), one block scan of
+// packed (nonzeros << 16 | pieces) per slot, giving every nonzero its
+// position in row-grouped order and every piece its start, length and row.
+// The (tile, row) pairs are then sorted by row across the tensor (or the
+// batch) and scanned, which lays the records out grouped by row.
+//
+// Call (the planned kernel): coalesced non-temporal loads of keys, values and
+// plan positions; the non-output coordinates are decoded from the bit runs
+// held in VGPRs and scattered once to LDS in row-grouped order; lane groups
+// (G lanes x VEC columns) take pieces round-robin (at most L nonzeros each,
+// so the static deal is balanced), gather the N-1 factor rows of the piece's
+// nonzeros with vector loads, form v * Hadamard, sum and store the record at
+// its plan-given slot.  No hashing, atomics or scans at run time.
 #include "tile_common.h"
 
 #ifndef SPT_SEG_UB
@@ -343,34 +343,13 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
     }
 }
 
-// Pieces of a tile regrouped by the hashing stage: piece k is the
-// (k - first piece)-th run of L nonzeros of slot ptab[k]; record rbase + k.
-template <int T>
-struct HashPieces {
-    const SegLds L;
-    int64_t rbase;
-    struct Raw {};
-    __device__ __forceinline__ Raw fetch(int) const { return Raw{}; }
-    __device__ __forceinline__ bool decode(int k, const Raw &, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
-        const int s = L.ptab[k];
-        const uint32_t pk = L.hcnt[s];
-        const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
-        const int first = (int)(pk >> 16), last = (int)(pn >> 16);
-        p0 = first + (k - (int)(pk & 0xFFFFu)) * kPiece;
-        p1 = min(p0 + kPiece, last);
-        row = L.hkey[s];
-        pos = rbase + k;
-        return true;
-    }
-};
-
 // Pieces given by the plan, read from global memory (the tile's range
 // starts at k0).  Reads stay inside the tile and a record outside the plan's
 // range is never written, whatever the plan holds.
 template <int T>
 struct PlanPieces {
     const uint32_t *__restrict__ pdesc, *__restrict__ prow, *__restrict__ pdst;
-    int64_t k0, cap;
+    int64_t k0, cap, rec_base;
     struct Raw {
         uint32_t d, r, x;
     };
@@ -379,8 +358,8 @@ struct PlanPieces {
         p0 = (int)(q.d & 0xFFFFu);
         p1 = min(p0 + (int)(q.d >> 16), T);
         row = q.r;
-        pos = q.x;
-        return pos < cap && p0 < p1;
+        pos = rec_base + q.x;
+        return q.x < cap && p0 < p1;
     }
 };
 
@@ -390,11 +369,9 @@ struct PlanPieces {
 // scatter of values and non-output coordinates to their positions; there is
 // no hashing, no atomic and no scan at run time.
 template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
-__global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles) {
+__device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, char *lds, uint64_t *__restrict__ rec_row,
+                                          float *__restrict__ rec_val, int ld, int64_t rec_base, int64_t row_base) {
     constexpr int T = 4 * NT;
-    extern __shared__ __align__(16) char lds[];
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
     const int nm = a.nmodes, mode = a.mode, tid = threadIdx.x;
     uint32_t *crdg = (uint32_t *)lds;
     float *valg = (float *)(crdg + (size_t)(nm - 1) * T);
@@ -456,23 +433,60 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles
         if (tid + u * NT < cnt) valg[ps[u]] = v[u];
     __syncthreads();
     seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, crdg, valg, npieces,
-                                          PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap}, a.rec_row,
-                                          a.rec_val, a.rank, 0);
+                                          PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, rec_base},
+                                          rec_row, rec_val, ld, row_base);
+}
+
+template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
+__global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles) {
+    extern __shared__ __align__(16) char lds[];
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    segp_tile<NT, G, VEC, NB, NMAX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
+}
+
+// Batched: tile `it` of the whole batch belongs to the last item whose
+// first_tile <= it.
+__device__ __forceinline__ int seg_item_of(const SegItem *__restrict__ items, int count, int64_t it) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_tile <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Every tensor's records start at its rec_base in the batch's record array,
+// its rows at row_base of the concatenated output (records of the whole batch
+// stay grouped by row: tensors are laid out in order).
+template <int NT, int G, int VEC, int NB, int NMAX>
+__global__ __launch_bounds__(NT) void k_mttkrp_segp_batched(const SegItem *__restrict__ items, int count,
+                                                            int64_t total_tiles, uint64_t *__restrict__ rec_row,
+                                                            float *__restrict__ rec_val, int ld) {
+    extern __shared__ __align__(16) char lds[];
+    const int64_t it = xcd_remap(blockIdx.x, gridDim.x);
+    if (it >= total_tiles) return;
+    const int b = seg_item_of(items, count, it);
+    const SegItem &item = items[b];
+    segp_tile<NT, G, VEC, NB, NMAX, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
+                                           item.row_base);
 }
 
 // The plan of one mode: positions of every nonzero, and per piece its
 // (start | length << 16), row, and (for the record layout) its pair and index
 // within the pair; per distinct (tile, row) pair its row (sort key) and pieces.
+// Emission of one tile: positions to pos (the tensor's), piece start/length
+// and row to desc/prow at a.pl_off[tile]; piece pair and index to
+// ppair/psub at gpiece; pair (row_base + row, pieces) to pair_key/pair_np at
+// gpair (pair indices are global, gpair-based).
 template <int NT, int NMAX>
-__global__ __launch_bounds__(NT) void k_emit_plan(MttkrpArgs a, int64_t ntiles, const int64_t *__restrict__ pair_off,
-                                                  uint16_t *__restrict__ pos, uint32_t *__restrict__ desc,
-                                                  uint32_t *__restrict__ prow, uint32_t *__restrict__ ppair,
-                                                  uint32_t *__restrict__ psub, uint64_t *__restrict__ pair_key,
-                                                  uint32_t *__restrict__ pair_np) {
+__device__ __forceinline__ void emit_tile(const MttkrpArgs &a, int64_t tile, char *lds, uint32_t *wsum,
+                                          uint16_t *__restrict__ pos, uint32_t *__restrict__ desc,
+                                          uint32_t *__restrict__ prow, int64_t gpiece, int64_t gpair, int64_t row_base,
+                                          uint32_t *__restrict__ ppair, uint32_t *__restrict__ psub,
+                                          uint64_t *__restrict__ pair_key, uint32_t *__restrict__ pair_np) {
     constexpr int T = 4 * NT;
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[NT / 64];
-    const int64_t tile = blockIdx.x;
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum, pos);
@@ -484,13 +498,13 @@ __global__ __launch_bounds__(NT) void k_emit_plan(MttkrpArgs a, int64_t ntiles, 
     }
     __syncthreads();
     block_scan_lds(occ, T, NT, wsum);
-    const int64_t pbase = a.pl_off[tile], qbase = pair_off[tile];
+    const int64_t pbase = a.pl_off[tile], qbase = gpair;
     for (int i = threadIdx.x; i < T; i += NT) {
         const uint32_t pk = L.hcnt[i];
         const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
         const uint32_t c = (nx >> 16) - (pk >> 16);
         if (c > 0) {
-            pair_key[qbase + occ[i]] = L.hkey[i];
+            pair_key[qbase + occ[i]] = (uint64_t)(row_base + L.hkey[i]);
             pair_np[qbase + occ[i]] = (c + kPiece - 1) / kPiece;
         }
     }
@@ -505,8 +519,63 @@ __global__ __launch_bounds__(NT) void k_emit_plan(MttkrpArgs a, int64_t ntiles, 
         const int p1 = min(p0 + kPiece, last);
         desc[pbase + k] = (uint32_t)p0 | ((uint32_t)(p1 - p0) << 16);
         prow[pbase + k] = L.hkey[s];
-        ppair[pbase + k] = (uint32_t)(qbase + occ[s]);
-        psub[pbase + k] = (uint32_t)i;
+        ppair[gpiece + k] = (uint32_t)(qbase + occ[s]);
+        psub[gpiece + k] = (uint32_t)i;
+    }
+}
+
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_emit_plan(MttkrpArgs a, int64_t ntiles, const int64_t *__restrict__ pair_off,
+                                                  uint16_t *__restrict__ pos, uint32_t *__restrict__ desc,
+                                                  uint32_t *__restrict__ prow, uint32_t *__restrict__ ppair,
+                                                  uint32_t *__restrict__ psub, uint64_t *__restrict__ pair_key,
+                                                  uint32_t *__restrict__ pair_np) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t tile = blockIdx.x;
+    emit_tile<NT, NMAX>(a, tile, lds, wsum, pos, desc, prow, a.pl_off[tile], pair_off[tile], 0, ppair, psub, pair_key,
+                        pair_np);
+}
+
+// Batched emission: item b's plan arrays come in its args (pl_pos, pl_desc,
+// pl_row, pl_off); gpiece_off / gpair_off give each global tile's first
+// piece and pair in the batch-wide arrays; pair keys are rows of the
+// concatenated output (row_base + row).
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_emit_plan_batched(const SegItem *__restrict__ items, int count,
+                                                          const int64_t *__restrict__ gpiece_off,
+                                                          const int64_t *__restrict__ gpair_off,
+                                                          uint32_t *__restrict__ ppair, uint32_t *__restrict__ psub,
+                                                          uint64_t *__restrict__ pair_key,
+                                                          uint32_t *__restrict__ pair_np) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t wsum[NT / 64];
+    const int64_t it = blockIdx.x;
+    const int b = seg_item_of(items, count, it);
+    const SegItem &item = items[b];
+    const MttkrpArgs &a = item.a;
+    emit_tile<NT, NMAX>(a, it - item.first_tile, lds, wsum, const_cast<uint16_t *>(a.pl_pos),
+                        const_cast<uint32_t *>(a.pl_desc), const_cast<uint32_t *>(a.pl_row), gpiece_off[it],
+                        gpair_off[it], item.row_base, ppair, psub, pair_key, pair_np);
+}
+
+// Batched piece records: global piece g of item b (pieces from
+// items[b].rec_base) gets its first pair record plus its index, made local
+// to the item (the item's records start at its rec_base).
+__global__ __launch_bounds__(256) void k_piece_dest_batched(const SegItem *__restrict__ items, int count,
+                                                            const int64_t *__restrict__ piece_base,
+                                                            const uint32_t *__restrict__ ppair,
+                                                            const uint32_t *__restrict__ psub,
+                                                            const uint32_t *__restrict__ pair_first, int64_t n) {
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (int64_t)gridDim.x * 256) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (piece_base[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t d = pair_first[ppair[g]] + psub[g];
+        const_cast<uint32_t *>(items[lo].a.pl_dest)[g - piece_base[lo]] = d - (uint32_t)piece_base[lo];
     }
 }
 
@@ -518,40 +587,23 @@ __global__ __launch_bounds__(256) void k_piece_dest(const uint32_t *__restrict__
         dest[k] = pair_first[ppair[k]] + psub[k];
 }
 
-// Batched: tile `it` of the whole batch belongs to the last item whose
-// first_tile <= it; records go to the batch's arrays at the item's base.
-__device__ __forceinline__ int seg_item_of(const SegItem *__restrict__ items, int count, int64_t it) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].first_tile <= it) lo = mid;
-        else hi = mid - 1;
+// pieces | distinct rows << 32 of a tile after the hashing stage
+template <int T>
+__device__ __forceinline__ int64_t tile_counts(const SegLds &L) {
+    __shared__ uint32_t s_distinct;
+    if (threadIdx.x == 0) s_distinct = 0;
+    __syncthreads();
+    uint32_t d = 0;
+    for (int i = threadIdx.x; i < T; i += blockDim.x) {
+        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
+        d += (nx >> 16) != (L.hcnt[i] >> 16);
     }
-    return __builtin_amdgcn_readfirstlane(lo);
+    atomicAdd(&s_distinct, d);
+    __syncthreads();
+    return (int64_t)(L.hcnt[T] & 0xFFFFu) | ((int64_t)s_distinct << 32);
 }
 
-template <int NT, int G, int VEC, int NB, int NMAX>
-__global__ __launch_bounds__(NT) void k_mttkrp_seg_batched(const SegItem *__restrict__ items, int count,
-                                                           int64_t total_tiles, uint64_t *__restrict__ rec_row,
-                                                           float *__restrict__ rec_val, int ld) {
-    constexpr int T = 4 * NT;
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t wsum[NT / 64];
-    const int64_t it = xcd_remap(blockIdx.x, gridDim.x);
-    if (it >= total_tiles) return;
-    const int b = seg_item_of(items, count, it);
-    const SegItem &item = items[b];
-    const MttkrpArgs &a = item.a;
-    const int64_t tile = it - item.first_tile;
-    const SegLds L = seg_carve(lds, T, a.nmodes);
-    const CodecRegs cr = load_codec_regs(a.codec);
-    seg_stage<NT, NMAX, true>(a, tile, L, cr, wsum);
-    seg_walk<NT, G, VEC, NB, NMAX, false>(a, L.crdg, L.valg, (int)(L.hcnt[T] & 0xFFFFu),
-                                          HashPieces<T>{L, item.rec_base + a.rec_off[tile]}, rec_row, rec_val, ld,
-                                          item.row_base);
-}
-
-// Pieces of every tile (the plan's counting pass).
+// Pieces and distinct rows of every tile (the plan's counting pass).
 template <int NT, int NMAX>
 __global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntiles, int64_t *__restrict__ out) {
     constexpr int T = 4 * NT;
@@ -561,18 +613,8 @@ __global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntile
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
-    // distinct rows: slots whose element range is not empty
-    __shared__ uint32_t s_distinct;
-    if (threadIdx.x == 0) s_distinct = 0;
-    __syncthreads();
-    uint32_t d = 0;
-    for (int i = threadIdx.x; i < T; i += NT) {
-        const uint32_t nx = i + 1 < T ? L.hcnt[i + 1] : L.hcnt[T];
-        d += (nx >> 16) != (L.hcnt[i] >> 16);
-    }
-    atomicAdd(&s_distinct, d);
-    __syncthreads();
-    if (threadIdx.x == 0) out[tile] = (int64_t)(L.hcnt[T] & 0xFFFFu) | ((int64_t)s_distinct << 32);
+    const int64_t c = tile_counts<T>(L);
+    if (threadIdx.x == 0) out[tile] = c;
 }
 
 template <int NT, int NMAX>
@@ -587,7 +629,8 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
     const SegLds L = seg_carve(lds, T, a.nmodes);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, it - items[b].first_tile, L, cr, wsum);
-    if (threadIdx.x == 0) out[it] = L.hcnt[T] & 0xFFFFu;
+    const int64_t c = tile_counts<T>(L);
+    if (threadIdx.x == 0) out[it] = c;
 }
 
 template <int NT, int NMAX, int G, int VEC, int NB>
@@ -699,8 +742,8 @@ template <int NMAX, int G, int VEC, int NB>
 spt_status launch_segb_k(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
                          int ld, hipStream_t s) {
     constexpr int NT = kBatchTile / 4;
-    const size_t lds = seg_lds_bytes(kBatchTile, NMAX);
-    hipLaunchKernelGGL((k_mttkrp_seg_batched<NT, G, VEC, NB, NMAX>), dim3((unsigned)total_tiles), dim3(NT), lds, s,
+    const size_t lds = segp_lds_bytes(kBatchTile, NMAX);
+    hipLaunchKernelGGL((k_mttkrp_segp_batched<NT, G, VEC, NB, NMAX>), dim3((unsigned)total_tiles), dim3(NT), lds, s,
                        items, count, total_tiles, rec_row, rec_val, ld);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
@@ -721,7 +764,34 @@ spt_status launch_segb_n(const SegItem *items, int count, int64_t total_tiles, u
 }
 }  // namespace
 
-bool seg_batch_fits(int nmodes_max) { return seg_lds_bytes(kBatchTile, nmodes_max) <= 160 * 1024 - 1024; }
+bool seg_batch_fits(int nmodes_max) { return seg_tile_ok(kBatchTile, nmodes_max); }
+
+spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+                                    const int64_t *gpiece_off, const int64_t *gpair_off, uint32_t *ppair,
+                                    uint32_t *psub, uint64_t *pair_key, uint32_t *pair_np, hipStream_t s) {
+    if (total_tiles == 0) return SPT_OK;
+    constexpr int NT = kBatchTile / 4;
+    if (nmodes_max <= 4)
+        hipLaunchKernelGGL((k_emit_plan_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT),
+                           seg_lds_bytes(kBatchTile, 4), s, items, count, gpiece_off, gpair_off, ppair, psub, pair_key,
+                           pair_np);
+    else
+        hipLaunchKernelGGL((k_emit_plan_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
+                           seg_lds_bytes(kBatchTile, 8), s, items, count, gpiece_off, gpair_off, ppair, psub, pair_key,
+                           pair_np);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_piece_dest_batched(const SegItem *items, int count, const int64_t *piece_base, const uint32_t *ppair,
+                                     const uint32_t *psub, const uint32_t *pair_first, int64_t n, hipStream_t s) {
+    if (n == 0) return SPT_OK;
+    const int64_t g = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_piece_dest_batched, dim3((unsigned)g), dim3(256), 0, s, items, count, piece_base, ppair, psub,
+                       pair_first, n);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
 
 spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
                                        int64_t *counts, hipStream_t s) {

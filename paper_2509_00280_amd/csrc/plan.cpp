@@ -118,12 +118,17 @@ void release_mode_plan(Tensor *t, int n) {
     p = ModePlan{};
 }
 
+void release_batch_plan(Tensor *t, int n, hipStream_t s) {
+    ModePlan &p = t->bplan[n];
+    for (void *q : {(void *)p.pl_pos, (void *)p.pl_off, (void *)p.pl_desc, (void *)p.pl_row, (void *)p.pl_dest})
+        dev_free(q, s);
+    p = ModePlan{};
+}
+
 void release_plans(Tensor *t) {
     for (int n = 0; n < kMaxModes; ++n) {
         release_mode_plan(t, n);
-        dev_free(t->bseg_off[n], nullptr);  // callers order this after the tensor's last use
-        t->bseg_off[n] = nullptr;
-        t->bseg_records[n] = 0;
+        release_batch_plan(t, n, nullptr);  // callers order this after the tensor's last use
     }
 }
 

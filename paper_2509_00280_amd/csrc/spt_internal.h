@@ -90,9 +90,8 @@ struct Tensor {
     double norm_x2 = 0.0;
     spt_plan plan{};
     ModePlan mplan[kMaxModes];
-    // batched SEGMENT plan per mode (tiles of kBatchTile): per-tile record offsets
-    int64_t *bseg_off[kMaxModes] = {};
-    int64_t bseg_records[kMaxModes] = {};
+    // batched SEGMENT plan per mode (tiles of kBatchTile; stream-ordered allocations)
+    ModePlan bplan[kMaxModes];
     void *ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
 };
@@ -107,6 +106,8 @@ void release_plans(Tensor *t);
 void tensor_release(Tensor *t, hipStream_t s);
 // drop the cached plan of one mode (the next call at that mode plans again)
 void release_mode_plan(Tensor *t, int mode);
+// drop a batched plan (stream-ordered frees on s)
+void release_batch_plan(Tensor *t, int mode, hipStream_t s);
 bool seg_tile_ok(int tile, int nmodes);
 bool priv_feasible(const Tensor *t, int mode, int rank);
 // workspace slot of at least `bytes` (synchronises s before replacing a smaller buffer)
@@ -175,29 +176,40 @@ spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const 
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 
 // Batched SEGMENT MTTKRP: every tensor's tiles of kBatchTile nonzeros in one
-// launch; records carry global rows (row_base + row) of the batch's
-// concatenated output and are written at rec_base + the tile's offset.
+// launch, each with the tensor's batched plan (a.pl_*); records carry rows of
+// the batch's concatenated output (row_base + row) and go to rec_base + the
+// plan's record, so the batch's records stay grouped by row.
 constexpr int kBatchTile = 2048;
 struct SegItem {
-    MttkrpArgs a;        // a.rec_off: the tensor's per-tile record offsets for this mode
+    MttkrpArgs a;        // a.pl_*: the tensor's batched plan for this mode; a.rec_cap its records
     int64_t first_tile;  // prefix of tiles over the batch
     int64_t rec_base;    // first record of this tensor
     int64_t row_base;    // first row of this tensor in the concatenated output
 };
 bool seg_batch_fits(int nmodes_max);
+// per global tile: pieces | distinct rows << 32
 spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
                                        int64_t *counts, hipStream_t s);
+spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+                                    const int64_t *gpiece_off, const int64_t *gpair_off, uint32_t *ppair,
+                                    uint32_t *psub, uint64_t *pair_key, uint32_t *pair_np, hipStream_t s);
+spt_status launch_piece_dest_batched(const SegItem *items, int count, const int64_t *piece_base, const uint32_t *ppair,
+                                     const uint32_t *psub, const uint32_t *pair_first, int64_t n, hipStream_t s);
 spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int ld,
                                      bool vec4, uint64_t *rec_row, float *rec_val, hipStream_t s);
 
 // Batched dense steps (dense.hip): one workgroup per item, except apply
 // (a grid over the items' row blocks).
+constexpr int kGramSliceRows = 2048;  // rows per workgroup of the batched Gram
 struct GramItem {
     const float *C;   // rows x rank, leading dimension ld
     int64_t rows;
     int ld, rank;
     double *G;        // rank x rank (out)
+    int64_t first_slice, nslices;  // the item's row slices in the launch (gram_slices(rows) of them)
 };
+int64_t gram_slices(int64_t rows);
+size_t gram_batched_ws_bytes(int64_t total_slices, int rmax);
 struct SolveItem {
     const double *grams;  // nmodes x rank x rank
     const double *gram_m; // rank x rank Gram of the MTTKRP output
@@ -220,7 +232,8 @@ struct FitItem {
     double norm_x2;
     int nmodes, rank, nparts, pad;
 };
-spt_status launch_gram_batched(const GramItem *items, int count, int rmax, hipStream_t s);
+spt_status launch_gram_batched(const GramItem *items, int count, int64_t total_slices, int rmax, double *work,
+                               hipStream_t s);
 spt_status launch_solve_prep_batched(const SolveItem *items, int count, int mode, hipStream_t s);
 int apply_rows_per_launch_block(int rmax);
 spt_status launch_apply_batched(const ApplyItem *items, int count, int64_t total_blocks, int rmax, hipStream_t s);
@@ -254,6 +267,7 @@ struct ModeItems {
     std::vector<int> member_idx;
     std::vector<SegItem> seg_v;
     std::vector<GramItem> gm_v, gc_v;
+    int64_t gm_slices = 0, gc_slices = 0;
     std::vector<SolveItem> sv_v;
     std::vector<ApplyItem> ap_v;
 };
@@ -325,6 +339,8 @@ private:
     char *d_items_ = nullptr;
     size_t items_bytes_ = 0, fit_off_ = 0, init_off_ = 0;
     int init_count_ = 0, init_rmax_ = 0;
+    int64_t init_slices_ = 0;
+    DevBuf gram_ws_;  // partial Grams of the batched Gram launches
     float *M_all_ = nullptr;
     size_t M_bytes_ = 0;
     double *fit_all_ = nullptr, *inner_all_ = nullptr, *resid_ = nullptr;
