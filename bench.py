@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "mttkrp_ratings_hbm_traffic.txt")
+def pmc_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"mttkrp_{workload}_hbm_traffic.txt")
 
 
 def log(msg):
@@ -61,7 +62,8 @@ def algorithmic_bytes(t, rank: int, mode: int) -> int:
 def cpu_baseline(t, factors, budget_s: float = 20.0):
     """The FP64 oracle MTTKRP (single thread, as it stands) on a bounded sample."""
     import oracle
-    n = min(t.nnz, 100_000_000)
+    # about 10-30 s of single-thread FP64 work: the whole ratings tensor, a prefix of larger ones
+    n = min(t.nnz, 100_000_000 if factors[0].shape[1] <= 32 else 20_000_000)
     sample = slice(0, n)
     c = np.ascontiguousarray(t.coords[:, sample])
     v = np.ascontiguousarray(t.vals[sample])
@@ -80,15 +82,23 @@ def cpu_baseline(t, factors, budget_s: float = 20.0):
                       f"{el:.1f} s on 1 thread of {os.cpu_count()} host cores"}
 
 
-PROFILE_CMDS = {
-    "kt": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/kt -o kt -- "
-          "python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "cf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/cf -o cf -- python -u bench.py --copy-calibration",
-    "cw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/cw -o cw -- python -u bench.py --copy-calibration",
-    "bf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/bf -o bf -- "
-          "python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline",
-    "bw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/bw -o bw -- "
-          "python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+def profile_cmds(workload: str) -> dict:
+    w = "" if workload == "ratings" else f" --workload {workload}"
+    return {
+        "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/kt -o kt -- "
+              f"python -u bench.py{w} --steps 2 --warmup 1 --no-cpu-baseline",
+        "cf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/cf -o cf -- python -u bench.py --copy-calibration",
+        "cw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/cw -o cw -- python -u bench.py --copy-calibration",
+        "bf": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/bf -o bf -- "
+              f"python -u bench.py{w} --steps 1 --warmup 0 --no-cpu-baseline",
+        "bw": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/bw -o bw -- "
+              f"python -u bench.py{w} --steps 1 --warmup 0 --no-cpu-baseline",
+    }
+
+
+WORKLOAD_TITLE = {
+    "ratings": "the ratings benchmark (480000 x 18000 x 2000, 100M nonzeros, rank 32)",
+    "skewed4d": "the skewed 4-mode benchmark (2000000 x 100000 x 50000 x 24, 150M nonzeros, rank 64)",
 }
 CALL_FIRST = ("k_mttkrp_seg", "k_mttkrp_table", "k_mttkrp<")
 CALL_LAST = ("k_reduce_records", "k_reduce_priv")
@@ -124,9 +134,10 @@ def _call_windows(rows, key):
     return calls
 
 
-def summarize_profiles(d: str):
+def summarize_profiles(d: str, workload: str = "ratings"):
     """Write the committed summaries from rocprofv3 CSV output under d."""
-    lines = ["# Kernel trace of the ratings benchmark (480000 x 18000 x 2000, 100M nonzeros, rank 32)",
+    PROFILE_CMDS = profile_cmds(workload)
+    lines = [f"# Kernel trace of {WORKLOAD_TITLE[workload]}",
              f"# command: cd /tmp && export TMPDIR=/tmp; cd <repo>; {PROFILE_CMDS['kt']}",
              "# columns: calls, average us, total ms, percent of GPU time, kernel", ""]
     st = _read_csv(os.path.join(d, "kt", "kt_kernel_stats.csv"))
@@ -141,7 +152,7 @@ def summarize_profiles(d: str):
         lines += ["", f"MTTKRP calls: {len(calls)}; kernel time per call (all kernels of the call) "
                       f"avg {sum(c[0] for c in calls) / len(calls):.1f} us; main kernel avg {sum(main) / len(main):.1f} us",
                   "kernels of one call: " + " ".join(calls[-1][1])]
-    with open(os.path.join(ROOT, "profiles", "mttkrp_ratings_kernels.txt"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"mttkrp_{workload}_kernels.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
     def copy_factor(sub):
@@ -158,8 +169,8 @@ def summarize_profiles(d: str):
     fetch = sum(c[0] for c in cf_) / len(cf_) * 1024 * ff
     write = sum(c[0] for c in cw_) / len(cw_) * 1024 * wf
     from paper_2509_00280_amd import synth
-    nnz = synth._CONFIGS["ratings"][2]
-    out = ["# HBM traffic of one mode-n MTTKRP call (all of its kernels) in the ratings benchmark",
+    nnz = synth._CONFIGS[workload][2]
+    out = [f"# HBM traffic of one mode-n MTTKRP call (all of its kernels) in {WORKLOAD_TITLE[workload]}",
            f"# commands (each its own run): cd /tmp && export TMPDIR=/tmp; cd <repo>;",
            f"#   {PROFILE_CMDS['cf']}", f"#   {PROFILE_CMDS['cw']}", f"#   {PROFILE_CMDS['bf']}", f"#   {PROFILE_CMDS['bw']}",
            f"# calibration: a 1 GiB device copy reads FETCH_SIZE {fk:.0f} KiB and WRITE_SIZE {wk:.0f} KiB per dispatch,",
@@ -171,7 +182,7 @@ def summarize_profiles(d: str):
            f"write_bytes_per_launch: {write:.0f}",
            f"hbm_bytes_per_launch: {fetch + write:.0f}",
            f"hbm_bytes_per_nnz: {(fetch + write) / nnz:.2f}"]
-    with open(PMC_FILE, "w") as f:
+    with open(pmc_file(workload), "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(lines + [""] + out))
 
@@ -315,8 +326,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nnz", type=float, default=None, help="scale the tensor down (debug only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("ratings", "batch", "serve"), default="ratings",
-                    help="ratings: the headline MTTKRP benchmark; batch: batched vs per-tensor CP-ALS; "
+    ap.add_argument("--workload", choices=("ratings", "skewed4d", "batch", "serve"), default="ratings",
+                    help="ratings: the headline MTTKRP benchmark; skewed4d: the 4-mode rank-64 tensor whose "
+                         "factors exceed the Infinity Cache; batch: batched vs per-tensor CP-ALS; "
                          "serve: continuous-batching server latency")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=10)
@@ -329,7 +341,7 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles)
+        summarize_profiles(args.summarize_profiles, args.workload)
         return
     if args.copy_calibration:
         import torch
@@ -356,7 +368,7 @@ def main():
     from paper_2509_00280_amd import spt, synth
 
     t0 = time.time()
-    t, F, rank, iters = synth.config("ratings", nnz=None if args.nnz is None else int(args.nnz))
+    t, F, rank, iters = synth.config(args.workload, nnz=None if args.nnz is None else int(args.nnz))
     log(f"generated {t.nnz} nonzeros in {time.time() - t0:.1f} s")
     dev = torch.device("cuda:0")
     coords = torch.from_numpy(t.coords.view(np.int32)).to(dev)
@@ -401,9 +413,9 @@ def main():
     alg_avg = sum(alg) / nm
     achieved = alg_avg / (mk_ms * 1e-3) / 1e9
     traffic = None
-    if os.path.exists(PMC_FILE):
+    if os.path.exists(pmc_file(args.workload)):
         pmc = {}
-        with open(PMC_FILE) as f:
+        with open(pmc_file(args.workload)) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -415,14 +427,19 @@ def main():
                 "kernel": "one mode-n MTTKRP call (k_mttkrp_seg, record radix sort, k_reduce_records)",
                 "algorithmic_bytes_per_launch": int(alg_avg),
                 "avg_launch_ms": round(mk_ms, 4)}
+    shape = "x".join(map(str, t.dims))
+    if args.workload == "ratings":
+        desc = (f"ratings-shaped 3-mode tensor {shape}, {t.nnz} nonzeros, Zipf(1.1)/Zipf(1.1)/uniform labels, "
+                f"values in 1..5, rank {rank}, ")
+    else:
+        desc = (f"skewed 4-mode tensor {shape}, {t.nnz} nonzeros, Zipf(1.3) x3 / uniform labels, "
+                f"lognormal values, rank {rank}, ")
     out = {
         "metric": "MTTKRP Gnnz/s per mode", "value": round(value, 3), "unit": "Gnnz/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"ratings-shaped 3-mode tensor {'x'.join(map(str, t.dims))}, {t.nnz} nonzeros, "
-                               f"Zipf(1.1)/Zipf(1.1)/uniform labels, values in 1..5, rank {rank}, "
-                               f"GPU encode + {iters} CP-ALS iterations per step",
+        "config": {"workload": desc + f"GPU encode + {iters} CP-ALS iterations per step",
                    "nnz": t.nnz, "rank": rank, "iters": iters, "parallelism": "single GPU"},
         "mttkrp_per_mode": per_mode,
         "solves_per_s": round(1e3 / ms_step, 4),

@@ -78,12 +78,14 @@ typedef struct {
                                    except for rows split between two reducer chunks) */
 #define SPT_STRATEGY_PRIV 3     /* the whole output (or column slices of it) lives in each workgroup's LDS;
                                    workgroup partials are summed (small modes) */
-#define SPT_STRATEGY_AUTO 4     /* PRIV for outputs that fit LDS in one pass with at most 256 rows,
-                                   else SEGMENT */
-#define SPT_STRATEGY_SEGMENT 5  /* regroup each tile by output row in LDS; every run of at most 32
-                                   nonzeros of one row becomes a record written with plain stores;
-                                   records are radix-sorted by row and summed (no atomics except for
-                                   rows split between two reducer chunks) */
+#define SPT_STRATEGY_AUTO 4     /* SEGMENT (measured fastest for small and large output modes);
+                                   the autotuner also tries PRIV where it fits */
+#define SPT_STRATEGY_SEGMENT 5  /* each tile regrouped by output row (the plan: positions of every
+                                   nonzero, pieces of at most 32 nonzeros of one row); every piece
+                                   becomes a record written with plain stores at a slot that keeps the
+                                   records grouped by row; records are summed per row (no atomics
+                                   except for rows split between two reducer chunks).  The first call
+                                   at a mode builds the plan: 2 B per nonzero plus 12 B per piece */
 typedef struct {
     int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256..1024 for DIRECT/REGROUP (larger
                                      values act as 1024), 1024/2048/4096 for SEGMENT (smaller values,

@@ -223,10 +223,7 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
     int want = t->plan.strategy[mode];
     const int64_t rows = t->dims[mode];
     int npass = 1, rs = rank, stride = rank + 1;
-    if (want == SPT_STRATEGY_AUTO) {
-        want = (rows <= 256 && priv_params(t->nmodes, rows, rank, 1, &npass, &rs, &stride)) ? SPT_STRATEGY_PRIV
-                                                                                              : SPT_STRATEGY_SEGMENT;
-    }
+    if (want == SPT_STRATEGY_AUTO) want = SPT_STRATEGY_SEGMENT;  // measured fastest for every mode size
     if (p.valid && p.rank == rank && p.strategy == want) {
         *out = &p;
         return SPT_OK;
