@@ -221,15 +221,20 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
     for (int o = 0; o < NO; ++o) fo[o] = o < no ? a.f[o + (o >= mode)] : nullptr;
     constexpr int NG = NT / G;
     if (npieces <= 0) return;
-    int k = threadIdx.x / G;
-    typename Pieces::Raw cur = pieces.fetch(k < npieces ? k : 0);
-    for (; k < npieces; k += NG) {
+    // pieces are dealt in snake order (round r: group g, then NG - 1 - g),
+    // which balances the groups when the plan lists the pieces longest first
+    const int g = threadIdx.x / G;
+    const int nr = (npieces + NG - 1) / NG;
+    auto kof = [&](int r) { return min(r * NG + ((r & 1) ? NG - 1 - g : g), npieces - 1); };
+    typename Pieces::Raw cur = pieces.fetch(kof(0));
+    for (int r = 0; r < nr; ++r) {
+        const int k = r * NG + ((r & 1) ? NG - 1 - g : g);
         // the next piece's descriptor is fetched while this one is walked
-        const typename Pieces::Raw nxt = pieces.fetch(k + NG < npieces ? k + NG : k);
+        const typename Pieces::Raw nxt = pieces.fetch(kof(r + 1));
         int p0, p1;
         uint32_t prow;
         int64_t pos;
-        const bool live = pieces.decode(k, cur, p0, p1, prow, pos);
+        const bool live = k < npieces && pieces.decode(k, cur, p0, p1, prow, pos);
         cur = nxt;
         if (!live) continue;
         float acc[NB][VEC];
@@ -508,19 +513,44 @@ __device__ __forceinline__ void emit_tile(const MttkrpArgs &a, int64_t tile, cha
             pair_np[qbase + occ[i]] = (c + kPiece - 1) / kPiece;
         }
     }
+    // the tile's pieces are stored longest first (a counting sort on the
+    // length): dealt to lane groups in snake order they balance the walk
+    __shared__ uint32_t lstart[kPiece + 1];
     const int npieces = (int)(L.hcnt[T] & 0xFFFFu);
-    for (int k = threadIdx.x; k < npieces; k += NT) {
-        const int s = L.ptab[k];
+    auto piece = [&](int k, int &s, int &i, int &p0, int &p1) {
+        s = L.ptab[k];
         const uint32_t pk = L.hcnt[s];
         const uint32_t pn = (s + 1 < T) ? L.hcnt[s + 1] : L.hcnt[T];
         const int first = (int)(pk >> 16), last = (int)(pn >> 16);
-        const int i = k - (int)(pk & 0xFFFFu);
-        const int p0 = first + i * kPiece;
-        const int p1 = min(p0 + kPiece, last);
-        desc[pbase + k] = (uint32_t)p0 | ((uint32_t)(p1 - p0) << 16);
-        prow[pbase + k] = L.hkey[s];
-        ppair[gpiece + k] = (uint32_t)(qbase + occ[s]);
-        psub[gpiece + k] = (uint32_t)i;
+        i = k - (int)(pk & 0xFFFFu);
+        p0 = first + i * kPiece;
+        p1 = min(p0 + kPiece, last);
+    };
+    for (int b = threadIdx.x; b <= kPiece; b += NT) lstart[b] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < npieces; k += NT) {
+        int sl, i, p0, p1;
+        piece(k, sl, i, p0, p1);
+        atomicAdd(&lstart[kPiece - (p1 - p0)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b <= kPiece; ++b) {
+            const uint32_t c = lstart[b];
+            lstart[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < npieces; k += NT) {
+        int sl, i, p0, p1;
+        piece(k, sl, i, p0, p1);
+        const uint32_t q = atomicAdd(&lstart[kPiece - (p1 - p0)], 1u);
+        desc[pbase + q] = (uint32_t)p0 | ((uint32_t)(p1 - p0) << 16);
+        prow[pbase + q] = L.hkey[sl];
+        ppair[gpiece + q] = (uint32_t)(qbase + occ[sl]);
+        psub[gpiece + q] = (uint32_t)i;
     }
 }
 
