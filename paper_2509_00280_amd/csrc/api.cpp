@@ -130,7 +130,10 @@ MttkrpArgs make_args(const Tensor *t, const float *const *factors, int rank, int
     a.mode = mode;
     a.rank = rank;
     a.tile = tile;
-    for (int k = 0; k < t->nmodes; ++k) a.f[k] = factors ? factors[k] : nullptr;
+    for (int k = 0; k < t->nmodes; ++k) {
+        a.f[k] = factors ? factors[k] : nullptr;
+        a.frows[k] = (uint32_t)std::min<int64_t>(t->dims[k], 0xFFFFFFFFll);
+    }
     a.out = out;
     a.codec = t->codec;
     return a;

@@ -186,7 +186,7 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
 }
 
 // The batched MTTKRP pipeline of one mode into M_all (rows x ld, overwritten).
-spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_max,
+spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_min, int nmodes_max,
                                    int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
                                    BatchMttkrpWs &ws, hipStream_t s) {
     if (rows == 0) return SPT_OK;
@@ -197,7 +197,7 @@ spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t to
     float *rval = (float *)ws.rec_val.get(sizeof(float) * n1 * ld, s);
     if (!rrow || !rval) return fail(SPT_E_OOM, "batch: record workspace");
     // the batch's records come out grouped by row: no sort
-    spt_status st = launch_mttkrp_seg_batched(d_items, count, total_tiles, nmodes_max, ld, vec4, rrow, rval, s);
+    spt_status st = launch_mttkrp_seg_batched(d_items, count, total_tiles, nmodes_min, nmodes_max, ld, vec4, rrow, rval, s);
     if (st == SPT_OK) st = launch_fill_zero(M_all, rows * (int64_t)ld, s);
     if (st == SPT_OK) st = launch_reduce_records(rrow, nullptr, rval, records, ld, rows, M_all, s);
     return st;
@@ -269,7 +269,11 @@ spt_status BatchEngine::rebuild() {
         if (!m->done) act.push_back(m);
     active_ = act;
     nmodes_max_ = 0;
-    for (Member *m : act) nmodes_max_ = std::max(nmodes_max_, m->t->nmodes);
+    nmodes_min_ = kMaxModes;
+    for (Member *m : act) {
+        nmodes_max_ = std::max(nmodes_max_, m->t->nmodes);
+        nmodes_min_ = std::min(nmodes_min_, m->t->nmodes);
+    }
     if (!act.empty() && !seg_batch_fits(nmodes_max_)) return fail(SPT_E_INVALID_ARG, "batch: too many modes");
     std::vector<Tensor *> ts;
     for (Member *m : act) ts.push_back(m->t);
@@ -493,7 +497,7 @@ spt_status BatchEngine::step() {
     for (int n = 0; n < nmodes_max_; ++n) {
         const ModeItems &mi = modes_[n];
         if (mi.count == 0) continue;
-        spt_status st = run_mttkrp_batched_mode((const SegItem *)(d_items_ + mi.seg_off), mi.count, mi.tiles, nmodes_max_,
+        spt_status st = run_mttkrp_batched_mode((const SegItem *)(d_items_ + mi.seg_off), mi.count, mi.tiles, nmodes_min_, nmodes_max_,
                                                 mi.records, mi.rows, mi.ld, mi.vec4, M_all_, ws_, s_);
         if (st == SPT_OK)
             st = launch_gram_batched((const GramItem *)(d_items_ + mi.gm_off), mi.count, mi.gm_slices, mi.rmax,
@@ -584,7 +588,7 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
     hipStream_t s = (hipStream_t)stream;
     std::vector<Tensor *> tv;
     std::vector<int> idx;
-    int rmax = 0, nmax = 0;
+    int rmax = 0, nmax = 0, nmin = kMaxModes;
     bool vec4 = true;
     for (int b = 0; b < count; ++b) {
         Tensor *t = ts[b];
@@ -598,6 +602,7 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         idx.push_back(b);
         rmax = std::max(rmax, ranks[b]);
         nmax = std::max(nmax, t->nmodes);
+        nmin = std::min(nmin, t->nmodes);
         vec4 = vec4 && ranks[b] % 4 == 0;
     }
     if (tv.empty()) return SPT_OK;
@@ -632,7 +637,7 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
     BatchMttkrpWs ws;
     if (hipMemcpyAsync(d_items, items.data(), sizeof(SegItem) * items.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         st = hip_fail(hipGetLastError(), "mttkrp_batched: upload");
-    if (st == SPT_OK) st = run_mttkrp_batched_mode(d_items, (int)items.size(), tiles, nmax, recs, rows, ld, vec4, M, ws, s);
+    if (st == SPT_OK) st = run_mttkrp_batched_mode(d_items, (int)items.size(), tiles, nmin, nmax, recs, rows, ld, vec4, M, ws, s);
     for (size_t i = 0; st == SPT_OK && i < tv.size(); ++i) {
         const int b = idx[i];
         const int64_t In = tv[i]->dims[mode];

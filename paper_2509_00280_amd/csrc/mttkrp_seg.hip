@@ -203,8 +203,11 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 // EXACT: the lane groups cover exactly R columns (no column mask).
 // With at most 4 modes every nonzero slot of an unrolled step reads all its
 // coordinates from LDS first, then issues every factor-row gather, then waits
-// once; with more modes the gathers go mode by mode.
-template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT, class Pieces>
+// once; with more modes the gathers go mode by mode.  NFIX > 0: the tensor has
+// exactly NFIX modes (no run-time mode test between the gathers, which would
+// otherwise make the compiler wait for one mode's rows before the next
+// mode's gathers are issued).
+template <int NT, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__restrict__ crdg,
                                          const float *__restrict__ valg, int npieces, const Pieces &pieces,
                                          uint64_t *__restrict__ rec_row, float *__restrict__ rec_val, int ld,
@@ -213,12 +216,15 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
     constexpr int UB = kUnroll;
     constexpr int NO = NMAX - 1;  // non-output modes at most
     const int j = threadIdx.x % G;
-    const int R = a.rank, mode = a.mode, no = a.nmodes - 1;
-    const uint32_t Ru = (uint32_t)R;
-    // factor of the o-th non-output mode
-    const float *fo[NO];
+    static_assert(NFIX == 0 || NFIX == NMAX, "a fixed mode count is the maximum");
+    const int R = a.rank, mode = a.mode, no = NFIX ? NFIX - 1 : a.nmodes - 1;
+    // factor of the o-th non-output mode as a row buffer
+    spt_i4 fb[NO];
 #pragma unroll
-    for (int o = 0; o < NO; ++o) fo[o] = o < no ? a.f[o + (o >= mode)] : nullptr;
+    for (int o = 0; o < NO; ++o) {
+        const int k = o + (o >= mode);
+        fb[o] = o < no ? row_rsrc(a.f[k], R, a.frows[k]) : row_rsrc(nullptr, R, 0u);
+    }
     constexpr int NG = NT / G;
     if (npieces <= 0) return;
     // pieces are dealt in snake order (round r: group g, then NG - 1 - g),
@@ -272,12 +278,11 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
                     if (o < no) {
 #pragma unroll
                         for (int u = 0; u < UB; ++u) {
-                            const float *fr = fo[o] + (uint64_t)row[o][u] * Ru;
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 const int c = (b * G + j) * VEC;
                                 if (EXACT || c < R) {
-                                    load_vec<VEC>(fr + c, xv[o][u][b]);
+                                    load_row_vec<VEC>(fb[o], row[o][u], c, xv[o][u][b]);
                                 } else {
 #pragma unroll
                                     for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
@@ -302,12 +307,12 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
                         float xv[UB][NB][VEC];
 #pragma unroll
                         for (int u = 0; u < UB; ++u) {
-                            const float *fr = fo[o] + (uint64_t)crdg[o * T + pp[u]] * Ru;
+                            const uint32_t rw = crdg[o * T + pp[u]];
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 const int c = (b * G + j) * VEC;
                                 if (EXACT || c < R) {
-                                    load_vec<VEC>(fr + c, xv[u][b]);
+                                    load_row_vec<VEC>(fb[o], rw, c, xv[u][b]);
                                 } else {
 #pragma unroll
                                     for (int v = 0; v < VEC; ++v) xv[u][b][v] = 0.f;
@@ -373,11 +378,11 @@ struct PlanPieces {
 // record), with the records of one row contiguous.  A tile is staged by one
 // scatter of values and non-output coordinates to their positions; there is
 // no hashing, no atomic and no scan at run time.
-template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
+template <int NT, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
 __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, char *lds, uint64_t *__restrict__ rec_row,
                                           float *__restrict__ rec_val, int ld, int64_t rec_base, int64_t row_base) {
     constexpr int T = 4 * NT;
-    const int nm = a.nmodes, mode = a.mode, tid = threadIdx.x;
+    const int nm = NFIX ? NFIX : a.nmodes, mode = a.mode, tid = threadIdx.x;
     uint32_t *crdg = (uint32_t *)lds;
     float *valg = (float *)(crdg + (size_t)(nm - 1) * T);
     const CodecRegs cr = load_codec_regs(a.codec);
@@ -437,17 +442,17 @@ __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, cha
     for (int u = 0; u < 4; ++u)
         if (tid + u * NT < cnt) valg[ps[u]] = v[u];
     __syncthreads();
-    seg_walk<NT, G, VEC, NB, NMAX, EXACT>(a, crdg, valg, npieces,
+    seg_walk<NT, G, VEC, NB, NMAX, NFIX, EXACT>(a, crdg, valg, npieces,
                                           PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, rec_base},
                                           rec_row, rec_val, ld, row_base);
 }
 
-template <int NT, int G, int VEC, int NB, int NMAX, bool EXACT>
+template <int NT, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
 __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles) {
     extern __shared__ __align__(16) char lds[];
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    segp_tile<NT, G, VEC, NB, NMAX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
+    segp_tile<NT, G, VEC, NB, NMAX, NFIX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
 }
 
 // Batched: tile `it` of the whole batch belongs to the last item whose
@@ -465,7 +470,7 @@ __device__ __forceinline__ int seg_item_of(const SegItem *__restrict__ items, in
 // Every tensor's records start at its rec_base in the batch's record array,
 // its rows at row_base of the concatenated output (records of the whole batch
 // stay grouped by row: tensors are laid out in order).
-template <int NT, int G, int VEC, int NB, int NMAX>
+template <int NT, int G, int VEC, int NB, int NMAX, int NFIX>
 __global__ __launch_bounds__(NT) void k_mttkrp_segp_batched(const SegItem *__restrict__ items, int count,
                                                             int64_t total_tiles, uint64_t *__restrict__ rec_row,
                                                             float *__restrict__ rec_val, int ld) {
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp_batched(const SegItem *__res
     if (it >= total_tiles) return;
     const int b = seg_item_of(items, count, it);
     const SegItem &item = items[b];
-    segp_tile<NT, G, VEC, NB, NMAX, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
+    segp_tile<NT, G, VEC, NB, NMAX, NFIX, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
                                            item.row_base);
 }
 
@@ -663,34 +668,34 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
     if (threadIdx.x == 0) out[it] = c;
 }
 
-template <int NT, int NMAX, int G, int VEC, int NB>
+template <int NT, int NMAX, int NFIX, int G, int VEC, int NB>
 spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
     const size_t lds = segp_lds_bytes(4 * NT, a.nmodes);
     if (a.rank == G * VEC * NB)
-        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, NFIX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
     else
-        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, false>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, NFIX, false>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
 
-template <int NT, int NMAX>
+template <int NT, int NMAX, int NFIX>
 spt_status launch_seg_nt(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
     const int R = a.rank;
     if ((R & 3) == 0) {
         const int r4 = R >> 2;
-        if (r4 <= 1) return launch_seg_k<NT, NMAX, 1, 4, 1>(a, ntiles, s);
-        if (r4 <= 2) return launch_seg_k<NT, NMAX, 2, 4, 1>(a, ntiles, s);
-        if (r4 <= 4) return launch_seg_k<NT, NMAX, 4, 4, 1>(a, ntiles, s);
-        if (r4 <= 8) return launch_seg_k<NT, NMAX, 8, 4, 1>(a, ntiles, s);
-        if (r4 <= 16) return launch_seg_k<NT, NMAX, 16, 4, 1>(a, ntiles, s);
-        if (r4 <= 32) return launch_seg_k<NT, NMAX, 32, 4, 1>(a, ntiles, s);
-        return launch_seg_k<NT, NMAX, 64, 4, 1>(a, ntiles, s);
+        if (r4 <= 1) return launch_seg_k<NT, NMAX, NFIX, 1, 4, 1>(a, ntiles, s);
+        if (r4 <= 2) return launch_seg_k<NT, NMAX, NFIX, 2, 4, 1>(a, ntiles, s);
+        if (r4 <= 4) return launch_seg_k<NT, NMAX, NFIX, 4, 4, 1>(a, ntiles, s);
+        if (r4 <= 8) return launch_seg_k<NT, NMAX, NFIX, 8, 4, 1>(a, ntiles, s);
+        if (r4 <= 16) return launch_seg_k<NT, NMAX, NFIX, 16, 4, 1>(a, ntiles, s);
+        if (r4 <= 32) return launch_seg_k<NT, NMAX, NFIX, 32, 4, 1>(a, ntiles, s);
+        return launch_seg_k<NT, NMAX, NFIX, 64, 4, 1>(a, ntiles, s);
     }
-    if (R <= 64) return launch_seg_k<NT, NMAX, 64, 1, 1>(a, ntiles, s);
-    if (R <= 128) return launch_seg_k<NT, NMAX, 64, 1, 2>(a, ntiles, s);
-    if (R <= 192) return launch_seg_k<NT, NMAX, 64, 1, 3>(a, ntiles, s);
-    return launch_seg_k<NT, NMAX, 64, 1, 4>(a, ntiles, s);
+    if (R <= 64) return launch_seg_k<NT, NMAX, NFIX, 64, 1, 1>(a, ntiles, s);
+    if (R <= 128) return launch_seg_k<NT, NMAX, NFIX, 64, 1, 2>(a, ntiles, s);
+    if (R <= 192) return launch_seg_k<NT, NMAX, NFIX, 64, 1, 3>(a, ntiles, s);
+    return launch_seg_k<NT, NMAX, NFIX, 64, 1, 4>(a, ntiles, s);
 }
 
 template <int NT>
@@ -752,45 +757,50 @@ spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t
     return launch_count_nt<1024>(a, ntiles, counts, s);
 }
 
+namespace {
+// 3 and 4 modes get a kernel with the mode count fixed; others the general one
+template <int NT>
+spt_status launch_seg_tile(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
+    const int nm = a.nmodes;
+    if (nm == 3) return launch_seg_nt<NT, 3, 3>(a, ntiles, s);
+    if (nm == 4) return launch_seg_nt<NT, 4, 4>(a, ntiles, s);
+    return nm < 3 ? launch_seg_nt<NT, 3, 0>(a, ntiles, s) : launch_seg_nt<NT, 8, 0>(a, ntiles, s);
+}
+}  // namespace
+
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
     if (ntiles == 0) return SPT_OK;
     if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
-    const int nm = a.nmodes;
-    if (a.tile == 1024)
-        return nm <= 3 ? launch_seg_nt<256, 3>(a, ntiles, s)
-                       : (nm <= 4 ? launch_seg_nt<256, 4>(a, ntiles, s) : launch_seg_nt<256, 8>(a, ntiles, s));
-    if (a.tile == 2048)
-        return nm <= 3 ? launch_seg_nt<512, 3>(a, ntiles, s)
-                       : (nm <= 4 ? launch_seg_nt<512, 4>(a, ntiles, s) : launch_seg_nt<512, 8>(a, ntiles, s));
-    return nm <= 3 ? launch_seg_nt<1024, 3>(a, ntiles, s)
-                   : (nm <= 4 ? launch_seg_nt<1024, 4>(a, ntiles, s) : launch_seg_nt<1024, 8>(a, ntiles, s));
+    if (a.tile == 1024) return launch_seg_tile<256>(a, ntiles, s);
+    if (a.tile == 2048) return launch_seg_tile<512>(a, ntiles, s);
+    return launch_seg_tile<1024>(a, ntiles, s);
 }
 
 namespace {
-template <int NMAX, int G, int VEC, int NB>
+template <int NMAX, int NFIX, int G, int VEC, int NB>
 spt_status launch_segb_k(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
                          int ld, hipStream_t s) {
     constexpr int NT = kBatchTile / 4;
     const size_t lds = segp_lds_bytes(kBatchTile, NMAX);
-    hipLaunchKernelGGL((k_mttkrp_segp_batched<NT, G, VEC, NB, NMAX>), dim3((unsigned)total_tiles), dim3(NT), lds, s,
+    hipLaunchKernelGGL((k_mttkrp_segp_batched<NT, G, VEC, NB, NMAX, NFIX>), dim3((unsigned)total_tiles), dim3(NT), lds, s,
                        items, count, total_tiles, rec_row, rec_val, ld);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
 
-template <int NMAX>
+template <int NMAX, int NFIX>
 spt_status launch_segb_n(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
                          int ld, bool vec4, hipStream_t s) {
     if (vec4) {
         const int r4 = ld >> 2;
-        if (r4 <= 1) return launch_segb_k<NMAX, 1, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        if (r4 <= 2) return launch_segb_k<NMAX, 2, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        if (r4 <= 4) return launch_segb_k<NMAX, 4, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        if (r4 <= 8) return launch_segb_k<NMAX, 8, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        return launch_segb_k<NMAX, 16, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 1) return launch_segb_k<NMAX, NFIX, 1, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 2) return launch_segb_k<NMAX, NFIX, 2, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 4) return launch_segb_k<NMAX, NFIX, 4, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 8) return launch_segb_k<NMAX, NFIX, 8, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        return launch_segb_k<NMAX, NFIX, 16, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
     }
-    return launch_segb_k<NMAX, 64, 1, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+    return launch_segb_k<NMAX, NFIX, 64, 1, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
 }
 }  // namespace
 
@@ -837,12 +847,15 @@ spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t 
     return SPT_OK;
 }
 
-spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int ld,
-                                     bool vec4, uint64_t *rec_row, float *rec_val, hipStream_t s) {
+spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_min,
+                                     int nmodes_max, int ld, bool vec4, uint64_t *rec_row, float *rec_val,
+                                     hipStream_t s) {
     if (total_tiles == 0) return SPT_OK;
     if (ld > 64 || (vec4 && (ld & 3))) return fail(SPT_E_INVALID_ARG, "batched MTTKRP: rank above 64");
-    if (nmodes_max <= 4) return launch_segb_n<4>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
-    return launch_segb_n<8>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
+    if (nmodes_min == 3 && nmodes_max == 3)
+        return launch_segb_n<3, 3>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
+    if (nmodes_max <= 4) return launch_segb_n<4, 0>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
+    return launch_segb_n<8, 0>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
 }
 
 }  // namespace spt

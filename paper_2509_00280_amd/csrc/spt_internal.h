@@ -144,6 +144,7 @@ struct MttkrpArgs {
     int rank;
     int tile;
     const float *f[kMaxModes];
+    uint32_t frows[kMaxModes];  // rows of each factor (clamped to 2^32 - 1)
     float *out;
     // SEGMENT strategy: record output
     uint64_t *rec_row;
@@ -195,8 +196,9 @@ spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t tot
                                     uint32_t *psub, uint64_t *pair_key, uint32_t *pair_np, hipStream_t s);
 spt_status launch_piece_dest_batched(const SegItem *items, int count, const int64_t *piece_base, const uint32_t *ppair,
                                      const uint32_t *psub, const uint32_t *pair_first, int64_t n, hipStream_t s);
-spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int ld,
-                                     bool vec4, uint64_t *rec_row, float *rec_val, hipStream_t s);
+spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_min,
+                                     int nmodes_max, int ld, bool vec4, uint64_t *rec_row, float *rec_val,
+                                     hipStream_t s);
 
 // Batched dense steps (dense.hip): one workgroup per item, except apply
 // (a grid over the items' row blocks).
@@ -307,7 +309,7 @@ struct BatchMttkrpWs {
         rec_row.release(); rec_val.release(); keys2.release(); ia.release(); ib.release(); cnt.release();
     }
 };
-spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_max,
+spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_min, int nmodes_max,
                                    int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
                                    BatchMttkrpWs &ws, hipStream_t s);
 spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s);
@@ -334,7 +336,7 @@ private:
     hipStream_t s_;
     std::vector<Member *> members_, active_;
     bool dirty_ = true;
-    int nmodes_max_ = 0;
+    int nmodes_max_ = 0, nmodes_min_ = 0;
     std::vector<ModeItems> modes_;
     char *d_items_ = nullptr;
     size_t items_bytes_ = 0, fit_off_ = 0, init_off_ = 0;

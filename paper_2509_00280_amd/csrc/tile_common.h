@@ -5,12 +5,19 @@
 
 namespace spt {
 
-// Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
-// contiguous range of work indices so its L2 sees the key-order locality.
+// Workgroups are dealt round-robin over the 8 XCDs.  Each XCD gets runs of
+// kXcdChunk consecutive work indices (its L2 sees the key-order locality
+// inside a run), and the runs of the 8 XCDs interleave over the whole index
+// range, so a heavy stretch of the tensor is shared by all XCDs instead of
+// landing on one (one contiguous eighth per XCD left the last XCD running
+// 1.5x longer than the first on skewed tensors).  A bijection on [0, nwg):
+// the indices past the last full round of 8 runs map to themselves.
+constexpr int64_t kXcdChunk = 64;
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nwg) {
-    const int64_t q = nwg >> 3, r = nwg & 7;
+    const int64_t full = (nwg / (8 * kXcdChunk)) * (8 * kXcdChunk);
+    if (b >= full) return b;
     const int64_t x = b & 7, j = b >> 3;
-    return x * q + (x < r ? x : r) + j;
+    return ((j / kXcdChunk) * 8 + x) * kXcdChunk + (j % kXcdChunk);
 }
 
 template <int VEC>
@@ -24,6 +31,41 @@ __device__ __forceinline__ void load_vec(const float *p, float (&x)[VEC]) {
     } else {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) x[q] = p[q];
+    }
+}
+
+// A factor matrix seen as a structured buffer whose records are its rows
+// (stride R floats): a gather passes the row index and the column's byte
+// offset straight to the load, with no address arithmetic, and rows past
+// `rows` read as zero.  The descriptor is wave-uniform (SGPRs); R <= 4095.
+typedef int spt_i4 __attribute__((ext_vector_type(4)));
+typedef float spt_f4 __attribute__((ext_vector_type(4)));
+__device__ spt_f4 spt_row_load4(spt_i4 rsrc, int vindex, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.struct.buffer.load.v4f32");
+__device__ float spt_row_load1(spt_i4 rsrc, int vindex, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.struct.buffer.load.f32");
+
+__device__ __forceinline__ spt_i4 row_rsrc(const float *base, int R, uint32_t rows) {
+    const uint64_t p = (uint64_t)base;
+    spt_i4 r;
+    r.x = (int)(uint32_t)p;
+    r.y = (int)(((uint32_t)(p >> 32) & 0xFFFFu) | ((uint32_t)(R * 4) << 16));  // base[47:32] | stride
+    r.z = (int)rows;                                                            // records
+    r.w = 0x00020000;                                                           // 32-bit data format
+    return r;
+}
+
+template <int VEC>
+__device__ __forceinline__ void load_row_vec(spt_i4 rsrc, uint32_t row, int col, float (&x)[VEC]) {
+    if constexpr (VEC == 4) {
+        const spt_f4 t = spt_row_load4(rsrc, (int)row, col * 4, 0, 0);
+        x[0] = t.x;
+        x[1] = t.y;
+        x[2] = t.z;
+        x[3] = t.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) x[q] = spt_row_load1(rsrc, (int)row, (col + q) * 4, 0, 0);
     }
 }
 
