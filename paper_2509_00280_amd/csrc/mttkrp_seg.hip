@@ -25,7 +25,7 @@
 #include "tile_common.h"
 
 #ifndef SPT_SEG_UB
-#define SPT_SEG_UB 2
+#define SPT_SEG_UB 1
 #endif
 #ifndef SPT_SEG_PIECE
 #define SPT_SEG_PIECE 32
@@ -37,6 +37,10 @@ namespace {
 
 constexpr int kPiece = SPT_SEG_PIECE;  // nonzeros per piece (L)
 constexpr int kUnroll = SPT_SEG_UB;    // nonzeros in flight per lane group
+#ifndef SPT_SEGP_NT4096
+#define SPT_SEGP_NT4096 1024
+#endif
+constexpr int kSegpThreads4096 = SPT_SEGP_NT4096;  // threads of the MTTKRP kernel on 4096-nonzero tiles
 
 // LDS of the hashing stage: crdg[nm - 1][T] u32 (non-output coordinates,
 // row-grouped), valg[T] f32, hkey[T] u32 (slot -> row), hcnt[T + 4] u32
@@ -207,12 +211,11 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 // exactly NFIX modes (no run-time mode test between the gathers, which would
 // otherwise make the compiler wait for one mode's rows before the next
 // mode's gathers are issued).
-template <int NT, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces>
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__restrict__ crdg,
                                          const float *__restrict__ valg, int npieces, const Pieces &pieces,
                                          uint64_t *__restrict__ rec_row, float *__restrict__ rec_val, int ld,
                                          int64_t row_base) {
-    constexpr int T = 4 * NT;
     constexpr int UB = kUnroll;
     constexpr int NO = NMAX - 1;  // non-output modes at most
     const int j = threadIdx.x % G;
@@ -378,10 +381,11 @@ struct PlanPieces {
 // record), with the records of one row contiguous.  A tile is staged by one
 // scatter of values and non-output coordinates to their positions; there is
 // no hashing, no atomic and no scan at run time.
-template <int NT, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
 __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, char *lds, uint64_t *__restrict__ rec_row,
                                           float *__restrict__ rec_val, int ld, int64_t rec_base, int64_t row_base) {
-    constexpr int T = 4 * NT;
+    constexpr int PER = T / NT;  // nonzeros staged per thread
+    static_assert(PER * NT == T && PER >= 1 && PER <= 8, "tile must be 1..8 nonzeros per thread");
     const int nm = NFIX ? NFIX : a.nmodes, mode = a.mode, tid = threadIdx.x;
     uint32_t *crdg = (uint32_t *)lds;
     float *valg = (float *)(crdg + (size_t)(nm - 1) * T);
@@ -392,11 +396,11 @@ __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, cha
     const int64_t rem = a.nnz - base;
     const int cnt = rem < T ? (int)rem : T;
     const int nwords = 2 * a.codec.key_words;
-    uint32_t w[4][4];
-    float v[4];
-    int ps[4];
+    uint32_t w[PER][4];
+    float v[PER];
+    int ps[PER];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < PER; ++u) {
         const int e = tid + u * NT;
         uint64_t klo = 0, khi = 0;
         float x = 0.f;
@@ -418,7 +422,9 @@ __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, cha
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         if (k < nm && k != mode) {
-            uint32_t x[4] = {0, 0, 0, 0};
+            uint32_t x[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) x[u] = 0;
 #pragma unroll
             for (int word = 0; word < 4; ++word) {
                 if (word < nwords) {
@@ -428,31 +434,31 @@ __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, cha
                         const uint32_t d = run_desc(cr, r);
                         const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) x[u] |= __builtin_amdgcn_ubfe(w[u][word], kpos, len) << cpos;
+                        for (int u = 0; u < PER; ++u) x[u] |= __builtin_amdgcn_ubfe(w[u][word], kpos, len) << cpos;
                     }
                 }
             }
             const int o = k - (k > mode);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < PER; ++u)
                 if (tid + u * NT < cnt) crdg[o * T + ps[u]] = x[u];
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < PER; ++u)
         if (tid + u * NT < cnt) valg[ps[u]] = v[u];
     __syncthreads();
-    seg_walk<NT, G, VEC, NB, NMAX, NFIX, EXACT>(a, crdg, valg, npieces,
+    seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(a, crdg, valg, npieces,
                                           PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, rec_base},
                                           rec_row, rec_val, ld, row_base);
 }
 
-template <int NT, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
 __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles) {
     extern __shared__ __align__(16) char lds[];
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    segp_tile<NT, G, VEC, NB, NMAX, NFIX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
+    segp_tile<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
 }
 
 // Batched: tile `it` of the whole batch belongs to the last item whose
@@ -479,7 +485,7 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp_batched(const SegItem *__res
     if (it >= total_tiles) return;
     const int b = seg_item_of(items, count, it);
     const SegItem &item = items[b];
-    segp_tile<NT, G, VEC, NB, NMAX, NFIX, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
+    segp_tile<NT, 4 * NT, G, VEC, NB, NMAX, NFIX, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
                                            item.row_base);
 }
 
@@ -668,34 +674,36 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
     if (threadIdx.x == 0) out[it] = c;
 }
 
-template <int NT, int NMAX, int NFIX, int G, int VEC, int NB>
+template <int NT, int T, int NMAX, int NFIX, int G, int VEC, int NB>
 spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
-    const size_t lds = segp_lds_bytes(4 * NT, a.nmodes);
+    const size_t lds = segp_lds_bytes(T, a.nmodes);
     if (a.rank == G * VEC * NB)
-        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, NFIX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+        hipLaunchKernelGGL((k_mttkrp_segp<NT, T, G, VEC, NB, NMAX, NFIX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s,
+                           a, ntiles);
     else
-        hipLaunchKernelGGL((k_mttkrp_segp<NT, G, VEC, NB, NMAX, NFIX, false>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles);
+        hipLaunchKernelGGL((k_mttkrp_segp<NT, T, G, VEC, NB, NMAX, NFIX, false>), dim3((unsigned)ntiles), dim3(NT), lds,
+                           s, a, ntiles);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
 
-template <int NT, int NMAX, int NFIX>
+template <int NT, int T, int NMAX, int NFIX>
 spt_status launch_seg_nt(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
     const int R = a.rank;
     if ((R & 3) == 0) {
         const int r4 = R >> 2;
-        if (r4 <= 1) return launch_seg_k<NT, NMAX, NFIX, 1, 4, 1>(a, ntiles, s);
-        if (r4 <= 2) return launch_seg_k<NT, NMAX, NFIX, 2, 4, 1>(a, ntiles, s);
-        if (r4 <= 4) return launch_seg_k<NT, NMAX, NFIX, 4, 4, 1>(a, ntiles, s);
-        if (r4 <= 8) return launch_seg_k<NT, NMAX, NFIX, 8, 4, 1>(a, ntiles, s);
-        if (r4 <= 16) return launch_seg_k<NT, NMAX, NFIX, 16, 4, 1>(a, ntiles, s);
-        if (r4 <= 32) return launch_seg_k<NT, NMAX, NFIX, 32, 4, 1>(a, ntiles, s);
-        return launch_seg_k<NT, NMAX, NFIX, 64, 4, 1>(a, ntiles, s);
+        if (r4 <= 1) return launch_seg_k<NT, T, NMAX, NFIX, 1, 4, 1>(a, ntiles, s);
+        if (r4 <= 2) return launch_seg_k<NT, T, NMAX, NFIX, 2, 4, 1>(a, ntiles, s);
+        if (r4 <= 4) return launch_seg_k<NT, T, NMAX, NFIX, 4, 4, 1>(a, ntiles, s);
+        if (r4 <= 8) return launch_seg_k<NT, T, NMAX, NFIX, 8, 4, 1>(a, ntiles, s);
+        if (r4 <= 16) return launch_seg_k<NT, T, NMAX, NFIX, 16, 4, 1>(a, ntiles, s);
+        if (r4 <= 32) return launch_seg_k<NT, T, NMAX, NFIX, 32, 4, 1>(a, ntiles, s);
+        return launch_seg_k<NT, T, NMAX, NFIX, 64, 4, 1>(a, ntiles, s);
     }
-    if (R <= 64) return launch_seg_k<NT, NMAX, NFIX, 64, 1, 1>(a, ntiles, s);
-    if (R <= 128) return launch_seg_k<NT, NMAX, NFIX, 64, 1, 2>(a, ntiles, s);
-    if (R <= 192) return launch_seg_k<NT, NMAX, NFIX, 64, 1, 3>(a, ntiles, s);
-    return launch_seg_k<NT, NMAX, NFIX, 64, 1, 4>(a, ntiles, s);
+    if (R <= 64) return launch_seg_k<NT, T, NMAX, NFIX, 64, 1, 1>(a, ntiles, s);
+    if (R <= 128) return launch_seg_k<NT, T, NMAX, NFIX, 64, 1, 2>(a, ntiles, s);
+    if (R <= 192) return launch_seg_k<NT, T, NMAX, NFIX, 64, 1, 3>(a, ntiles, s);
+    return launch_seg_k<NT, T, NMAX, NFIX, 64, 1, 4>(a, ntiles, s);
 }
 
 template <int NT>
@@ -759,12 +767,12 @@ spt_status launch_count_pieces(const MttkrpArgs &a, int64_t *counts, hipStream_t
 
 namespace {
 // 3 and 4 modes get a kernel with the mode count fixed; others the general one
-template <int NT>
+template <int NT, int T>
 spt_status launch_seg_tile(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
     const int nm = a.nmodes;
-    if (nm == 3) return launch_seg_nt<NT, 3, 3>(a, ntiles, s);
-    if (nm == 4) return launch_seg_nt<NT, 4, 4>(a, ntiles, s);
-    return nm < 3 ? launch_seg_nt<NT, 3, 0>(a, ntiles, s) : launch_seg_nt<NT, 8, 0>(a, ntiles, s);
+    if (nm == 3) return launch_seg_nt<NT, T, 3, 3>(a, ntiles, s);
+    if (nm == 4) return launch_seg_nt<NT, T, 4, 4>(a, ntiles, s);
+    return nm < 3 ? launch_seg_nt<NT, T, 3, 0>(a, ntiles, s) : launch_seg_nt<NT, T, 8, 0>(a, ntiles, s);
 }
 }  // namespace
 
@@ -772,9 +780,9 @@ spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
     if (ntiles == 0) return SPT_OK;
     if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
-    if (a.tile == 1024) return launch_seg_tile<256>(a, ntiles, s);
-    if (a.tile == 2048) return launch_seg_tile<512>(a, ntiles, s);
-    return launch_seg_tile<1024>(a, ntiles, s);
+    if (a.tile == 1024) return launch_seg_tile<256, 1024>(a, ntiles, s);
+    if (a.tile == 2048) return launch_seg_tile<512, 2048>(a, ntiles, s);
+    return launch_seg_tile<kSegpThreads4096, 4096>(a, ntiles, s);
 }
 
 namespace {
