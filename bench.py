@@ -38,7 +38,7 @@ def source_digest() -> str:
     """Digest of the sources of every kernel one MTTKRP call runs (main kernel,
     record sort, record reduction, plan); stored HBM counters are valid only for it."""
     h = hashlib.sha256()
-    for f in ("mttkrp_seg.hip", "mttkrp_table.hip", "encode.hip", "plan.cpp"):
+    for f in ("mttkrp_seg.hip", "mttkrp_table.hip", "encode.hip", "plan.cpp", "tile_common.h"):
         with open(os.path.join(ROOT, "paper_2509_00280_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
