@@ -92,6 +92,12 @@ typedef struct {
                                      or a tile that does not fit LDS for this mode count, act as the
                                      largest that fits); default 4096 */
     int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
+    int row_cache;                /* SEGMENT with 4096-nonzero tiles on tensors of 2..4 modes: 1
+                                     (default) keeps each tile's most used factor rows in LDS, read
+                                     through the tile dictionaries (built once per encoding on first
+                                     use: 2 B per nonzero per mode plus 4 B per distinct (tile, row)
+                                     pair; the build synchronises the stream once); 0 reads every
+                                     factor row from memory */
 } spt_plan;
 
 /* ---------------------------------------------------------------------- */

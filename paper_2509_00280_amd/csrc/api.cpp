@@ -106,6 +106,7 @@ static void default_plan(const Tensor *t, spt_plan *p) {
         p->tile[n] = 4096;
         p->strategy[n] = SPT_STRATEGY_AUTO;
     }
+    p->row_cache = 1;
     (void)t;
 }
 
@@ -115,7 +116,7 @@ static bool plan_ok(const spt_plan *p, int nmodes) {
         if (T != 256 && T != 512 && T != 1024 && T != 2048 && T != 4096) return false;
         if (p->strategy[n] < SPT_STRATEGY_DIRECT || p->strategy[n] > SPT_STRATEGY_SEGMENT) return false;
     }
-    return true;
+    return p->row_cache == 0 || p->row_cache == 1;
 }
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -280,7 +281,7 @@ spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
 
 spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
     if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
-    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256..4096 (power of two) and strategy 0..5");
+    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256..4096 (power of two), strategy 0..5, row_cache 0 or 1");
     (void)hipDeviceSynchronize();  // resolved plans (record offsets) may still be in use
     release_plans(t);
     t->plan = *plan;
@@ -298,10 +299,12 @@ void tensor_release(Tensor *t, hipStream_t s) {
     for (int n = 0; n < kMaxModes; ++n)
         host_sync |= t->mplan[n].rec_off || t->mplan[n].pl_off || t->mplan[n].pl_pos;
     for (int i = 0; i < WS_NSLOTS; ++i) host_sync |= t->ws[i] != nullptr;
+    host_sync |= t->dict_state == 1;
     if (host_sync) {
         (void)hipStreamSynchronize(s);
         for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n);
         release_ws(t);
+        release_dict(t);
     }
     for (int n = 0; n < kMaxModes; ++n) {
         release_batch_plan(t, n, s);

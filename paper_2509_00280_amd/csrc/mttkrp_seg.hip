@@ -211,15 +211,19 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 // exactly NFIX modes (no run-time mode test between the gathers, which would
 // otherwise make the compiler wait for one mode's rows before the next
 // mode's gathers are issued).
-template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces>
+// DICT: a crdg entry with kDictHit set is the LDS slot of a row held in
+// `cache` (non-output mode o, slot s at cache[(o * cap + s) * R]); any other
+// entry is a global row.
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces, bool DICT = false>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__restrict__ crdg,
                                          const float *__restrict__ valg, int npieces, const Pieces &pieces,
                                          uint64_t *__restrict__ rec_row, float *__restrict__ rec_val, int ld,
-                                         int64_t row_base) {
+                                         int64_t row_base, const float *__restrict__ cache = nullptr, int cap = 0) {
     constexpr int UB = kUnroll;
     constexpr int NO = NMAX - 1;  // non-output modes at most
     const int j = threadIdx.x % G;
     static_assert(NFIX == 0 || NFIX == NMAX, "a fixed mode count is the maximum");
+    static_assert(!DICT || NMAX <= 4, "the row cache serves at most 3 non-output modes");
     const int R = a.rank, mode = a.mode, no = NFIX ? NFIX - 1 : a.nmodes - 1;
     // factor of the o-th non-output mode as a row buffer
     spt_i4 fb[NO];
@@ -284,6 +288,30 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 const int c = (b * G + j) * VEC;
+                                if constexpr (DICT) {
+                                    const uint32_t rv = row[o][u];
+                                    if (EXACT || c < R) {
+                                        if (rv & kDictHit) {
+                                            const float *cp = cache + ((size_t)(o * cap) + (rv & ~kDictHit)) * R + c;
+                                            if constexpr (VEC == 4) {
+                                                const float4 t4 = *reinterpret_cast<const float4 *>(cp);
+                                                xv[o][u][b][0] = t4.x;
+                                                xv[o][u][b][1] = t4.y;
+                                                xv[o][u][b][2] = t4.z;
+                                                xv[o][u][b][3] = t4.w;
+                                            } else {
+#pragma unroll
+                                                for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = cp[v];
+                                            }
+                                        } else {
+                                            load_row_vec<VEC>(fb[o], rv, c, xv[o][u][b]);
+                                        }
+                                    } else {
+#pragma unroll
+                                        for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
+                                    }
+                                    continue;
+                                }
                                 if (EXACT || c < R) {
                                     load_row_vec<VEC>(fb[o], row[o][u], c, xv[o][u][b]);
                                 } else {
@@ -459,6 +487,219 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     segp_tile<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
+}
+
+// ---------------------------------------------------------------- row cache
+// Tile dictionary (mode-agnostic, tiles of kDictTile nonzeros in key order):
+// for every mode k, a tile's distinct mode-k rows, most frequent first, and
+// per nonzero the index of its row in that list.  The linearized order keeps
+// a tile inside a small sub-box of the index space, so a tile touches few
+// distinct rows of every mode (a few hundred per 4096 nonzeros on the ratings
+// tensor) and each of them many times.
+
+// Build one mode's dictionary: one workgroup per tile hashes the tile's
+// mode-a.mode rows, buckets them by count (64 buckets, counts >= 63 in the
+// first), and writes row[off[tile] + i] (i-th most frequent row) and
+// slot[e] = i for every nonzero e.  off comes from the counting pass (its
+// distinct rows per tile).
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_emit_dict(MttkrpArgs a, const int64_t *__restrict__ off,
+                                                  uint32_t *__restrict__ row_out, uint16_t *__restrict__ slot_out) {
+    constexpr int T = 4 * NT;
+    constexpr int NBK = 64;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ uint32_t bucket[NBK];
+    uint32_t *hkey = (uint32_t *)lds;
+    uint32_t *hcnt = hkey + T;
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * (int64_t)T;
+    const int64_t rem = a.nnz - base;
+    const int cnt = rem < T ? (int)rem : T;
+    const int64_t d0 = off[tile], d1 = off[tile + 1];
+    for (int i = tid; i < T; i += NT) {
+        hkey[i] = kNoRow;
+        hcnt[i] = 0;
+    }
+    if (tid < NBK) bucket[tid] = 0;
+    const CodecRegs cr = load_codec_regs(a.codec);
+    const int nwords = 2 * a.codec.key_words;
+    uint32_t rowv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT;
+        uint32_t w[4] = {0, 0, 0, 0};
+        if (e < cnt) {
+            const uint64_t klo = a.lo[base + e];
+            const uint64_t khi = nwords == 4 ? a.hi[base + e] : 0ull;
+            w[0] = (uint32_t)klo;
+            w[1] = (uint32_t)(klo >> 32);
+            w[2] = (uint32_t)khi;
+            w[3] = (uint32_t)(khi >> 32);
+        }
+        rowv[u] = decode_mode(cr, a.mode, nwords, w);
+    }
+    __syncthreads();  // hash cleared
+    uint32_t hs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT;
+        hs[u] = 0;
+        if (e < cnt) {
+            const uint32_t r = rowv[u];
+            uint32_t h = mix_hash(r) & (uint32_t)(T - 1);
+            for (;;) {
+                const uint32_t prev = atomicCAS(&hkey[h], kNoRow, r);
+                if (prev == kNoRow || prev == r) break;
+                h = (h + 1) & (uint32_t)(T - 1);
+            }
+            atomicAdd(&hcnt[h], 1u);
+            hs[u] = h;
+        }
+    }
+    __syncthreads();
+    auto bucket_of = [](uint32_t c) { return c >= (uint32_t)(NBK - 1) ? 0u : (uint32_t)(NBK - 1) - c; };
+    for (int i = tid; i < T; i += NT)
+        if (hkey[i] != kNoRow) atomicAdd(&bucket[bucket_of(hcnt[i])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < NBK; ++b) {
+            const uint32_t c = bucket[b];
+            bucket[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < T; i += NT) {
+        if (hkey[i] != kNoRow) {
+            const uint32_t d = atomicAdd(&bucket[bucket_of(hcnt[i])], 1u);
+            if (d0 + d < d1) row_out[d0 + d] = hkey[i];
+            hcnt[i] = d;  // the slot now holds its row's dictionary index
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT;
+        if (e < cnt) slot_out[base + e] = (uint16_t)hcnt[hs[u]];
+    }
+}
+
+// LDS of the row-cached kernel: crdg[nm - 1][T], valg[T], then the cache of
+// cap rows of R floats per non-output mode.
+__host__ __device__ inline size_t segd_lds_bytes(int T, int nmodes, int cap, int R) {
+    return segp_lds_bytes(T, nmodes) + (size_t)(nmodes - 1) * cap * R * 4;
+}
+
+// Row-cached form of segp_tile (tiles of kDictTile nonzeros).  Staging reads
+// no keys: per nonzero the value, its plan position and its dictionary index
+// in every non-output mode.  The first cap rows of each non-output mode's
+// tile dictionary are copied to LDS; a nonzero whose index is below cap
+// reads its factor row there, any other reads it from HBM/L2 by its global
+// row.
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
+__device__ __forceinline__ void segd_tile(const MttkrpArgs &a, int64_t tile, char *lds) {
+    constexpr int PER = T / NT;
+    constexpr int NO = NMAX - 1;
+    static_assert(PER * NT == T && NMAX <= 4, "row cache: 4 modes at most");
+    const int nm = NFIX ? NFIX : a.nmodes, mode = a.mode, tid = threadIdx.x, no = nm - 1;
+    const int R = a.rank, cap = a.d_cap;
+    uint32_t *crdg = (uint32_t *)lds;
+    float *valg = (float *)(crdg + (size_t)no * T);
+    float *cache = valg + T;
+    const int64_t k0 = a.pl_off[tile], k1 = min(a.pl_off[tile + 1], k0 + T);
+    const int64_t base = tile * (int64_t)T;
+    const int64_t rem = a.nnz - base;
+    const int cnt = rem < T ? (int)rem : T;
+    float v[PER];
+    uint32_t q[PER];
+    uint32_t sl[NO][PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * NT;
+        v[u] = 0.f;
+        q[u] = 0;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) sl[o][u] = 0;
+        if (e < cnt) {
+            v[u] = __builtin_nontemporal_load(a.vals + base + e);
+            q[u] = a.pl_pos[base + e] & (T - 1);
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+                if (o < no) sl[o][u] = __builtin_nontemporal_load(a.d_slot[o] + base + e);
+        }
+    }
+    // copy the cached rows: the first min(distinct, cap) of each dictionary
+    int64_t dbase[NO];
+    int dn[NO], dlast[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        dbase[o] = 0;
+        dn[o] = 0;
+        dlast[o] = 0;
+        if (o < no) {
+            dbase[o] = a.d_off[o][tile];
+            const int64_t d = a.d_off[o][tile + 1] - dbase[o];  // distinct rows of the tile
+            dn[o] = (int)min<int64_t>(d, (int64_t)cap);
+            dlast[o] = (int)max<int64_t>(d - 1, 0);
+        }
+    }
+    if ((R & 3) == 0) {
+        const int r4 = R >> 2;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            if (o < no) {
+                const float *f = a.f[o + (o >= mode)];
+                const uint32_t *dr = a.d_row[o] + dbase[o];
+                float *cb = cache + (size_t)o * cap * R;
+                for (int i = tid; i < dn[o] * r4; i += NT) {
+                    const int sidx = i / r4, c = i - sidx * r4;
+                    const float4 x = *reinterpret_cast<const float4 *>(f + (size_t)dr[sidx] * R + 4 * c);
+                    *reinterpret_cast<float4 *>(cb + (size_t)sidx * R + 4 * c) = x;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            if (o < no) {
+                const float *f = a.f[o + (o >= mode)];
+                const uint32_t *dr = a.d_row[o] + dbase[o];
+                float *cb = cache + (size_t)o * cap * R;
+                for (int i = tid; i < dn[o] * R; i += NT) {
+                    const int sidx = i / R, c = i - sidx * R;
+                    cb[(size_t)sidx * R + c] = f[(size_t)dr[sidx] * R + c];
+                }
+            }
+        }
+    }
+    // scatter: cached rows by slot, the others by global row
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (tid + u * NT < cnt) {
+            valg[q[u]] = v[u];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                if (o < no) {
+                    const uint32_t si = min(sl[o][u], (uint32_t)dlast[o]);
+                    crdg[o * T + q[u]] = (int)si < dn[o] ? (si | kDictHit) : a.d_row[o][dbase[o] + si];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT, PlanPieces<T>, true>(
+        a, crdg, valg, (int)(k1 - k0), PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, 0}, a.rec_row,
+        a.rec_val, a.rank, 0, cache, cap);
+}
+
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
+__global__ __launch_bounds__(NT) void k_mttkrp_segd(MttkrpArgs a, int64_t ntiles) {
+    extern __shared__ __align__(16) char lds[];
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    segd_tile<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(a, tile, lds);
 }
 
 // Batched: tile `it` of the whole batch belongs to the last item whose
@@ -676,6 +917,19 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
 
 template <int NT, int T, int NMAX, int NFIX, int G, int VEC, int NB>
 spt_status launch_seg_k(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
+    if constexpr (T == kDictTile && NMAX <= 4) {
+        if (a.d_cap > 0) {
+            const size_t lds = segd_lds_bytes(T, a.nmodes, a.d_cap, a.rank);
+            if (a.rank == G * VEC * NB)
+                hipLaunchKernelGGL((k_mttkrp_segd<NT, T, G, VEC, NB, NMAX, NFIX, true>), dim3((unsigned)ntiles),
+                                   dim3(NT), lds, s, a, ntiles);
+            else
+                hipLaunchKernelGGL((k_mttkrp_segd<NT, T, G, VEC, NB, NMAX, NFIX, false>), dim3((unsigned)ntiles),
+                                   dim3(NT), lds, s, a, ntiles);
+            SPT_HIP(hipGetLastError());
+            return SPT_OK;
+        }
+    }
     const size_t lds = segp_lds_bytes(T, a.nmodes);
     if (a.rank == G * VEC * NB)
         hipLaunchKernelGGL((k_mttkrp_segp<NT, T, G, VEC, NB, NMAX, NFIX, true>), dim3((unsigned)ntiles), dim3(NT), lds, s,
@@ -775,6 +1029,24 @@ spt_status launch_seg_tile(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
     return nm < 3 ? launch_seg_nt<NT, T, 3, 0>(a, ntiles, s) : launch_seg_nt<NT, T, 8, 0>(a, ntiles, s);
 }
 }  // namespace
+
+spt_status launch_emit_dict(const MttkrpArgs &a, const int64_t *off, uint32_t *rows, uint16_t *slots, hipStream_t s) {
+    const int64_t ntiles = (a.nnz + kDictTile - 1) / kDictTile;
+    if (ntiles == 0) return SPT_OK;
+    constexpr int NT = kDictTile / 4;
+    const size_t lds = (size_t)kDictTile * 8;
+    hipLaunchKernelGGL((k_emit_dict<NT, 8>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, off, rows, slots);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+int dict_cap(int nmodes, int rank) {
+    if (nmodes < 2 || nmodes > 4) return 0;
+    const size_t fixed = segp_lds_bytes(kDictTile, nmodes);
+    if (fixed >= kDictLdsBudget) return 0;
+    const size_t cap = (kDictLdsBudget - fixed) / ((size_t)(nmodes - 1) * rank * 4);
+    return cap >= (size_t)kDictMinCap ? (int)std::min<size_t>(cap, kDictTile) : 0;
+}
 
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;

@@ -125,11 +125,69 @@ void release_batch_plan(Tensor *t, int n, hipStream_t s) {
     p = ModePlan{};
 }
 
+void release_dict(Tensor *t) {
+    for (int k = 0; k < kMaxModes; ++k) {
+        for (void *q : {(void *)t->dict_slot[k], (void *)t->dict_row[k], (void *)t->dict_off[k]})
+            if (q) (void)hipFree(q);
+        t->dict_slot[k] = nullptr;
+        t->dict_row[k] = nullptr;
+        t->dict_off[k] = nullptr;
+    }
+    t->dict_state = 0;
+}
+
 void release_plans(Tensor *t) {
     for (int n = 0; n < kMaxModes; ++n) {
         release_mode_plan(t, n);
         release_batch_plan(t, n, nullptr);  // callers order this after the tensor's last use
     }
+    release_dict(t);
+}
+
+// Tile dictionaries of every mode (once per encoding; synchronises s).  They
+// are an optimisation: when one cannot be built (too many modes, a mode of
+// 2^31 rows or more, no memory) the tensor is marked and the uncached kernel
+// runs.
+static spt_status build_dict(Tensor *t, hipStream_t s) {
+    if (t->dict_state != 0) return SPT_OK;
+    t->dict_state = -1;
+    if (t->nmodes < 2 || t->nmodes > 4 || t->nnz == 0 || !seg_tile_ok(kDictTile, t->nmodes)) return SPT_OK;
+    for (int k = 0; k < t->nmodes; ++k)
+        if (t->dims[k] >= (int64_t)kDictHit) return SPT_OK;
+    const int64_t ntiles = (t->nnz + kDictTile - 1) / kDictTile;
+    std::vector<int64_t> h(ntiles + 1, 0);
+    bool ok = true;
+    for (int k = 0; k < t->nmodes && ok; ++k) {
+        ok = hipMalloc(&t->dict_off[k], sizeof(int64_t) * (ntiles + 1)) == hipSuccess &&
+             hipMalloc(&t->dict_slot[k], sizeof(uint16_t) * t->nnz) == hipSuccess;
+        const MttkrpArgs a = make_args(t, nullptr, 1, k, nullptr, kDictTile);
+        ok = ok && launch_count_pieces(a, t->dict_off[k], s) == SPT_OK &&
+             hipMemcpyAsync(h.data(), t->dict_off[k], sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s) ==
+                 hipSuccess &&
+             hipStreamSynchronize(s) == hipSuccess;
+        if (!ok) break;
+        int64_t run = 0;
+        for (int64_t i = 0; i < ntiles; ++i) {
+            const int64_t c = h[i] >> 32;  // distinct mode-k rows of the tile
+            h[i] = run;
+            run += c;
+        }
+        h[ntiles] = run;
+        ok = hipMemcpy(t->dict_off[k], h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice) ==
+                 hipSuccess &&
+             hipMalloc(&t->dict_row[k], sizeof(uint32_t) * std::max<int64_t>(run, 1)) == hipSuccess &&
+             launch_emit_dict(a, t->dict_off[k], t->dict_row[k], t->dict_slot[k], s) == SPT_OK;
+    }
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        release_dict(t);
+        t->dict_state = -1;
+        return SPT_OK;
+    }
+    t->dict_state = 1;
+    return SPT_OK;
 }
 
 // SEGMENT tile: the plan's tile if it is one the kernel serves and it fits
@@ -418,6 +476,22 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
         a.pl_row = p->pl_row;
         a.pl_dest = p->pl_dest;
         a.rec_cap = p->records;
+        // row cache: 4096-nonzero tiles, when the cache holds enough rows
+        const int cap = p->ts == kDictTile ? dict_cap(t->nmodes, rank) : 0;
+        if (cap > 0 && t->plan.row_cache != 0) {
+            st = build_dict(t, s);
+            if (st != SPT_OK) return st;
+            if (t->dict_state == 1) {
+                for (int o = 0, k = 0; k < t->nmodes; ++k) {
+                    if (k == mode) continue;
+                    a.d_slot[o] = t->dict_slot[k];
+                    a.d_row[o] = t->dict_row[k];
+                    a.d_off[o] = t->dict_off[k];
+                    ++o;
+                }
+                a.d_cap = cap;
+            }
+        }
         return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/true);
     }
     if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {

@@ -14,6 +14,13 @@ namespace spt {
 constexpr int kMaxModes = SPT_MAX_MODES;
 constexpr int kMaxRuns = 160;          // l(p) <= 128 bits plus splits at 32-bit word boundaries
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+constexpr uint32_t kDictHit = 0x80000000u;  // row-cache entry flag (global rows stay below it)
+constexpr int kDictTile = 4096;             // tile of the dictionaries and the row-cached kernel
+#ifndef SPT_DICT_LDS_KB
+#define SPT_DICT_LDS_KB 80
+#endif
+constexpr size_t kDictLdsBudget = (size_t)SPT_DICT_LDS_KB * 1024;  // LDS of one row-cached workgroup
+constexpr int kDictMinCap = 16;
 
 // A maximal group of consecutive coordinate bits that land on consecutive key
 // bits inside one 32-bit word of the key: coordinate bits [cpos, cpos+len) of
@@ -94,6 +101,12 @@ struct Tensor {
     ModePlan bplan[kMaxModes];
     void *ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
+    // tile dictionaries (built on first use by a row-cached MTTKRP): per mode
+    // slot[nnz] u16, row[distinct (tile, row) pairs] u32, off[ntiles + 1]
+    uint16_t *dict_slot[kMaxModes] = {};
+    uint32_t *dict_row[kMaxModes] = {};
+    int64_t *dict_off[kMaxModes] = {};
+    int dict_state = 0;  // 0 not built, 1 built, -1 not applicable
 };
 
 // plan.cpp
@@ -102,6 +115,8 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
 void release_plans(Tensor *t);
+// drop the tile dictionaries (after the tensor's last use)
+void release_dict(Tensor *t);
 // release a handle after its last use on stream s (stream-ordered frees)
 void tensor_release(Tensor *t, hipStream_t s);
 // drop the cached plan of one mode (the next call at that mode plans again)
@@ -155,6 +170,13 @@ struct MttkrpArgs {
     const int64_t *pl_off;
     const uint32_t *pl_desc, *pl_row, *pl_dest;
     int64_t rec_cap;          // records the plan laid out (writes beyond are dropped)
+    // row cache (SEGMENT, tiles of kDictTile): the tile dictionaries of the
+    // non-output modes in order (o-th non-output mode), and the cached rows
+    // per mode (0: no cache)
+    const uint16_t *d_slot[kMaxModes - 1];
+    const uint32_t *d_row[kMaxModes - 1];
+    const int64_t *d_off[kMaxModes - 1];
+    int d_cap;
     Codec codec;
 };
 spt_status launch_fill_zero(float *p, int64_t n, hipStream_t s);
@@ -175,6 +197,12 @@ spt_status launch_emit_plan(const MttkrpArgs &a, const PlanOut &o, hipStream_t s
 spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first, uint32_t *dest,
                              int64_t n, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
+// Tile dictionary of mode a.mode (tiles of kDictTile): off from the counting
+// pass (distinct rows per tile, exclusive prefix), rows and slots written.
+spt_status launch_emit_dict(const MttkrpArgs &a, const int64_t *off, uint32_t *rows, uint16_t *slots, hipStream_t s);
+// Rows of each non-output factor the row-cached kernel keeps in LDS (0: the
+// cache does not fit).
+int dict_cap(int nmodes, int rank);
 
 // Batched SEGMENT MTTKRP: every tensor's tiles of kBatchTile nonzeros in one
 // launch, each with the tensor's batched plan (a.pl_*); records carry rows of

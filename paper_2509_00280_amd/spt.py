@@ -39,7 +39,7 @@ class TensorInfo(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int * MAX_MODES), ("strategy", ctypes.c_int * MAX_MODES)]
+    _fields_ = [("tile", ctypes.c_int * MAX_MODES), ("strategy", ctypes.c_int * MAX_MODES), ("row_cache", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -166,9 +166,9 @@ class Tensor:
     def get_plan(self) -> dict:
         p = Plan()
         _check(lib().spt_tensor_get_plan(self._h, ctypes.byref(p)))
-        return {"tile": list(p.tile), "strategy": list(p.strategy)}
+        return {"tile": list(p.tile), "strategy": list(p.strategy), "row_cache": int(p.row_cache)}
 
-    def set_plan(self, tile=None, strategy=None):
+    def set_plan(self, tile=None, strategy=None, row_cache=None):
         p = Plan()
         _check(lib().spt_tensor_get_plan(self._h, ctypes.byref(p)))
         for n in range(MAX_MODES):
@@ -178,6 +178,8 @@ class Tensor:
             if strategy is not None:
                 p.strategy[n] = strategy[n] if isinstance(strategy, (list, tuple)) and n < len(strategy) else (
                     strategy if isinstance(strategy, int) else p.strategy[n])
+        if row_cache is not None:
+            p.row_cache = 1 if row_cache else 0
         _check(lib().spt_tensor_set_plan(self._h, ctypes.byref(p)))
 
     def free(self):
