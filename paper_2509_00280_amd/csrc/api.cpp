@@ -299,7 +299,7 @@ void tensor_release(Tensor *t, hipStream_t s) {
     for (int n = 0; n < kMaxModes; ++n)
         host_sync |= t->mplan[n].rec_off || t->mplan[n].pl_off || t->mplan[n].pl_pos;
     for (int i = 0; i < WS_NSLOTS; ++i) host_sync |= t->ws[i] != nullptr;
-    host_sync |= t->dict_state == 1;
+    for (int k = 0; k < kMaxModes; ++k) host_sync |= t->dict_slot[k] != nullptr;
     if (host_sync) {
         (void)hipStreamSynchronize(s);
         for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n);

@@ -144,49 +144,56 @@ void release_plans(Tensor *t) {
     release_dict(t);
 }
 
-// Tile dictionaries of every mode (once per encoding; synchronises s).  They
-// are an optimisation: when one cannot be built (too many modes, a mode of
-// 2^31 rows or more, no memory) the tensor is marked and the uncached kernel
-// runs.
-static spt_status build_dict(Tensor *t, hipStream_t s) {
-    if (t->dict_state != 0) return SPT_OK;
-    t->dict_state = -1;
-    if (t->nmodes < 2 || t->nmodes > 4 || t->nnz == 0 || !seg_tile_ok(kDictTile, t->nmodes)) return SPT_OK;
+// Tile dictionaries (per mode, once per encoding).  They are an
+// optimisation: a tensor that cannot have them (more than 4 modes, a mode of
+// 2^31 rows or more) or whose build fails (no memory) is marked, and the
+// uncached kernel runs.
+static bool dict_eligible(const Tensor *t) {
+    if (t->dict_state < 0 || t->nmodes < 2 || t->nmodes > 4 || t->nnz == 0 || !seg_tile_ok(kDictTile, t->nmodes))
+        return false;
     for (int k = 0; k < t->nmodes; ++k)
-        if (t->dims[k] >= (int64_t)kDictHit) return SPT_OK;
+        if (t->dims[k] >= (int64_t)kDictHit) return false;
+    return true;
+}
+
+// Mode k's dictionary.  pairs: per tile of kDictTile nonzeros, the exclusive
+// prefix of its distinct mode-k rows (ntiles + 1 entries) when a counting
+// pass already produced it (the mode-k SEGMENT plan's), else null (the pass
+// runs here and synchronises s).  Asynchronous otherwise.
+static spt_status build_dict_mode(Tensor *t, int k, hipStream_t s, const int64_t *pairs) {
+    if (t->dict_slot[k] || !dict_eligible(t)) return SPT_OK;
     const int64_t ntiles = (t->nnz + kDictTile - 1) / kDictTile;
-    std::vector<int64_t> h(ntiles + 1, 0);
-    bool ok = true;
-    for (int k = 0; k < t->nmodes && ok; ++k) {
-        ok = hipMalloc(&t->dict_off[k], sizeof(int64_t) * (ntiles + 1)) == hipSuccess &&
-             hipMalloc(&t->dict_slot[k], sizeof(uint16_t) * t->nnz) == hipSuccess;
-        const MttkrpArgs a = make_args(t, nullptr, 1, k, nullptr, kDictTile);
-        ok = ok && launch_count_pieces(a, t->dict_off[k], s) == SPT_OK &&
+    std::vector<int64_t> h;
+    const MttkrpArgs a = make_args(t, nullptr, 1, k, nullptr, kDictTile);
+    bool ok = hipMalloc(&t->dict_off[k], sizeof(int64_t) * (ntiles + 1)) == hipSuccess;
+    if (ok && !pairs) {
+        h.assign(ntiles + 1, 0);
+        ok = launch_count_pieces(a, t->dict_off[k], s) == SPT_OK &&
              hipMemcpyAsync(h.data(), t->dict_off[k], sizeof(int64_t) * ntiles, hipMemcpyDeviceToHost, s) ==
                  hipSuccess &&
              hipStreamSynchronize(s) == hipSuccess;
-        if (!ok) break;
         int64_t run = 0;
-        for (int64_t i = 0; i < ntiles; ++i) {
+        for (int64_t i = 0; ok && i < ntiles; ++i) {
             const int64_t c = h[i] >> 32;  // distinct mode-k rows of the tile
             h[i] = run;
             run += c;
         }
-        h[ntiles] = run;
-        ok = hipMemcpy(t->dict_off[k], h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice) ==
-                 hipSuccess &&
-             hipMalloc(&t->dict_row[k], sizeof(uint32_t) * std::max<int64_t>(run, 1)) == hipSuccess &&
-             launch_emit_dict(a, t->dict_off[k], t->dict_row[k], t->dict_slot[k], s) == SPT_OK;
+        if (ok) h[ntiles] = run;
+        pairs = h.data();
     }
-    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    ok = ok &&
+         hipMemcpyAsync(t->dict_off[k], pairs, sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s) ==
+             hipSuccess &&
+         hipMalloc(&t->dict_slot[k], sizeof(uint16_t) * t->nnz) == hipSuccess &&
+         hipMalloc(&t->dict_row[k], sizeof(uint32_t) * std::max<int64_t>(pairs[ntiles], 1)) == hipSuccess &&
+         launch_emit_dict(a, t->dict_off[k], t->dict_row[k], t->dict_slot[k], s) == SPT_OK;
+    // the host prefix must outlive the copy
+    ok = hipStreamSynchronize(s) == hipSuccess && ok;
     if (!ok) {
-        (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
         release_dict(t);
         t->dict_state = -1;
-        return SPT_OK;
     }
-    t->dict_state = 1;
     return SPT_OK;
 }
 
@@ -273,6 +280,9 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     for (void *q : {(void *)pair_off, (void *)ppair, (void *)psub, (void *)keys, (void *)keys2, (void *)np, (void *)ia,
                     (void *)ib, (void *)cnt})
         dev_free(q, s);
+    // the counting pass gave this mode's distinct rows per tile: its tile
+    // dictionary costs one more pass
+    if (st == SPT_OK && p.ts == kDictTile) st = build_dict_mode(t, mode, s, hq.data());
     return st;
 }
 
@@ -464,6 +474,7 @@ spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int
 }
 
 spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
+    const bool had_plan = t->mplan[mode].valid && t->mplan[mode].rank == rank;
     ModePlan *p = nullptr;
     spt_status st = resolve_plan(t, mode, rank, s, &p);
     if (st != SPT_OK) return st;
@@ -477,11 +488,21 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
         a.pl_dest = p->pl_dest;
         a.rec_cap = p->records;
         // row cache: 4096-nonzero tiles, when the cache holds enough rows
+        // Every non-output mode needs its dictionary.  A mode gets one with its
+        // own plan; missing ones are built here from the second call at this
+        // mode on (a CP-ALS sweep has them all by its last mode).
         const int cap = p->ts == kDictTile ? dict_cap(t->nmodes, rank) : 0;
         if (cap > 0 && t->plan.row_cache != 0) {
-            st = build_dict(t, s);
-            if (st != SPT_OK) return st;
-            if (t->dict_state == 1) {
+            bool all = true;
+            for (int k = 0; k < t->nmodes; ++k) {
+                if (k == mode) continue;
+                if (!t->dict_slot[k] && had_plan) {
+                    st = build_dict_mode(t, k, s, nullptr);
+                    if (st != SPT_OK) return st;
+                }
+                all = all && t->dict_slot[k] != nullptr;
+            }
+            if (all) {
                 for (int o = 0, k = 0; k < t->nmodes; ++k) {
                     if (k == mode) continue;
                     a.d_slot[o] = t->dict_slot[k];

@@ -101,12 +101,13 @@ struct Tensor {
     ModePlan bplan[kMaxModes];
     void *ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
-    // tile dictionaries (built on first use by a row-cached MTTKRP): per mode
-    // slot[nnz] u16, row[distinct (tile, row) pairs] u32, off[ntiles + 1]
+    // tile dictionaries (tiles of kDictTile, built with a mode's SEGMENT plan or
+    // on a row-cached MTTKRP's second call): per mode slot[nnz] u16,
+    // row[distinct (tile, row) pairs] u32, off[ntiles + 1]
     uint16_t *dict_slot[kMaxModes] = {};
     uint32_t *dict_row[kMaxModes] = {};
     int64_t *dict_off[kMaxModes] = {};
-    int dict_state = 0;  // 0 not built, 1 built, -1 not applicable
+    int dict_state = 0;  // -1: not applicable, or a build failed
 };
 
 // plan.cpp
