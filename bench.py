@@ -424,7 +424,7 @@ def main():
             traffic = float(pmc["hbm_bytes_per_launch"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "one mode-n MTTKRP call (k_mttkrp_segp, k_fill_zero, k_reduce_records)",
+                "kernel": "one mode-n MTTKRP call (k_mttkrp_segd, k_fill_zero, k_reduce_records)",
                 "algorithmic_bytes_per_launch": int(alg_avg),
                 "avg_launch_ms": round(mk_ms, 4)}
     shape = "x".join(map(str, t.dims))
