@@ -217,14 +217,15 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restr
 }
 
 // ------------------------------------------------------------------ solve preparation
-// One workgroup; R <= 64.  LDS: two R x R FP64 matrices.
+// One workgroup; R <= 64.  LDS: two R x R FP64 matrices.  W = V^-1 by
+// Gauss-Jordan elimination with all threads updating the matrix per pivot
+// (64 barrier pairs at R = 64) rather than a column-serial Cholesky and
+// triangular inverse.
 __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                 const double *__restrict__ gram_m, double *__restrict__ S,
                                                 double *__restrict__ lambda, int *__restrict__ status) {
     __shared__ double A[64 * 64];
     __shared__ double B[64 * 64];
-    __shared__ double sdiag;
-    __shared__ int sfail;
     const int tid = threadIdx.x;
     const int RR = R * R;
     // V = Hadamard product of the Grams of every mode except `mode` -> A
@@ -238,66 +239,87 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
     double trace = 0.0;
     for (int i = 0; i < R; ++i) trace += A[i * R + i];
     const double ridge0 = 1e-12 * trace / R;
+    constexpr int PT = 64 * 64 / kThreads;  // elements per thread (R <= 64)
+    int ei[PT], ek[PT];                     // row and column of each (e < RR)
+#pragma unroll
+    for (int m = 0; m < PT; ++m) {
+        const int e = tid + m * kThreads;
+        ei[m] = e / R;
+        ek[m] = e - ei[m] * R;
+    }
     int attempt = 0;
     for (; attempt < 4; ++attempt) {
         const double ridge = attempt == 0 ? 0.0 : ridge0 * pow(1e3, (double)(attempt - 1));
         for (int e = tid; e < RR; e += kThreads) {
             const int i = e / R, j = e % R;
-            B[e] = (i >= j) ? A[e] + (i == j ? ridge : 0.0) : 0.0;
+            B[e] = A[e] + (i == j ? ridge : 0.0);
         }
-        if (tid == 0) sfail = 0;
         __syncthreads();
-        // left-looking Cholesky in B (lower triangle), column by column
+        // Gauss-Jordan inversion in place, pivots on the diagonal: for a
+        // symmetric V every pivot is positive exactly when V is positive
+        // definite (they are the pivots of its Cholesky factorisation,
+        // squared), so a non-positive pivot is the same failure as a failed
+        // Cholesky and takes the next ridge.  All threads read the same pivot.
+        bool ok = true;
         for (int j = 0; j < R; ++j) {
-            double s = 0.0;
-            const int i = j + tid;
-            if (i < R) {
-                s = B[i * R + j];
-                for (int k = 0; k < j; ++k) s -= B[i * R + k] * B[j * R + k];
+            const double piv = B[j * R + j];
+            if (!(piv > 0.0) || !isfinite(piv)) {
+                ok = false;
+                break;
             }
-            if (tid == 0) {
-                if (!(s > 0.0) || !isfinite(s)) sfail = 1;
-                sdiag = sqrt(s > 0.0 ? s : 1.0);
+            const double ip = 1.0 / piv;
+            double nv[PT];
+#pragma unroll
+            for (int m = 0; m < PT; ++m) {
+                const int e = tid + m * kThreads;
+                nv[m] = 0.0;
+                if (e < RR) {
+                    const int i = ei[m], k = ek[m];
+                    if (i == j) {
+                        nv[m] = k == j ? ip : B[j * R + k] * ip;
+                    } else {
+                        const double f = B[i * R + j];
+                        nv[m] = k == j ? -f * ip : B[i * R + k] - f * ip * B[j * R + k];
+                    }
+                }
             }
             __syncthreads();
-            if (i < R) B[i * R + j] = (tid == 0) ? sdiag : s / sdiag;
+#pragma unroll
+            for (int m = 0; m < PT; ++m) {
+                const int e = tid + m * kThreads;
+                if (e < RR) B[e] = nv[m];
+            }
             __syncthreads();
         }
-        if (!sfail) break;
+        if (ok) break;
         __syncthreads();
     }
     if (attempt == 4) {
         if (tid == 0) *status = -1;
         return;
     }
-    // Linv (lower) into A: thread c solves L x = e_c by forward substitution
-    for (int c = tid; c < R; c += kThreads) {
-        for (int i = 0; i < R; ++i) {
-            if (i < c) {
-                A[i * R + c] = 0.0;
-                continue;
+    // B = W = V^-1.  Tm = gram_m W into A (gram_m staged in A first)
+    for (int e = tid; e < RR; e += kThreads) A[e] = gram_m[e];
+    __syncthreads();
+    {
+        double tv[PT];
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kThreads;
+            tv[m] = 0.0;
+            if (e < RR) {
+                const int a = ei[m], r = ek[m];
+                double acc = 0.0;
+                for (int b = 0; b < R; ++b) acc += A[a * R + b] * B[b * R + r];
+                tv[m] = acc;
             }
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) s -= B[i * R + k] * A[k * R + c];
-            A[i * R + c] = s / B[i * R + i];
         }
-    }
-    __syncthreads();
-    // W = Linv^T Linv into B
-    for (int e = tid; e < RR; e += kThreads) {
-        const int p = e / R, q = e % R;
-        const int i0 = p > q ? p : q;
-        double s = 0.0;
-        for (int i = i0; i < R; ++i) s += A[i * R + p] * A[i * R + q];
-        B[e] = s;
-    }
-    __syncthreads();
-    // Tm = gram_m W into A
-    for (int e = tid; e < RR; e += kThreads) {
-        const int a = e / R, r = e % R;
-        double s = 0.0;
-        for (int b = 0; b < R; ++b) s += gram_m[a * R + b] * B[b * R + r];
-        A[e] = s;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kThreads;
+            if (e < RR) A[e] = tv[m];
+        }
     }
     __syncthreads();
     // lambda_r^2 = sum_a W[r][a] Tm[a][r]
