@@ -217,10 +217,11 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restr
 }
 
 // ------------------------------------------------------------------ solve preparation
-// One workgroup; R <= 64.  LDS: two R x R FP64 matrices.  W = V^-1 by
-// Gauss-Jordan elimination with all threads updating the matrix per pivot
-// (64 barrier pairs at R = 64) rather than a column-serial Cholesky and
-// triangular inverse.
+// One workgroup; R <= 64.  LDS: two R x R FP64 matrices.  W = V^-1 from the
+// Cholesky factor: a right-looking factorisation and a right-looking forward
+// substitution, in both of which all threads update the matrix per column
+// (R barrier pairs each), then W = L^-T L^-1.
+constexpr int kSolveThreads = 1024;  // 16 waves: 4 matrix elements per thread at R = 64
 __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                 const double *__restrict__ gram_m, double *__restrict__ S,
                                                 double *__restrict__ lambda, int *__restrict__ status) {
@@ -229,7 +230,7 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
     const int tid = threadIdx.x;
     const int RR = R * R;
     // V = Hadamard product of the Grams of every mode except `mode` -> A
-    for (int e = tid; e < RR; e += kThreads) {
+    for (int e = tid; e < RR; e += kSolveThreads) {
         double v = 1.0;
         for (int k = 0; k < nmodes; ++k)
             if (k != mode) v *= grams[(size_t)k * RR + e];
@@ -239,54 +240,50 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
     double trace = 0.0;
     for (int i = 0; i < R; ++i) trace += A[i * R + i];
     const double ridge0 = 1e-12 * trace / R;
-    constexpr int PT = 64 * 64 / kThreads;  // elements per thread (R <= 64)
+    constexpr int PT = 64 * 64 / kSolveThreads;  // elements per thread (R <= 64)
     int ei[PT], ek[PT];                     // row and column of each (e < RR)
 #pragma unroll
     for (int m = 0; m < PT; ++m) {
-        const int e = tid + m * kThreads;
+        const int e = tid + m * kSolveThreads;
         ei[m] = e / R;
         ek[m] = e - ei[m] * R;
     }
     int attempt = 0;
     for (; attempt < 4; ++attempt) {
         const double ridge = attempt == 0 ? 0.0 : ridge0 * pow(1e3, (double)(attempt - 1));
-        for (int e = tid; e < RR; e += kThreads) {
+        for (int e = tid; e < RR; e += kSolveThreads) {
             const int i = e / R, j = e % R;
             B[e] = A[e] + (i == j ? ridge : 0.0);
         }
         __syncthreads();
-        // Gauss-Jordan inversion in place, pivots on the diagonal: for a
-        // symmetric V every pivot is positive exactly when V is positive
-        // definite (they are the pivots of its Cholesky factorisation,
-        // squared), so a non-positive pivot is the same failure as a failed
-        // Cholesky and takes the next ridge.  All threads read the same pivot.
+        // Right-looking Cholesky V = L L^T in place (lower triangle of B): per
+        // column every thread updates its elements of the trailing matrix
+        // from the values before the step.  All threads read the same pivot.
         bool ok = true;
         for (int j = 0; j < R; ++j) {
-            const double piv = B[j * R + j];
-            if (!(piv > 0.0) || !isfinite(piv)) {
+            const double d = B[j * R + j];
+            if (!(d > 0.0) || !isfinite(d)) {
                 ok = false;
                 break;
             }
-            const double ip = 1.0 / piv;
+            const double l = sqrt(d), il = 1.0 / l, id = 1.0 / d;
             double nv[PT];
 #pragma unroll
             for (int m = 0; m < PT; ++m) {
-                const int e = tid + m * kThreads;
+                const int e = tid + m * kSolveThreads;
                 nv[m] = 0.0;
                 if (e < RR) {
                     const int i = ei[m], k = ek[m];
-                    if (i == j) {
-                        nv[m] = k == j ? ip : B[j * R + k] * ip;
-                    } else {
-                        const double f = B[i * R + j];
-                        nv[m] = k == j ? -f * ip : B[i * R + k] - f * ip * B[j * R + k];
-                    }
+                    const double x = B[e];
+                    if (k == j) nv[m] = i == j ? l : (i > j ? x * il : x);
+                    else if (i > j && k > j && k <= i) nv[m] = x - B[i * R + j] * B[k * R + j] * id;
+                    else nv[m] = x;
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < PT; ++m) {
-                const int e = tid + m * kThreads;
+                const int e = tid + m * kSolveThreads;
                 if (e < RR) B[e] = nv[m];
             }
             __syncthreads();
@@ -298,14 +295,62 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         if (tid == 0) *status = -1;
         return;
     }
+    // X = L^-1 into A by right-looking forward substitution on the identity
+    for (int e = tid; e < RR; e += kSolveThreads) A[e] = (e / R == e % R) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int i = 0; i < R; ++i) {
+        const double ii = 1.0 / B[i * R + i];
+        double nv[PT];
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kSolveThreads;
+            nv[m] = 0.0;
+            if (e < RR) {
+                const int k = ei[m], c = ek[m];
+                const double x = A[e];
+                if (k == i) nv[m] = x * ii;
+                else if (k > i && c <= i) nv[m] = x - B[k * R + i] * A[i * R + c] * ii;
+                else nv[m] = x;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kSolveThreads;
+            if (e < RR) A[e] = nv[m];
+        }
+        __syncthreads();
+    }
+    // W = X^T X = V^-1 into B
+    {
+        double wv[PT];
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kSolveThreads;
+            wv[m] = 0.0;
+            if (e < RR) {
+                const int p = ei[m], q = ek[m];
+                double acc = 0.0;
+                for (int i = p > q ? p : q; i < R; ++i) acc += A[i * R + p] * A[i * R + q];
+                wv[m] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kSolveThreads;
+            if (e < RR) B[e] = wv[m];
+        }
+    }
+    __syncthreads();
     // B = W = V^-1.  Tm = gram_m W into A (gram_m staged in A first)
-    for (int e = tid; e < RR; e += kThreads) A[e] = gram_m[e];
+    for (int e = tid; e < RR; e += kSolveThreads) A[e] = gram_m[e];
     __syncthreads();
     {
         double tv[PT];
 #pragma unroll
         for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kThreads;
+            const int e = tid + m * kSolveThreads;
             tv[m] = 0.0;
             if (e < RR) {
                 const int a = ei[m], r = ek[m];
@@ -317,14 +362,14 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kThreads;
+            const int e = tid + m * kSolveThreads;
             if (e < RR) A[e] = tv[m];
         }
     }
     __syncthreads();
     // lambda_r^2 = sum_a W[r][a] Tm[a][r]
     __shared__ double lam_s[64];
-    for (int r = tid; r < R; r += kThreads) {
+    for (int r = tid; r < R; r += kSolveThreads) {
         double s = 0.0;
         for (int a = 0; a < R; ++a) s += B[r * R + a] * A[a * R + r];
         const double l = s > 0.0 ? sqrt(s) : 0.0;
@@ -332,17 +377,17 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         lambda[r] = lam_s[r];
     }
     __syncthreads();
-    for (int e = tid; e < RR; e += kThreads) S[e] = B[e] / lam_s[e % R];
+    for (int e = tid; e < RR; e += kSolveThreads) S[e] = B[e] / lam_s[e % R];
     if (tid == 0) *status = attempt;
 }
 
-__global__ __launch_bounds__(kThreads) void k_solve_prep(const double *__restrict__ grams, int nmodes, int mode, int R,
+__global__ __launch_bounds__(kSolveThreads) void k_solve_prep(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                          const double *__restrict__ gram_m, double *__restrict__ S,
                                                          double *__restrict__ lambda, int *__restrict__ status) {
     solve_prep_body(grams, nmodes, mode, R, gram_m, S, lambda, status);
 }
 
-__global__ __launch_bounds__(kThreads) void k_solve_prep_batched(const SolveItem *__restrict__ items, int mode) {
+__global__ __launch_bounds__(kSolveThreads) void k_solve_prep_batched(const SolveItem *__restrict__ items, int mode) {
     const SolveItem &it = items[blockIdx.x];
     solve_prep_body(it.grams, it.nmodes, mode, it.rank, it.gram_m, it.S, it.lambda, it.status + mode);
 }
@@ -550,7 +595,7 @@ spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double
 spt_status launch_solve_prep(const double *grams, int nmodes, int mode, int rank, const double *gram_m, double *S,
                              double *lambda, int *status_out, hipStream_t s) {
     if (rank > 64) return fail(SPT_E_INVALID_ARG, "solve: rank above 64");
-    hipLaunchKernelGGL(k_solve_prep, dim3(1), dim3(kThreads), 0, s, grams, nmodes, mode, rank, gram_m, S, lambda,
+    hipLaunchKernelGGL(k_solve_prep, dim3(1), dim3(kSolveThreads), 0, s, grams, nmodes, mode, rank, gram_m, S, lambda,
                        status_out);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
@@ -624,7 +669,7 @@ spt_status launch_gram_batched(const GramItem *items, int count, int64_t total_s
 
 spt_status launch_solve_prep_batched(const SolveItem *items, int count, int mode, hipStream_t s) {
     if (count == 0) return SPT_OK;
-    hipLaunchKernelGGL(k_solve_prep_batched, dim3(count), dim3(kThreads), 0, s, items, mode);
+    hipLaunchKernelGGL(k_solve_prep_batched, dim3(count), dim3(kSolveThreads), 0, s, items, mode);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
