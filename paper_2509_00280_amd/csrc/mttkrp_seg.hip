@@ -18,10 +18,16 @@
 // Call (the planned kernel): coalesced non-temporal loads of keys, values and
 // plan positions; the non-output coordinates are decoded from the bit runs
 // held in VGPRs and scattered once to LDS in row-grouped order; lane groups
-// (G lanes x VEC columns) take pieces round-robin (at most L nonzeros each,
-// so the static deal is balanced), gather the N-1 factor rows of the piece's
-// nonzeros with vector loads, form v * Hadamard, sum and store the record at
-// its plan-given slot.  No hashing, atomics or scans at run time.
+// (G lanes x VEC columns) take the tile's pieces (stored longest first) in
+// snake order, gather the N-1 factor rows of the piece's nonzeros with
+// buffer loads, form v * Hadamard, sum and store the record at its
+// plan-given slot.  No hashing, atomics or scans at run time.
+//
+// Row-cached call (4096-nonzero tiles, 2..4 modes): the tile dictionaries
+// (per mode, each tile's distinct rows most frequent first, and each
+// nonzero's index in that list) replace the key decode; the first cap rows
+// of every non-output mode's list are copied to LDS and a nonzero reads its
+// factor row there when its index is below cap.
 #include "tile_common.h"
 
 #ifndef SPT_SEG_UB
