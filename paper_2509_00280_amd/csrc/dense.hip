@@ -19,45 +19,49 @@ namespace spt {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kGramRowsPerWave = 256;
-constexpr int kGramMaxWaves = 4096;
+constexpr int kGramSliceRows1 = 512;   // rows of a Gram slice (one workgroup, 8 waves)
+constexpr int kGramSThreads = 512;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 int gram_nb(int R) { return (R + 15) / 16; }
-// workgroups of the Gram kernel (4 waves, one row slice each)
+// row slices (workgroups, one partial each) of the Gram kernel
 int gram_chunks(int64_t rows, int R) {
     const int ld = gram_nb(R) * 16;
-    int64_t waves = (rows + kGramRowsPerWave - 1) / kGramRowsPerWave;
+    int64_t slices = (rows + kGramSliceRows1 - 1) / kGramSliceRows1;
     const int64_t cap = std::max<int64_t>(4, (int64_t)(32u << 20) / ((int64_t)ld * ld * 8));  // ~32 MB of partials
-    waves = std::min<int64_t>(std::min<int64_t>(waves, kGramMaxWaves), cap);
-    return (int)std::max<int64_t>(1, (waves + 3) / 4);
+    slices = std::min<int64_t>(slices, cap);
+    return (int)std::max<int64_t>(1, slices);
 }
 
-// Partial Grams of row slices, one slice per wave.  A wave owns every
-// 16x16 tile (pb <= qb) of R for its rows, so consecutive MFMAs go to
-// independent accumulators; UNR groups of 4 rows are loaded before use.
-// Lane layout of v_mfma_f64_16x16x4_f64: A[m][k] from lane m + 16k, B[k][n]
-// from lane n + 16k, D[m][n] in lane n + 16*(m%4), element m/4.
+// Partial Grams of row slices, one slice per workgroup of 8 waves (so
+// enough waves keep the row loads in flight while the number of partials
+// stays bounded).  Wave w takes the slice's row groups of 4 rows
+// w UNR + 8 UNR j, ..., accumulates every 16x16 block tile (pb <= qb) of R
+// with FP64 MFMA into independent accumulators, and the waves add their
+// tiles in LDS in wave order (deterministic).  Lane layout of
+// v_mfma_f64_16x16x4_f64: A[m][k] from lane m + 16k, B[k][n] from lane
+// n + 16k, D[m][n] in lane n + 16*(m%4), element m/4.
 template <int NB, int UNR>
-__global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restrict__ C, int64_t rows, int R,
-                                                           double *__restrict__ work) {
-    constexpr int NT = NB * (NB + 1) / 2;
+__global__ __launch_bounds__(kGramSThreads) void k_gram_partial(const float *__restrict__ C, int64_t rows, int R,
+                                                                double *__restrict__ work) {
+    constexpr int NT = NB * (NB + 1) / 2, LDP = NB * 16, NWAVE = kGramSThreads / 64;
+    __shared__ double red[LDP * LDP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slice = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t nslices = (int64_t)gridDim.x * 4;
-    const int64_t r_per = ((rows + nslices - 1) / nslices + 4 * UNR - 1) / (4 * UNR) * (4 * UNR);
+    const int64_t slice = blockIdx.x;
+    const int64_t nslices = gridDim.x;
+    const int64_t r_per = ((rows + nslices - 1) / nslices + 3) / 4 * 4;
     const int64_t r0 = slice * r_per;
     const int64_t r1 = min(r0 + r_per, rows);
     const int kr = lane >> 4, cc = lane & 15;
     double4_t acc[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[i] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    for (int64_t i0 = r0; i0 < r1; i0 += 4 * UNR) {
+    for (int64_t g0 = r0 / 4 + (int64_t)wave * UNR; g0 * 4 < r1; g0 += (int64_t)NWAVE * UNR) {
         double v[UNR][NB];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int64_t row = i0 + 4 * u + kr;
+            const int64_t row = (g0 + u) * 4 + kr;
             const bool rok = row < r1;
             const float *rp = C + row * R;
 #pragma unroll
@@ -76,18 +80,24 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const float *__restri
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][pb], v[u][qb], acc[t], 0, 0, 0);
         }
     }
-    const int ld = NB * 16;
-    double *wb = work + (size_t)slice * ld * ld;
-    int t = 0;
+    for (int w = 0; w < NWAVE; ++w) {
+        if (wave == w) {
+            int t = 0;
 #pragma unroll
-    for (int pb = 0; pb < NB; ++pb)
+            for (int pb = 0; pb < NB; ++pb)
 #pragma unroll
-        for (int qb = pb; qb < NB; ++qb, ++t)
+                for (int qb = pb; qb < NB; ++qb, ++t)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int m = 4 * e + (lane >> 4), n = lane & 15;
-                wb[(size_t)(pb * 16 + m) * ld + qb * 16 + n] = acc[t][e];
-            }
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = 4 * e + (lane >> 4), n = lane & 15;
+                        double &d = red[(pb * 16 + m) * LDP + qb * 16 + n];
+                        d = (w == 0) ? acc[t][e] : d + acc[t][e];
+                    }
+        }
+        __syncthreads();
+    }
+    double *wb = work + (size_t)slice * LDP * LDP;
+    for (int e = threadIdx.x; e < LDP * LDP; e += kGramSThreads) wb[e] = red[e];
 }
 
 // Batched Gram in two launches.  (1) One workgroup of 8 waves per row slice
@@ -569,7 +579,7 @@ __global__ __launch_bounds__(kThreads) void k_fit_direct(const double *__restric
 
 size_t gram_work_bytes(int64_t rows, int rank) {
     const int ld = gram_nb(rank) * 16;
-    return (size_t)gram_chunks(rows, rank) * 4 * ld * ld * sizeof(double) + (size_t)kGramSplit * rank * rank * sizeof(double);
+    return (size_t)gram_chunks(rows, rank) * ld * ld * sizeof(double) + (size_t)kGramSplit * rank * rank * sizeof(double);
 }
 
 spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double *work, size_t work_bytes,
@@ -578,11 +588,12 @@ spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double
     const int chunks = gram_chunks(rows, rank);
     if (gram_work_bytes(rows, rank) > work_bytes) return fail(SPT_E_INVALID_ARG, "gram: workspace too small");
     const int nb = gram_nb(rank), ld = nb * 16;
-    if (nb == 1) hipLaunchKernelGGL((k_gram_partial<1, 4>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
-    else if (nb == 2) hipLaunchKernelGGL((k_gram_partial<2, 4>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
-    else if (nb == 3) hipLaunchKernelGGL((k_gram_partial<3, 2>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
-    else hipLaunchKernelGGL((k_gram_partial<4, 2>), dim3(chunks), dim3(kThreads), 0, s, C, rows, rank, work);
-    const int nslices = chunks * 4;
+    const dim3 g((unsigned)chunks), b(kGramSThreads);
+    if (nb == 1) hipLaunchKernelGGL((k_gram_partial<1, 4>), g, b, 0, s, C, rows, rank, work);
+    else if (nb == 2) hipLaunchKernelGGL((k_gram_partial<2, 4>), g, b, 0, s, C, rows, rank, work);
+    else if (nb == 3) hipLaunchKernelGGL((k_gram_partial<3, 2>), g, b, 0, s, C, rows, rank, work);
+    else hipLaunchKernelGGL((k_gram_partial<4, 2>), g, b, 0, s, C, rows, rank, work);
+    const int nslices = chunks;
     const int S = std::min(kGramSplit, nslices);
     double *w2 = work + (size_t)nslices * ld * ld;
     const int rb = (rank * rank + kThreads - 1) / kThreads;
