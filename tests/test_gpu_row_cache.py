@@ -80,6 +80,14 @@ def test_row_cache_extremes(spt, dims, n):
     _check(t, F, outs, f"dims {dims}")
 
 
+@pytest.mark.parametrize("rank", [130, 256])
+def test_row_cache_wide_ranks(spt, rank):
+    # wide rows: a small cache (16 rows per mode at rank 256), several column blocks per lane
+    t, F = _uniform(rank, (3000, 2000, 500), 150_000, rank)
+    _, outs = _both(spt, t, F)
+    _check(t, F, outs, f"rank {rank}")
+
+
 def test_row_cache_five_modes_falls_back(spt):
     # more than 4 modes: no dictionaries, the uncached kernel runs under either setting
     t, F = _uniform(5, (40, 30, 20, 10, 8), 100_000, 16)
