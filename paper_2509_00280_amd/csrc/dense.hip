@@ -468,12 +468,77 @@ __device__ __forceinline__ void apply_body(const float *__restrict__ M, int ldm,
     }
 }
 
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_apply(const float *__restrict__ M, int64_t rows, int R,
-                                                    const double *__restrict__ S, float *__restrict__ C,
-                                                    const double *__restrict__ lambda,
-                                                    double *__restrict__ inner_partials) {
-    apply_body<RP>(M, R, rows, R, S, C, lambda, inner_partials, blockIdx.x);
+
+// Single-tensor apply on FP64 MFMA: C = M S for 16-row tiles, one tile per
+// wave at a time (tiles strided over the grid), S (RP x RP) in LDS.  The k
+// index of v_mfma_f64_16x16x4_f64 is only summed over, so step j takes
+// columns kq KS + j (KS = RP / 4) for lane quarter kq: every lane then holds
+// 16 (or RP / 4) contiguous values of its row of M, loaded once per tile.
+// Also the fit's inner product sum_rc M[r][c] C[r][c] lambda[c] per block.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_apply_mfma(const float *__restrict__ M, int64_t rows, int R,
+                                                         const double *__restrict__ S, float *__restrict__ C,
+                                                         const double *__restrict__ lambda,
+                                                         double *__restrict__ inner_partials) {
+    constexpr int RP = NB * 16, KS = RP / 4;
+    __shared__ double sS[RP * RP];
+    __shared__ double red[kThreads / 64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < RP * RP; e += kThreads) {
+        const int p = e / RP, q = e % RP;
+        sS[e] = (p < R && q < R) ? S[p * R + q] : 0.0;
+    }
+    __syncthreads();
+    const int mrow = lane & 15, kq = lane >> 4;
+    const int64_t ntile = (rows + 15) / 16;
+    double inner = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave; t < ntile;
+         t += (int64_t)gridDim.x * (kThreads / 64)) {
+        const int64_t r0 = t * 16;
+        const int64_t arow = r0 + mrow;
+        float a[KS];
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int c = kq * KS + j;
+            a[j] = (arow < rows && c < R) ? M[arow * R + c] : 0.f;
+        }
+        double4_t acc[NB];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const double av = (double)a[j];
+            const double *srow = sS + (kq * KS + j) * RP + mrow;  // B[k][n] = S[k][cb 16 + n], n = lane & 15
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, srow[cb * 16], acc[cb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = 4 * e + (lane >> 4), n = lane & 15;
+                const int64_t row = r0 + m;
+                const int c = cb * 16 + n;
+                if (row < rows && c < R) {
+                    const float v = (float)acc[cb][e];
+                    C[row * R + c] = v;
+                    if (inner_partials) inner += (double)M[row * R + c] * (double)v * lambda[c];
+                }
+            }
+        }
+    }
+    if (inner_partials) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) inner += __shfl_down(inner, off, 64);
+        if (lane == 0) red[wave] = inner;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) sum += red[w];
+            inner_partials[blockIdx.x] = sum;
+        }
+    }
 }
 
 // Batched: block `g` belongs to the last item whose first_block <= g.
@@ -612,23 +677,27 @@ spt_status launch_solve_prep(const double *grams, int nmodes, int mode, int rank
     return SPT_OK;
 }
 
+constexpr int64_t kApplyMaxBlocks = 2048;
 int apply_blocks(int64_t rows, int rank) {
-    const int rp = apply_rp(rank);
-    const int rw = rp == 16 ? apply_rows_per_block<16>() : (rp == 32 ? apply_rows_per_block<32>() : apply_rows_per_block<64>());
-    int64_t b = (rows + rw - 1) / rw;
-    return (int)(b < 1 ? 1 : b);
+    (void)rank;
+    const int64_t tiles = (rows + 15) / 16;  // 16-row MFMA tiles, 4 per block at a time
+    return (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, kApplyMaxBlocks));
 }
+
 
 spt_status launch_apply(const float *M, int64_t rows, int rank, const double *S, float *C, const double *lambda,
                         double *inner_partials, int *nparts_out, hipStream_t s) {
     const int blocks = apply_blocks(rows, rank);
     const int rp = apply_rp(rank);
     if (rp == 16)
-        hipLaunchKernelGGL(k_apply<16>, dim3(blocks), dim3(kThreads), 0, s, M, rows, rank, S, C, lambda, inner_partials);
+        hipLaunchKernelGGL(k_apply_mfma<1>, dim3(blocks), dim3(kThreads), 0, s, M, rows, rank, S, C, lambda,
+                           inner_partials);
     else if (rp == 32)
-        hipLaunchKernelGGL(k_apply<32>, dim3(blocks), dim3(kThreads), 0, s, M, rows, rank, S, C, lambda, inner_partials);
+        hipLaunchKernelGGL(k_apply_mfma<2>, dim3(blocks), dim3(kThreads), 0, s, M, rows, rank, S, C, lambda,
+                           inner_partials);
     else
-        hipLaunchKernelGGL(k_apply<64>, dim3(blocks), dim3(kThreads), 0, s, M, rows, rank, S, C, lambda, inner_partials);
+        hipLaunchKernelGGL(k_apply_mfma<4>, dim3(blocks), dim3(kThreads), 0, s, M, rows, rank, S, C, lambda,
+                           inner_partials);
     SPT_HIP(hipGetLastError());
     if (nparts_out) *nparts_out = blocks;
     return SPT_OK;

@@ -298,7 +298,9 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
                                     const uint32_t rv = row[o][u];
                                     if (EXACT || c < R) {
                                         if (rv & kDictHit) {
-                                            const float *cp = cache + ((size_t)(o * cap) + (rv & ~kDictHit)) * R + c;
+                                            // row stride: a compile-time shift when the groups cover R exactly
+                                            const int rs = EXACT ? G * VEC * NB : R;
+                                            const float *cp = cache + ((size_t)(o * cap) + (rv & ~kDictHit)) * rs + c;
                                             if constexpr (VEC == 4) {
                                                 const float4 t4 = *reinterpret_cast<const float4 *>(cp);
                                                 xv[o][u][b][0] = t4.x;
