@@ -40,3 +40,21 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     lib.spt_version.restype = ctypes.c_char_p
     assert lib.spt_version().decode().startswith("spt-gfx950")
+
+
+def test_binding_plan_struct_matches_header():
+    # the ctypes mirror of spt_plan lists the header's fields in order with the same types
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    m = re.search(r"typedef struct \{([^}]*)\} spt_plan;", src)
+    assert m, "spt_plan not found"
+    fields = [" ".join(f.split()) for f in m.group(1).split(";") if f.strip()]
+    want = []
+    for f in fields:
+        g = re.match(r"int (\w+)(\[SPT_MAX_MODES\])?$", f)
+        assert g, f
+        want.append((g.group(1), bool(g.group(2))))
+    from paper_2509_00280_amd import spt
+    got = [(name, hasattr(ty, "_length_")) for name, ty in spt.Plan._fields_]
+    assert got == want
+    assert ctypes.sizeof(spt.Plan) == 4 * sum(spt.MAX_MODES if arr else 1 for _, arr in want)
