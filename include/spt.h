@@ -22,6 +22,9 @@
  *    returns a message (thread-local).
  *  - The caller owns every buffer it passes; the library owns the memory
  *    behind an spt_tensor until spt_tensor_free.
+ *  - Every device buffer the library owns is taken from and returned to the
+ *    allocator hook (spt_set_allocator) in stream order: releasing memory
+ *    never synchronises the device or a stream.
  */
 #ifndef SPT_H
 #define SPT_H
@@ -84,8 +87,8 @@ typedef struct {
                                    nonzero, pieces of at most 32 nonzeros of one row); every piece
                                    becomes a record written with plain stores at a slot that keeps the
                                    records grouped by row; records are summed per row (no atomics
-                                   except for rows split between two reducer chunks).  The first call
-                                   at a mode builds the plan: 2 B per nonzero plus 12 B per piece */
+                                   except for rows split between two reducer chunks).  The plan is
+                                   built by spt_tensor_prepare: 2 B per nonzero plus 12 B per piece */
 typedef struct {
     int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256..1024 for DIRECT/REGROUP (larger
                                      values act as 1024), 1024/2048/4096 for SEGMENT (smaller values,
@@ -94,11 +97,33 @@ typedef struct {
     int strategy[SPT_MAX_MODES];  /* SPT_STRATEGY_* */
     int row_cache;                /* SEGMENT with 4096-nonzero tiles on tensors of 2..4 modes: 1
                                      (default) keeps each tile's most used factor rows in LDS, read
-                                     through the tile dictionaries (built once per encoding on first
-                                     use: 2 B per nonzero per mode plus 4 B per distinct (tile, row)
-                                     pair; the build synchronises the stream once); 0 reads every
-                                     factor row from memory */
+                                     through the tile dictionaries (built by spt_tensor_prepare: 2 B
+                                     per nonzero per mode plus 4 B per distinct (tile, row) pair);
+                                     0 reads every factor row from memory */
 } spt_plan;
+
+/* ---------------------------------------------------------------------- */
+/* Device memory.                                                          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Allocator hook: alloc(bytes, stream, ctx) returns device memory usable by
+ * work ordered after the call on `stream` (NULL on failure; the library
+ * reports SPT_E_OOM); release(ptr, stream, ctx) returns it once all work the
+ * library ordered on `stream` before the call is done with it.  The library
+ * releases a buffer on the stream of the call that frees it; a hook whose
+ * memory is reused per stream (PyTorch's caching allocator) therefore needs
+ * that a buffer is used on one stream, which holds for every call except the
+ * server, whose requests the library synchronises before release.  Requests
+ * are rounded up to 256 bytes and the returned pointer must be 256-byte
+ * aligned.  Passing NULL for both restores the default (the device's
+ * stream-ordered memory pool).  Every buffer goes back to the allocator
+ * that supplied it, whatever hook is set when it is released.
+ * Errors: SPT_E_INVALID_ARG (exactly one hook NULL).
+ */
+typedef void *(*spt_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*spt_release_fn)(void *ptr, void *stream, void *ctx);
+spt_status spt_set_allocator(spt_alloc_fn alloc, spt_release_fn release, void *ctx);
 
 /* ---------------------------------------------------------------------- */
 /* Encoding (Section III-C: linearized tensor, positions of l(p) bits).    */
@@ -138,12 +163,41 @@ spt_status spt_tensor_export(spt_tensor t, uint64_t *keys, float *vals, uint32_t
 /* Decode every key back to coordinates: coords[n * nnz + j] (device, uint32 SoA). */
 spt_status spt_tensor_decode(spt_tensor t, uint32_t *coords, void *stream);
 
-/* Plan of the tensor (host copy) / replace it. */
+/* Plan of the tensor (host copy). */
 spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan);
-spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan);
 
-/* Release the handle (waits for nothing; the caller orders it after its last use). */
-void spt_tensor_free(spt_tensor t);
+/*
+ * Replace the plan.  The per-mode state built for the old plan is released
+ * in stream order on `stream` (the caller orders this call after every use
+ * of the tensor on other streams) and the tensor becomes unprepared: call
+ * spt_tensor_prepare before the next spt_mttkrp.  Does not synchronise.
+ */
+spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan, void *stream);
+
+#define SPT_PREPARE_SINGLE 1   /* per-mode plans of spt_mttkrp (and the tile dictionaries) */
+#define SPT_PREPARE_BATCHED 2  /* per-mode plans of the batched launch (spt_mttkrp_batched) */
+
+/*
+ * Build the per-mode state MTTKRP needs under the tensor's plan, for every
+ * mode: the SEGMENT plan (a counting pass and one emission pass over the
+ * nonzeros: 2 B per nonzero plus 12 B per piece), the tile dictionaries of
+ * the row cache (2 B per nonzero per mode plus 4 B per distinct (tile, row)
+ * pair) and, under the TABLE strategy, that strategy's plan for `rank`
+ * (the only rank-dependent plan).  `what` is a mask of SPT_PREPARE_*.  It is
+ * derived from the encoding alone (Section III-C keeps one mode-agnostic
+ * copy; this is an index over it) and kept until the plan changes or the
+ * tensor is freed; preparing again is free.  Synchronises `stream` (the
+ * sizes of the plans are read back).  1 <= rank <= SPT_MAX_RANK.
+ * Errors: SPT_E_INVALID_ARG, SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_tensor_prepare(spt_tensor t, int rank, int what, void *stream);
+
+/*
+ * Release the handle in stream order on `stream`: the caller orders this
+ * call after the tensor's last use (on `stream`, or on another stream that
+ * `stream` waits for).  Does not synchronise.
+ */
+void spt_tensor_free(spt_tensor t, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* MTTKRP (Section II-B, Fig. 2).                                          */
@@ -155,9 +209,12 @@ void spt_tensor_free(spt_tensor t);
  * factors[k][i_k, :].  FP32 inputs, FP32 accumulation (order unspecified).
  *   factors  host array of nmodes device pointers (factors[mode] is not read).
  *   out      device, I_mode x rank, OVERWRITTEN (rows without nonzeros are 0).
- * Asynchronous; host-side argument checks only.  1 <= rank <= SPT_MAX_RANK.
- * The first call at a (mode, rank) under the TABLE or SEGMENT strategy
- * builds that mode's plan (a counting pass) and synchronises the stream once.
+ * Asynchronous and free of synchronisation: host-side argument checks
+ * only; the record workspace of the call is taken from the allocator hook and
+ * released in stream order on `stream`, so calls on different streams over
+ * one tensor may overlap.  The tensor must be prepared (spt_tensor_prepare,
+ * SPT_PREPARE_SINGLE; under the TABLE strategy for this rank), else
+ * SPT_E_INVALID_ARG.  1 <= rank <= SPT_MAX_RANK.
  */
 spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
                       void *stream);
@@ -178,11 +235,35 @@ spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int m
  *   factors  host array of nmodes device pointers, in: initial, out: normalised.
  *   lambda   device, rank FP64 (out).
  *   fit_out, iters_out  host (out).
- * Synchronises `stream` once per iteration.  1 <= rank <= SPT_MAX_ALS_RANK.
+ * The iterations run on library-owned copies of the factors: factors and
+ * lambda are written only when the call returns SPT_OK.  Prepares the
+ * tensor for `rank` if needed.  Synchronises `stream` once per iteration
+ * (and while preparing).  1 <= rank <= SPT_MAX_ALS_RANK.
  * Errors: SPT_E_INVALID_ARG (also when |X| = 0), SPT_E_NOT_SPD, SPT_E_OOM, SPT_E_DEVICE.
  */
 spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *const *factors,
                       double *lambda, double *fit_out, int *iters_out, void *stream);
+
+/*
+ * One ALS mode update on dense operands (the solve step of spt_cp_als, for
+ * callers that form M themselves): V = Hadamard product of grams[k] over
+ * k != mode (FP64), Cholesky V = L L^T with the ridge retry (V + d_k I,
+ * d_k = 1e-12 tr(V)/R * 1e3^(k-1) on retry k = 1..3), C = M V^-1 with
+ * columns normalised to unit 2-norm, their norms in lambda (a zero column
+ * keeps norm 1), rounded to FP32.  Kolda and Bader's ALS, which Section II-B
+ * cites for CP-ALS.
+ *   grams    device, nmodes x rank x rank FP64 (grams[mode] is not read).
+ *   M        device, rows x rank FP32 (the mode's MTTKRP output).
+ *   C        device out, rows x rank FP32 (may alias nothing else).
+ *   lambda   device out, rank FP64.
+ *   retries_out  host out: ridge retries taken (0 when V was positive definite).
+ * Synchronises `stream` once (the factorisation status).  C, lambda and
+ * retries_out are written only on SPT_OK.  1 <= rank <= SPT_MAX_ALS_RANK.
+ * Errors: SPT_E_INVALID_ARG, SPT_E_NOT_SPD (V + d_3 I still not positive
+ * definite, or not finite), SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_als_update(const double *grams, int nmodes, int mode, int rank, const float *M, int64_t rows,
+                          float *C, double *lambda, int *retries_out, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batches of independent tensors (many decompositions, Section IV-D).     */
@@ -194,9 +275,9 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
  * records and one reduction; tensors with nmodes <= mode are skipped and
  * their outs[b] is not touched.  factors[b] is a host array of device
  * pointers for tensor b, outs[b] its output (I_mode x ranks[b], overwritten),
- * 1 <= ranks[b] <= 64.  The first call at a mode plans every tensor that
- * lacks a batched plan (one counting launch for all of them).  Synchronises
- * `stream` before returning (the record workspace is released).
+ * 1 <= ranks[b] <= 64.  Every tensor must be prepared with
+ * SPT_PREPARE_BATCHED (else SPT_E_INVALID_ARG).  Asynchronous and free of
+ * synchronisation: the call's workspaces are released in stream order.
  */
 spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *const *const *factors,
                               const int *ranks, int mode, float *const *outs, void *stream);
@@ -211,7 +292,10 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
  * host array of device pointers (in: initial, out: normalised), lambdas[b]
  * a device array of ranks[b] doubles, fits[b] and iters[b] host outputs.
  * Synchronises once per iteration (plus once when a fit takes the direct
- * residual).  Errors: as spt_cp_als, for the first failing tensor.
+ * residual; plus the batched plans of tensors not yet prepared with
+ * SPT_PREPARE_BATCHED).  The iterations run on library-owned copies:
+ * factors and lambdas are written only when the call returns SPT_OK.
+ * Errors: as spt_cp_als, for the first failing tensor.
  */
 spt_status spt_cp_als_batched(const spt_tensor *ts, int count, const int *ranks, int max_iters,
                               double tol, float *const *const *factors, double *const *lambdas,
@@ -221,16 +305,33 @@ spt_status spt_cp_als_batched(const spt_tensor *ts, int count, const int *ranks,
 /* Autotuner (the measured search over encodings of Section III-C).        */
 /* ---------------------------------------------------------------------- */
 
+/* Outcome of spt_autotune (host).  Times are all-mode MTTKRP milliseconds,
+ * each mode at its best plan for the layout. */
+typedef struct {
+    double best_ms;      /* the winning layout (the tensor holds it on return) */
+    double alto_ms;      /* the default (ALTO) layout: alto_ms / best_ms is the paper's reward */
+    double start_ms;     /* the layout the tensor had on entry */
+    int candidates;      /* layouts measured, cache hits included */
+    int random_samples;  /* of which drawn uniformly from the interleaving space */
+    int cache_hits;      /* of which answered by the measurement cache */
+    int pad;
+} spt_tune_result;
+
 /*
- * Search layouts (the default interleaving and valid local moves of it) and
- * per-mode tile/strategy by timing all-mode MTTKRP on `stream`; re-encodes
- * *t in place when a different layout wins and stores the winning plan.
- * Measured candidates are cached per (tensor shape, nnz, rank, layout).
- * budget_ms bounds the search's GPU time.  Host out: best_ms, the all-mode
- * time of the winner.  Synchronises.
+ * Measured search over the tensor's bit layout (the interleavings of Section
+ * III-C, counted by Eq. (1)) and the per-mode plan (strategy, tile), with the
+ * paper's reward: all-mode MTTKRP time against the default (ALTO) layout.
+ * Candidates: the tensor's layout, the ALTO layout, `random_samples` layouts
+ * drawn uniformly from the interleaving space (seeded by `seed`), then a hill
+ * climb of adjacent-bit exchanges from the best so far, within budget_ms of
+ * wall time.  Each layout is measured with every mode at its best plan and
+ * cached per (mode lengths, nnz, rank, layout, content fingerprint).
+ * Re-encodes *t in place when another layout wins (export keeps naming the
+ * caller's input order) and leaves it prepared (SPT_PREPARE_SINGLE) for
+ * `rank` under the winning plan.  Synchronises.
  */
-spt_status spt_autotune(spt_tensor *t, const float *const *factors, int rank, double budget_ms,
-                        double *best_ms, void *stream);
+spt_status spt_autotune(spt_tensor *t, const float *const *factors, int rank, double budget_ms, int random_samples,
+                        uint64_t seed, spt_tune_result *result, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of CP-ALS requests.                        */

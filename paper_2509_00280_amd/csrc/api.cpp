@@ -6,8 +6,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "spt_internal.h"
@@ -30,10 +32,17 @@ spt_status hip_fail(hipError_t e, const char *what) {
 }
 
 // ---------------------------------------------------------------- device memory
-// Stream-ordered allocations from the device's default pool; the pool keeps
-// freed blocks (release threshold raised once per device) so repeated
-// encode / cp_als calls do not go back to the driver.
+// Every device buffer the library owns comes from dev_alloc and goes back
+// through dev_free on a stream, in stream order: a buffer released on stream
+// s may be reused by work ordered after that point of s, so releasing never
+// waits for the device.  By default the bytes come from the device's
+// stream-ordered pool (release threshold raised once per device, so repeated
+// calls do not return memory to the driver); spt_set_allocator replaces the
+// source, e.g. with PyTorch's caching allocator.
 static std::once_flag g_pool_once[64];
+static std::atomic<spt_alloc_fn> g_alloc{nullptr};
+static std::atomic<spt_release_fn> g_release{nullptr};
+static std::atomic<void *> g_alloc_ctx{nullptr};
 
 static void tune_pool() {
     int dev = 0;
@@ -47,10 +56,33 @@ static void tune_pool() {
     });
 }
 
+// Buffers taken from a hook remember the hook that releases them, so
+// changing the hook never sends a buffer to the wrong allocator.
+struct HookOwner {
+    spt_release_fn release;
+    void *ctx;
+};
+static std::mutex g_owner_mu;
+static std::unordered_map<void *, HookOwner> g_owner;
+
 void *dev_alloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (spt_alloc_fn f = g_alloc.load()) {
+        void *ctx = g_alloc_ctx.load();
+        const spt_release_fn rel = g_release.load();
+        void *p = f(bytes, (void *)s, ctx);
+        if (!p) return nullptr;
+        if ((uintptr_t)p & 255u) {  // the kernels assume 256-byte alignment
+            rel(p, (void *)s, ctx);
+            return nullptr;
+        }
+        std::lock_guard<std::mutex> lk(g_owner_mu);
+        g_owner[p] = HookOwner{rel, ctx};
+        return p;
+    }
     tune_pool();
     void *p = nullptr;
-    if (bytes == 0) bytes = 16;
     if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
@@ -59,7 +91,21 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
 }
 
 void dev_free(void *p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    HookOwner o{nullptr, nullptr};
+    {
+        std::lock_guard<std::mutex> lk(g_owner_mu);
+        auto it = g_owner.find(p);
+        if (it != g_owner.end()) {
+            o = it->second;
+            g_owner.erase(it);
+        }
+    }
+    if (o.release) {
+        o.release(p, (void *)s, o.ctx);
+        return;
+    }
+    (void)hipFreeAsync(p, s);
 }
 
 // ---------------------------------------------------------------- codec
@@ -99,6 +145,21 @@ static int bit_length(int64_t d) {  // ceil(log2 d) for d >= 1
     int b = 0;
     while ((int64_t(1) << b) < d) ++b;
     return b;
+}
+
+// The default (ALTO) interleaving: level by level, modes of shorter bit
+// length first, equal lengths in mode order (Section III-C: partitioning the
+// longest mode first is interleaving from the shortest mode).
+void default_layout(int nmodes, const int *lbits, uint8_t *layout) {
+    int order[kMaxModes];
+    for (int n = 0; n < nmodes; ++n) order[n] = n;
+    std::stable_sort(order, order + nmodes, [&](int a, int b) { return lbits[a] < lbits[b]; });
+    int maxb = 0;
+    for (int n = 0; n < nmodes; ++n) maxb = std::max(maxb, lbits[n]);
+    int pos = 0;
+    for (int j = 0; j < maxb; ++j)
+        for (int i = 0; i < nmodes; ++i)
+            if (j < lbits[order[i]]) layout[pos++] = (uint8_t)order[i];
 }
 
 static void default_plan(const Tensor *t, spt_plan *p) {
@@ -161,6 +222,14 @@ const char *spt_last_error(void) { return g_last_error.c_str(); }
 
 const char *spt_version(void) { return "spt-gfx950 0.1"; }
 
+spt_status spt_set_allocator(spt_alloc_fn alloc, spt_release_fn release, void *ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) return fail(SPT_E_INVALID_ARG, "set_allocator: give both hooks or neither");
+    g_alloc_ctx.store(ctx);
+    g_release.store(release);
+    g_alloc.store(alloc);
+    return SPT_OK;
+}
+
 spt_status spt_profile_enable(int on) { return profile_enable(on); }
 
 spt_status spt_profile_read(double *ms, int64_t *launches) {
@@ -216,16 +285,7 @@ spt_status spt_encode(const int64_t *dims, int nmodes, const uint32_t *coords, c
             }
         std::memcpy(t->layout, layout, lp);
     } else {
-        // default interleaving: level by level, modes ordered by (bit length, index)
-        int order[kMaxModes];
-        for (int n = 0; n < nmodes; ++n) order[n] = n;
-        std::stable_sort(order, order + nmodes, [&](int a, int b) { return t->lbits[a] < t->lbits[b]; });
-        int maxb = 0;
-        for (int n = 0; n < nmodes; ++n) maxb = std::max(maxb, t->lbits[n]);
-        int pos = 0;
-        for (int j = 0; j < maxb; ++j)
-            for (int i = 0; i < nmodes; ++i)
-                if (j < t->lbits[order[i]]) t->layout[pos++] = (uint8_t)order[i];
+        default_layout(nmodes, t->lbits, t->layout);
     }
     make_codec(nmodes, t->lbits, t->layout, lp, &t->codec);
     default_plan(t, &t->plan);
@@ -279,36 +339,41 @@ spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
     return SPT_OK;
 }
 
-spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan) {
+spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan, void *stream) {
     if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
     if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256..4096 (power of two), strategy 0..5, row_cache 0 or 1");
-    (void)hipDeviceSynchronize();  // resolved plans (record offsets) may still be in use
-    release_plans(t);
+    // the old plans may still be read by queued work: released in stream order
+    const hipStream_t s = (hipStream_t)stream;
+    for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n, s);
+    if (plan->row_cache != t->plan.row_cache) release_dict(t, s);
     t->plan = *plan;
+    return SPT_OK;
+}
+
+spt_status spt_tensor_prepare(spt_tensor t, int rank, int what, void *stream) {
+    if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
+    if (rank < 1 || rank > SPT_MAX_RANK) return fail(SPT_E_INVALID_ARG, "rank must be in 1..256");
+    if (what & ~(SPT_PREPARE_SINGLE | SPT_PREPARE_BATCHED)) return fail(SPT_E_INVALID_ARG, "prepare: unknown flags");
+    const hipStream_t s = (hipStream_t)stream;
+    if (what & SPT_PREPARE_SINGLE) {
+        spt_status st = prepare_single(t, rank, s);
+        if (st != SPT_OK) return st;
+    }
+    if (what & SPT_PREPARE_BATCHED) {
+        spt_status st = prepare_batched(t, s);
+        if (st != SPT_OK) return st;
+    }
     return SPT_OK;
 }
 
 }  // extern "C"
 
 namespace spt {
-// Release a handle after its last use on stream s without a device-wide
-// sync: the encoding and batched plans are stream-ordered allocations.
+// Release a handle after its last use on stream s: every buffer is freed in
+// stream order, so nothing waits for the device.
 void tensor_release(Tensor *t, hipStream_t s) {
     if (!t) return;
-    bool host_sync = false;
-    for (int n = 0; n < kMaxModes; ++n)
-        host_sync |= t->mplan[n].rec_off || t->mplan[n].pl_off || t->mplan[n].pl_pos;
-    for (int i = 0; i < WS_NSLOTS; ++i) host_sync |= t->ws[i] != nullptr;
-    for (int k = 0; k < kMaxModes; ++k) host_sync |= t->dict_slot[k] != nullptr;
-    if (host_sync) {
-        (void)hipStreamSynchronize(s);
-        for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n);
-        release_ws(t);
-        release_dict(t);
-    }
-    for (int n = 0; n < kMaxModes; ++n) {
-        release_batch_plan(t, n, s);
-    }
+    release_plans(t, s);
     dev_free(t->lo, s);
     dev_free(t->hi, s);
     dev_free(t->vals, s);
@@ -319,19 +384,7 @@ void tensor_release(Tensor *t, hipStream_t s) {
 
 extern "C" {
 
-void spt_tensor_free(spt_tensor t) {
-    if (!t) return;
-    // the handle's buffers were allocated stream-ordered; release them on the null
-    // stream after the device is idle so no in-flight kernel still reads them
-    (void)hipDeviceSynchronize();
-    release_plans(t);
-    release_ws(t);
-    dev_free(t->lo, nullptr);
-    dev_free(t->hi, nullptr);
-    dev_free(t->vals, nullptr);
-    dev_free(t->perm, nullptr);
-    delete t;
-}
+void spt_tensor_free(spt_tensor t, void *stream) { tensor_release(t, (hipStream_t)stream); }
 
 spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out, void *stream) {
     if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
@@ -354,6 +407,8 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
     spt_status st = check_factors(t, (const float *const *)factors, rank, -1);
     if (st != SPT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    st = prepare_single(t, rank, s);
+    if (st != SPT_OK) return st;
     const int N = t->nmodes;
     const int R = rank;
     int64_t maxI = 0;
@@ -372,14 +427,26 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
     double *inner = (double *)dev_alloc(sizeof(double) * inner_parts, s);
     double *resid = (double *)dev_alloc(sizeof(double) * 2 * std::max<int64_t>(resid_tiles, 1), s);
     double *fitd = (double *)dev_alloc(sizeof(double) * 4 + sizeof(int) * kMaxModes, s);
+    double *lam = (double *)dev_alloc(sizeof(double) * R, s);
+    // the iterations run on copies: the caller's factors and lambda are
+    // written only when the call succeeds
+    float *F[kMaxModes] = {};
+    bool fok = true;
+    for (int k = 0; k < N; ++k) fok = fok && (F[k] = (float *)dev_alloc(sizeof(float) * t->dims[k] * R, s)) != nullptr;
     auto cleanup = [&]() {
         dev_free(M, s); dev_free(grams, s); dev_free(gram_m, s); dev_free(S, s); dev_free(gwork, s);
-        dev_free(inner, s); dev_free(resid, s); dev_free(fitd, s);
+        dev_free(inner, s); dev_free(resid, s); dev_free(fitd, s); dev_free(lam, s);
+        for (int k = 0; k < N; ++k) dev_free(F[k], s);
     };
-    if (!M || !grams || !gram_m || !S || !gwork || !inner || !resid || !fitd) {
+    if (!M || !grams || !gram_m || !S || !gwork || !inner || !resid || !fitd || !lam || !fok) {
         cleanup();
         return fail(SPT_E_OOM, "cp_als: workspace allocation failed");
     }
+    for (int k = 0; k < N; ++k)
+        if (hipMemcpyAsync(F[k], factors[k], sizeof(float) * t->dims[k] * R, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            cleanup();
+            return hip_fail(hipGetLastError(), "cp_als: factor copy");
+        }
     int *status = (int *)(fitd + 4);
 #define CK(x)                    \
     do {                         \
@@ -389,19 +456,19 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
             return st__;         \
         }                        \
     } while (0)
-    for (int k = 0; k < N; ++k) CK(launch_gram(factors[k], t->dims[k], R, grams + (size_t)k * R * R, gwork, gw, s));
+    for (int k = 0; k < N; ++k) CK(launch_gram(F[k], t->dims[k], R, grams + (size_t)k * R * R, gwork, gw, s));
     double fit = 0.0, fit_prev = 0.0;
     int it = 0;
     while (it < max_iters) {
         for (int n = 0; n < N; ++n) {
             const int64_t In = t->dims[n];
-            CK(run_mttkrp(t, (const float *const *)factors, R, n, M, s));
+            CK(run_mttkrp(t, (const float *const *)F, R, n, M, s));
             CK(launch_gram(M, In, R, gram_m, gwork, gw, s));
-            CK(launch_solve_prep(grams, N, n, R, gram_m, S, lambda, status + n, s));
-            CK(launch_apply(M, In, R, S, factors[n], lambda, n == N - 1 ? inner : nullptr, nullptr, s));
-            CK(launch_gram(factors[n], In, R, grams + (size_t)n * R * R, gwork, gw, s));
+            CK(launch_solve_prep(grams, N, n, R, gram_m, S, lam, status + n, s));
+            CK(launch_apply(M, In, R, S, F[n], lam, n == N - 1 ? inner : nullptr, nullptr, s));
+            CK(launch_gram(F[n], In, R, grams + (size_t)n * R * R, gwork, gw, s));
         }
-        CK(launch_fit(grams, N, R, lambda, inner, inner_parts, t->norm_x2, fitd, s));
+        CK(launch_fit(grams, N, R, lam, inner, inner_parts, t->norm_x2, fitd, s));
         double hf[4];
         int hs[kMaxModes];
         if (hipMemcpyAsync(hf, fitd, sizeof(hf), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -420,8 +487,8 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
         if (1.0 - fit < 1e-2 && t->nnz > 0) {
             // near convergence the Gram shortcut loses accuracy (FP32 MTTKRP); take the
             // residual directly over the nonzeros in FP64
-            MttkrpArgs a = make_args(t, (const float *const *)factors, R, -1, nullptr, 1024);
-            CK(launch_resid(a, lambda, resid, (int)resid_tiles, s));
+            MttkrpArgs a = make_args(t, (const float *const *)F, R, -1, nullptr, 1024);
+            CK(launch_resid(a, lam, resid, (int)resid_tiles, s));
             CK(launch_fit_direct(resid, (int)resid_tiles, t->norm_x2, fitd, s));
             if (hipMemcpyAsync(hf, fitd, sizeof(hf), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
@@ -434,11 +501,68 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
         if (tol > 0.0 && std::fabs(fit - fit_prev) < tol) break;
         fit_prev = fit;
     }
+    for (int k = 0; k < N; ++k)
+        if (hipMemcpyAsync(factors[k], F[k], sizeof(float) * t->dims[k] * R, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            cleanup();
+            return hip_fail(hipGetLastError(), "cp_als: factor copy back");
+        }
+    if (it > 0 && hipMemcpyAsync(lambda, lam, sizeof(double) * R, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        cleanup();
+        return hip_fail(hipGetLastError(), "cp_als: lambda copy back");
+    }
 #undef CK
     cleanup();
     *fit_out = fit;
     *iters_out = it;
     return SPT_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+spt_status spt_als_update(const double *grams, int nmodes, int mode, int rank, const float *M, int64_t rows,
+                          float *C, double *lambda, int *retries_out, void *stream) {
+    if (!grams || !lambda || !retries_out || (rows > 0 && (!M || !C)))
+        return fail(SPT_E_INVALID_ARG, "als_update: NULL argument");
+    if (nmodes < 1 || nmodes > kMaxModes || mode < 0 || mode >= nmodes)
+        return fail(SPT_E_INVALID_ARG, "als_update: mode out of range");
+    if (rank < 1 || rank > SPT_MAX_ALS_RANK) return fail(SPT_E_INVALID_ARG, "als_update: rank must be in 1..64");
+    if (rows < 0) return fail(SPT_E_INVALID_ARG, "als_update: rows < 0");
+    if ((M && !aligned16(M)) || (C && !aligned16(C))) return fail(SPT_E_INVALID_ARG, "als_update: M/C not 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int R = rank;
+    const size_t gw = gram_work_bytes(rows, R);
+    double *gram_m = (double *)dev_alloc(sizeof(double) * R * R, s);
+    double *S = (double *)dev_alloc(sizeof(double) * R * R, s);
+    double *gwork = (double *)dev_alloc(gw, s);
+    double *lam = (double *)dev_alloc(sizeof(double) * R, s);
+    int *status = (int *)dev_alloc(sizeof(int), s);
+    auto cleanup = [&]() {
+        dev_free(gram_m, s); dev_free(S, s); dev_free(gwork, s); dev_free(lam, s); dev_free(status, s);
+    };
+    if (!gram_m || !S || !gwork || !lam || !status) {
+        cleanup();
+        return fail(SPT_E_OOM, "als_update: workspace allocation failed");
+    }
+    spt_status st = SPT_OK;
+    if (rows > 0) st = launch_gram(M, rows, R, gram_m, gwork, gw, s);
+    else st = launch_fill_zero((float *)gram_m, 2 * (int64_t)R * R, s);  // FP64 zeros are all-zero bits
+    if (st == SPT_OK) st = launch_solve_prep(grams, nmodes, mode, R, gram_m, S, lam, status, s);
+    int hs = 0;
+    if (st == SPT_OK && (hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+        st = hip_fail(hipGetLastError(), "als_update: status readback");
+    if (st == SPT_OK && hs < 0)
+        st = fail(SPT_E_NOT_SPD, "als_update: normal-equation matrix not positive definite after ridge retries");
+    // outputs are written only once the solve is known to have succeeded
+    if (st == SPT_OK && rows > 0) st = launch_apply(M, rows, R, S, C, lam, nullptr, nullptr, s);
+    if (st == SPT_OK &&
+        hipMemcpyAsync(lambda, lam, sizeof(double) * R, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "als_update: lambda copy");
+    cleanup();
+    if (st == SPT_OK) *retries_out = hs;
+    return st;
 }
 
 }  // extern "C"

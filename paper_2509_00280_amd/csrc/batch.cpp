@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -86,13 +87,21 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
     if (tiles == 0) return SPT_OK;
     DevBuf d_items, d_cnt;
     std::vector<int64_t> h(tiles, 0);
-    if (!d_items.get(sizeof(SegItem) * n, s) || !d_cnt.get(sizeof(int64_t) * tiles, s))
+    if (!d_items.get(sizeof(SegItem) * n, s) || !d_cnt.get(sizeof(int64_t) * tiles, s)) {
+        d_items.release(s);
+        d_cnt.release(s);
         return fail(SPT_E_OOM, "batch plan: counts");
-    SPT_HIP(hipMemcpy(d_items.p, items.data(), sizeof(SegItem) * n, hipMemcpyHostToDevice));
+    }
+    SPT_HIP(hipMemcpyAsync(d_items.p, items.data(), sizeof(SegItem) * n, hipMemcpyHostToDevice, s));
     spt_status st = launch_count_pieces_batched((SegItem *)d_items.p, n, tiles, nmax, (int64_t *)d_cnt.p, s);
-    if (st != SPT_OK) return st;
-    SPT_HIP(hipMemcpyAsync(h.data(), d_cnt.p, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s));
-    SPT_HIP(hipStreamSynchronize(s));
+    if (st == SPT_OK && (hipMemcpyAsync(h.data(), d_cnt.p, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+        st = hip_fail(hipGetLastError(), "batch plan: counts");
+    if (st != SPT_OK) {
+        d_items.release(s);
+        d_cnt.release(s);
+        return st;
+    }
     // offsets: per tensor (local pieces per tile) and batch-wide (pieces, pairs)
     std::vector<std::vector<int64_t>> loff(n);
     std::vector<int64_t> gpiece(tiles), gpair(tiles), piece_base(n + 1, 0);
@@ -114,7 +123,11 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         G += local;
     }
     piece_base[n] = G;
-    if (G >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "batch plan: more than 2^32 records");
+    if (G >= (int64_t(1) << 32)) {
+        d_items.release(s);
+        d_cnt.release(s);
+        return fail(SPT_E_INVALID_ARG, "batch plan: more than 2^32 records");
+    }
     // the tensors' plan arrays (stream-ordered: released without a device-wide sync)
     for (int i = 0; i < n; ++i) {
         Tensor *t = need[i];
@@ -128,6 +141,8 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         if (!p.pl_off || !p.pl_pos || !p.pl_desc || !p.pl_row || !p.pl_dest) {
             (void)hipStreamSynchronize(s);  // copies from host vectors may be in flight
             for (int k = 0; k <= i; ++k) release_batch_plan(need[k], mode, s);
+            d_items.release(s);
+            d_cnt.release(s);
             return fail(SPT_E_OOM, "batch plan: arrays");
         }
         SPT_HIP(hipMemcpyAsync(p.pl_off, loff[i].data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, s));
@@ -154,6 +169,8 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         !cnt.get(sizeof(uint32_t) * std::max(sort_ws_counts(Q), exclusive_scan_ws(Q)), s)) {
         (void)hipStreamSynchronize(s);
         for (Tensor *t : need) release_batch_plan(t, mode, s);
+        for (DevBuf *b : {&d_items, &d_cnt, &d_gpiece, &d_gpair, &d_base, &ppair, &psub, &keys, &keys2, &np, &ia, &ib, &cnt})
+            b->release(s);
         return fail(SPT_E_OOM, "batch plan: workspace");
     }
     SPT_HIP(hipMemcpyAsync(d_gpiece.p, gpiece.data(), sizeof(int64_t) * tiles, hipMemcpyHostToDevice, s));
@@ -181,8 +198,17 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         for (Tensor *t : need) release_batch_plan(t, mode, s);
     }
     for (DevBuf *b : {&d_items, &d_cnt, &d_gpiece, &d_gpair, &d_base, &ppair, &psub, &keys, &keys2, &np, &ia, &ib, &cnt})
-        b->release();
+        b->release(s);
     return st;
+}
+
+spt_status prepare_batched(Tensor *t, hipStream_t s) {
+    std::vector<Tensor *> one{t};
+    for (int n = 0; n < t->nmodes; ++n) {
+        spt_status st = ensure_batch_plans(one, n, s);
+        if (st != SPT_OK) return st;
+    }
+    return SPT_OK;
 }
 
 // The batched MTTKRP pipeline of one mode into M_all (rows x ld, overwritten).
@@ -203,27 +229,63 @@ spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t to
     return st;
 }
 
+// ---------------------------------------------------------------- staged uploads
+// Host-to-device copies of per-call item tables go through a ring of pinned
+// host slots, each guarded by an event: a copy from pinned memory is truly
+// asynchronous, and a slot is reused only once its previous copy has run
+// (the host waits only when every slot's copy is still queued).
+namespace {
+struct PinnedSlot {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+constexpr int kPinnedSlots = 8;
+std::mutex g_pin_mu;
+PinnedSlot g_pin[kPinnedSlots];
+int g_pin_next = 0;
+}  // namespace
+
+spt_status upload_staged(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return SPT_OK;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    PinnedSlot &p = g_pin[g_pin_next];
+    g_pin_next = (g_pin_next + 1) % kPinnedSlots;
+    if (p.done) SPT_HIP(hipEventSynchronize(p.done));  // the slot's previous copy
+    else SPT_HIP(hipEventCreateWithFlags(&p.done, hipEventDisableTiming));
+    if (p.bytes < bytes) {
+        if (p.host) SPT_HIP(hipHostFree(p.host));
+        p.host = nullptr;
+        p.bytes = 0;
+        const size_t want = std::max<size_t>(bytes, 64 * 1024);
+        SPT_HIP(hipHostMalloc(&p.host, want, hipHostMallocDefault));
+        p.bytes = want;
+    }
+    std::memcpy(p.host, src, bytes);
+    SPT_HIP(hipMemcpyAsync(dst, p.host, bytes, hipMemcpyHostToDevice, s));
+    SPT_HIP(hipEventRecord(p.done, s));
+    return SPT_OK;
+}
+
 // ---------------------------------------------------------------- engine
 BatchEngine::BatchEngine(hipStream_t s) : s_(s) {}
 
+// Every engine buffer is released in stream order on the engine's stream:
+// work already queued keeps its memory until it has run.
 BatchEngine::~BatchEngine() {
-    (void)hipStreamSynchronize(s_);
     for (Member *m : members_) free_member_state(m);
     release_buffers();
 }
 
 void BatchEngine::release_buffers() {
-    for (void *p : {(void *)d_items_, (void *)M_all_, (void *)fit_all_, (void *)status_all_, (void *)inner_all_, (void *)resid_})
-        if (p) (void)hipFree(p);
+    for (DevBuf *b : {&items_buf_, &M_buf_, &fit_buf_, &status_buf_, &inner_buf_, &resid_buf_, &gram_ws_}) b->release(s_);
     d_items_ = nullptr;
     M_all_ = nullptr;
     fit_all_ = nullptr;
     status_all_ = nullptr;
     inner_all_ = nullptr;
     resid_ = nullptr;
-    items_bytes_ = M_bytes_ = fit_cap_ = inner_cap_ = resid_cap_ = 0;
-    ws_.release();
-    gram_ws_.release();
+    ws_.release(s_);
 }
 
 void BatchEngine::free_member_state(Member *m) {
@@ -283,6 +345,7 @@ spt_status BatchEngine::rebuild() {
     }
     // host images of every item array, packed into one upload
     std::vector<char> blob;
+    blob.reserve(blob_.capacity());
     auto put = [&blob](const void *p, size_t bytes) {
         const size_t off = (blob.size() + 255) & ~size_t(255);
         blob.resize(off + bytes);
@@ -393,30 +456,12 @@ spt_status BatchEngine::rebuild() {
         mi.gc_v = std::move(gc);
     }
     (void)max_records;
-    // device buffers that item pointers refer to
-    SPT_HIP(hipStreamSynchronize(s_));
-    if (M_need > M_bytes_) {
-        if (M_all_) (void)hipFree(M_all_);
-        M_all_ = nullptr;
-        M_bytes_ = 0;
-        SPT_HIP(hipMalloc(&M_all_, M_need));
-        M_bytes_ = M_need;
-    }
-    if ((size_t)A > fit_cap_) {
-        if (fit_all_) (void)hipFree(fit_all_);
-        if (status_all_) (void)hipFree(status_all_);
-        fit_all_ = nullptr;
-        status_all_ = nullptr;
-        SPT_HIP(hipMalloc(&fit_all_, sizeof(double) * 4 * A));
-        SPT_HIP(hipMalloc(&status_all_, sizeof(int) * kMaxModes * A));
-        fit_cap_ = A;
-    }
-    if ((size_t)inner_total > inner_cap_) {
-        if (inner_all_) (void)hipFree(inner_all_);
-        inner_all_ = nullptr;
-        SPT_HIP(hipMalloc(&inner_all_, sizeof(double) * std::max<int64_t>(inner_total, 1)));
-        inner_cap_ = inner_total;
-    }
+    // device buffers that item pointers refer to (replaced in stream order)
+    M_all_ = (float *)M_buf_.get(std::max<size_t>(M_need, 256), s_);
+    fit_all_ = (double *)fit_buf_.get(sizeof(double) * 4 * std::max(A, 1), s_);
+    status_all_ = (int *)status_buf_.get(sizeof(int) * kMaxModes * std::max(A, 1), s_);
+    inner_all_ = (double *)inner_buf_.get(sizeof(double) * std::max<int64_t>(inner_total, 1), s_);
+    if (!M_all_ || !fit_all_ || !status_all_ || !inner_all_) return fail(SPT_E_OOM, "batch: engine buffers");
     // rebase offsets into real pointers and pack
     std::vector<FitItem> fit(A);
     for (int i = 0; i < A; ++i) {
@@ -470,14 +515,12 @@ spt_status BatchEngine::rebuild() {
     init_off_ = put(init.data(), sizeof(GramItem) * init.size());
     init_count_ = (int)init.size();
     init_rmax_ = init_rmax;
-    if (blob.size() > items_bytes_) {
-        if (d_items_) (void)hipFree(d_items_);
-        d_items_ = nullptr;
-        items_bytes_ = 0;
-        SPT_HIP(hipMalloc(&d_items_, blob.size()));
-        items_bytes_ = blob.size();
-    }
-    if (!blob.empty()) SPT_HIP(hipMemcpy(d_items_, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    // the host image lives in the engine until the next rebuild, which comes
+    // after a step's synchronisation: the asynchronous upload has run by then
+    blob_.swap(blob);
+    d_items_ = (char *)items_buf_.get(std::max<size_t>(blob_.size(), 256), s_);
+    if (!d_items_) return fail(SPT_E_OOM, "batch: item arrays");
+    if (!blob_.empty()) SPT_HIP(hipMemcpyAsync(d_items_, blob_.data(), blob_.size(), hipMemcpyHostToDevice, s_));
     if (init_count_ > 0) {
         spt_status st = launch_gram_batched((const GramItem *)(d_items_ + init_off_), init_count_, init_slices_,
                                             init_rmax_, (double *)gram_ws_.p, s_);
@@ -534,12 +577,8 @@ spt_status BatchEngine::step() {
     if (!direct.empty()) {
         int64_t need = 0;
         for (int i : direct) need = std::max<int64_t>(need, (active_[i]->t->nnz + 1023) / 1024);
-        if ((size_t)need > resid_cap_ || !resid_) {
-            if (resid_) (void)hipFree(resid_);
-            resid_ = nullptr;
-            SPT_HIP(hipMalloc(&resid_, sizeof(double) * 2 * need));
-            resid_cap_ = need;
-        }
+        resid_ = (double *)resid_buf_.get(sizeof(double) * 2 * need, s_);
+        if (!resid_) return fail(SPT_E_OOM, "batch: residual partials");
         for (int i : direct) {
             Member *m = active_[i];
             // each member's residual runs after the previous one (shared partials)
@@ -596,6 +635,9 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         if (t->nmodes <= mode) continue;
         if (ranks[b] < 1 || ranks[b] > 64) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: rank must be 1..64");
         if (!outs[b]) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: NULL output " + std::to_string(b));
+        if (!t->bplan[mode].pl_off)
+            return fail(SPT_E_INVALID_ARG, "mttkrp_batched: tensor " + std::to_string(b) +
+                                               " not prepared for the batched launch (spt_tensor_prepare)");
         spt_status st = check_factors(t, factors[b], ranks[b], mode);
         if (st != SPT_OK) return st;
         tv.push_back(t);
@@ -607,8 +649,6 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
     }
     if (tv.empty()) return SPT_OK;
     if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: too many modes");
-    spt_status st = ensure_batch_plans(tv, mode, s);
-    if (st != SPT_OK) return st;
     const int ld = rmax;
     std::vector<SegItem> items(tv.size());
     int64_t tiles = 0, recs = 0, rows = 0;
@@ -634,9 +674,8 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         dev_free(M, s);
         return fail(SPT_E_OOM, "mttkrp_batched: workspace");
     }
+    spt_status st = upload_staged(d_items, items.data(), sizeof(SegItem) * items.size(), s);
     BatchMttkrpWs ws;
-    if (hipMemcpyAsync(d_items, items.data(), sizeof(SegItem) * items.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-        st = hip_fail(hipGetLastError(), "mttkrp_batched: upload");
     if (st == SPT_OK) st = run_mttkrp_batched_mode(d_items, (int)items.size(), tiles, nmin, nmax, recs, rows, ld, vec4, M, ws, s);
     for (size_t i = 0; st == SPT_OK && i < tv.size(); ++i) {
         const int b = idx[i];
@@ -646,9 +685,8 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
                              sizeof(float) * ranks[b], In, hipMemcpyDeviceToDevice, s) != hipSuccess)
             st = hip_fail(hipGetLastError(), "mttkrp_batched: output copy");
     }
-    // the record buffers are freed only after the stream has consumed them
-    (void)hipStreamSynchronize(s);
-    ws.release();
+    // released in stream order after the kernels above: no synchronisation
+    ws.release(s);
     dev_free(d_items, s);
     dev_free(M, s);
     return st;
@@ -662,26 +700,69 @@ spt_status spt_cp_als_batched(const spt_tensor *ts, int count, const int *ranks,
     if (max_iters < 0) return fail(SPT_E_INVALID_ARG, "cp_als_batched: max_iters < 0");
     hipStream_t s = (hipStream_t)stream;
     std::vector<Member> mem(count);
-    BatchEngine eng(s);
-    for (int b = 0; b < count; ++b) {
-        Member &m = mem[b];
-        if (!ts[b] || !factors[b] || !lambdas[b]) return fail(SPT_E_INVALID_ARG, "cp_als_batched: NULL member " + std::to_string(b));
-        m.t = ts[b];
-        m.R = ranks[b];
-        for (int k = 0; k < ts[b]->nmodes; ++k) m.F[k] = factors[b][k];
-        m.lambda = lambdas[b];
-        m.max_iters = max_iters;
-        m.tol = tol;
-        spt_status st = eng.add(&m);
-        if (st != SPT_OK) return st;
-        if (max_iters == 0) m.done = true;
-    }
-    while (eng.any_active()) {
-        spt_status st = eng.step();
-        if (st != SPT_OK) return st;
-        for (int b = 0; b < count; ++b)
-            if (mem[b].err != SPT_OK) return mem[b].err;
-    }
+    // the iterations run on copies of the factors and lambdas: the caller's
+    // buffers are written only when every member succeeded
+    std::vector<void *> owned;
+    auto release_owned = [&]() {
+        for (void *p : owned) dev_free(p, s);
+        owned.clear();
+    };
+    spt_status st = SPT_OK;
+    {
+        BatchEngine eng(s);
+        for (int b = 0; b < count && st == SPT_OK; ++b) {
+            Member &m = mem[b];
+            if (!ts[b] || !factors[b] || !lambdas[b]) {
+                st = fail(SPT_E_INVALID_ARG, "cp_als_batched: NULL member " + std::to_string(b));
+                break;
+            }
+            m.t = ts[b];
+            m.R = ranks[b];
+            if (m.R < 1 || m.R > SPT_MAX_ALS_RANK) {
+                st = fail(SPT_E_INVALID_ARG, "cp_als_batched: rank must be 1..64");
+                break;
+            }
+            st = check_factors(m.t, (const float *const *)factors[b], m.R, -1);
+            for (int k = 0; k < m.t->nmodes && st == SPT_OK; ++k) {
+                const size_t bytes = sizeof(float) * (size_t)m.t->dims[k] * m.R;
+                m.F[k] = (float *)dev_alloc(bytes, s);
+                if (!m.F[k]) st = fail(SPT_E_OOM, "cp_als_batched: factor copies");
+                else {
+                    owned.push_back(m.F[k]);
+                    if (hipMemcpyAsync(m.F[k], factors[b][k], bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                        st = hip_fail(hipGetLastError(), "cp_als_batched: factor copy");
+                }
+            }
+            if (st != SPT_OK) break;
+            m.lambda = (double *)dev_alloc(sizeof(double) * m.R, s);
+            if (!m.lambda) {
+                st = fail(SPT_E_OOM, "cp_als_batched: lambda");
+                break;
+            }
+            owned.push_back(m.lambda);
+            m.max_iters = max_iters;
+            m.tol = tol;
+            st = eng.add(&m);
+            if (st == SPT_OK && max_iters == 0) m.done = true;
+        }
+        while (st == SPT_OK && eng.any_active()) {
+            st = eng.step();
+            for (int b = 0; st == SPT_OK && b < count; ++b)
+                if (mem[b].err != SPT_OK) st = mem[b].err;
+        }
+        for (int b = 0; st == SPT_OK && b < count; ++b) {
+            for (int k = 0; k < mem[b].t->nmodes && st == SPT_OK; ++k)
+                if (hipMemcpyAsync(factors[b][k], mem[b].F[k], sizeof(float) * (size_t)mem[b].t->dims[k] * mem[b].R,
+                                   hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    st = hip_fail(hipGetLastError(), "cp_als_batched: factor copy back");
+            if (st == SPT_OK && max_iters > 0 &&
+                hipMemcpyAsync(lambdas[b], mem[b].lambda, sizeof(double) * mem[b].R, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                st = hip_fail(hipGetLastError(), "cp_als_batched: lambda copy back");
+        }
+    }  // the engine releases its buffers in stream order here
+    release_owned();
+    if (st != SPT_OK) return st;
     for (int b = 0; b < count; ++b) {
         fits[b] = mem[b].fit;
         iters[b] = mem[b].iters;

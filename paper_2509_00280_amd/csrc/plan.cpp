@@ -83,38 +83,11 @@ int device_cus() {
     return cus[dev];
 }
 
-void *tensor_ws(Tensor *t, int slot, size_t bytes, hipStream_t s) {
-    if (bytes == 0) bytes = 256;
-    if (t->ws_bytes[slot] >= bytes) return t->ws[slot];
-    if (t->ws[slot]) {
-        (void)hipStreamSynchronize(s);  // earlier work on this stream may still use the old buffer
-        (void)hipFree(t->ws[slot]);
-        t->ws[slot] = nullptr;
-        t->ws_bytes[slot] = 0;
-    }
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    t->ws[slot] = p;
-    t->ws_bytes[slot] = bytes;
-    return p;
-}
-
-void release_ws(Tensor *t) {
-    for (int i = 0; i < WS_NSLOTS; ++i) {
-        if (t->ws[i]) (void)hipFree(t->ws[i]);
-        t->ws[i] = nullptr;
-        t->ws_bytes[i] = 0;
-    }
-}
-
-void release_mode_plan(Tensor *t, int n) {
+void release_mode_plan(Tensor *t, int n, hipStream_t s) {
     ModePlan &p = t->mplan[n];
     for (void *q : {(void *)p.rec_off, (void *)p.pl_pos, (void *)p.pl_off, (void *)p.pl_desc, (void *)p.pl_row,
                     (void *)p.pl_dest})
-        if (q) (void)hipFree(q);
+        dev_free(q, s);
     p = ModePlan{};
 }
 
@@ -125,10 +98,9 @@ void release_batch_plan(Tensor *t, int n, hipStream_t s) {
     p = ModePlan{};
 }
 
-void release_dict(Tensor *t) {
+void release_dict(Tensor *t, hipStream_t s) {
     for (int k = 0; k < kMaxModes; ++k) {
-        for (void *q : {(void *)t->dict_slot[k], (void *)t->dict_row[k], (void *)t->dict_off[k]})
-            if (q) (void)hipFree(q);
+        for (void *q : {(void *)t->dict_slot[k], (void *)t->dict_row[k], (void *)t->dict_off[k]}) dev_free(q, s);
         t->dict_slot[k] = nullptr;
         t->dict_row[k] = nullptr;
         t->dict_off[k] = nullptr;
@@ -136,12 +108,12 @@ void release_dict(Tensor *t) {
     t->dict_state = 0;
 }
 
-void release_plans(Tensor *t) {
+void release_plans(Tensor *t, hipStream_t s) {
     for (int n = 0; n < kMaxModes; ++n) {
-        release_mode_plan(t, n);
-        release_batch_plan(t, n, nullptr);  // callers order this after the tensor's last use
+        release_mode_plan(t, n, s);
+        release_batch_plan(t, n, s);
     }
-    release_dict(t);
+    release_dict(t, s);
 }
 
 // Tile dictionaries (per mode, once per encoding).  They are an
@@ -165,7 +137,8 @@ static spt_status build_dict_mode(Tensor *t, int k, hipStream_t s, const int64_t
     const int64_t ntiles = (t->nnz + kDictTile - 1) / kDictTile;
     std::vector<int64_t> h;
     const MttkrpArgs a = make_args(t, nullptr, 1, k, nullptr, kDictTile);
-    bool ok = hipMalloc(&t->dict_off[k], sizeof(int64_t) * (ntiles + 1)) == hipSuccess;
+    t->dict_off[k] = (int64_t *)dev_alloc(sizeof(int64_t) * (ntiles + 1), s);
+    bool ok = t->dict_off[k] != nullptr;
     if (ok && !pairs) {
         h.assign(ntiles + 1, 0);
         ok = launch_count_pieces(a, t->dict_off[k], s) == SPT_OK &&
@@ -181,17 +154,19 @@ static spt_status build_dict_mode(Tensor *t, int k, hipStream_t s, const int64_t
         if (ok) h[ntiles] = run;
         pairs = h.data();
     }
-    ok = ok &&
+    if (ok) {
+        t->dict_slot[k] = (uint16_t *)dev_alloc(sizeof(uint16_t) * t->nnz, s);
+        t->dict_row[k] = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max<int64_t>(pairs[ntiles], 1), s);
+    }
+    ok = ok && t->dict_slot[k] && t->dict_row[k] &&
          hipMemcpyAsync(t->dict_off[k], pairs, sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s) ==
              hipSuccess &&
-         hipMalloc(&t->dict_slot[k], sizeof(uint16_t) * t->nnz) == hipSuccess &&
-         hipMalloc(&t->dict_row[k], sizeof(uint32_t) * std::max<int64_t>(pairs[ntiles], 1)) == hipSuccess &&
          launch_emit_dict(a, t->dict_off[k], t->dict_row[k], t->dict_slot[k], s) == SPT_OK;
     // the host prefix must outlive the copy
     ok = hipStreamSynchronize(s) == hipSuccess && ok;
     if (!ok) {
         (void)hipGetLastError();
-        release_dict(t);
+        release_dict(t, s);
         t->dict_state = -1;
     }
     return SPT_OK;
@@ -219,7 +194,8 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     p.ts = segment_tile(t, mode);
     const int64_t ntiles = (t->nnz + p.ts - 1) / p.ts;
     std::vector<int64_t> h(ntiles + 1, 0), hq(ntiles + 1, 0);
-    SPT_HIP(hipMalloc(&p.pl_off, sizeof(int64_t) * (ntiles + 1)));
+    p.pl_off = (int64_t *)dev_alloc(sizeof(int64_t) * (ntiles + 1), s);
+    if (!p.pl_off) return fail(SPT_E_OOM, "plan: offsets");
     if (ntiles > 0) {
         spt_status st = launch_count_pieces(make_args(t, nullptr, rank, mode, nullptr, p.ts), p.pl_off, s);
         if (st != SPT_OK) return st;
@@ -238,14 +214,21 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     hq[ntiles] = pairs;
     p.records = pieces;
     if (pieces >= (int64_t(1) << 32)) return fail(SPT_E_INVALID_ARG, "plan: more than 2^32 records");
-    SPT_HIP(hipMemcpy(p.pl_off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice));
+    SPT_HIP(hipMemcpyAsync(p.pl_off, h.data(), sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, s));
     const size_t n1 = (size_t)std::max<int64_t>(t->nnz, 1), k1 = (size_t)std::max<int64_t>(pieces, 1),
                  q1 = (size_t)std::max<int64_t>(pairs, 1);
-    SPT_HIP(hipMalloc(&p.pl_pos, sizeof(uint16_t) * n1));
-    SPT_HIP(hipMalloc(&p.pl_desc, sizeof(uint32_t) * k1));
-    SPT_HIP(hipMalloc(&p.pl_row, sizeof(uint32_t) * k1));
-    SPT_HIP(hipMalloc(&p.pl_dest, sizeof(uint32_t) * k1));
-    if (pieces == 0) return SPT_OK;
+    p.pl_pos = (uint16_t *)dev_alloc(sizeof(uint16_t) * n1, s);
+    p.pl_desc = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
+    p.pl_row = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
+    p.pl_dest = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
+    if (!p.pl_pos || !p.pl_desc || !p.pl_row || !p.pl_dest) {
+        (void)hipStreamSynchronize(s);  // the host offsets must outlive their copy
+        return fail(SPT_E_OOM, "plan: arrays");
+    }
+    if (pieces == 0) {
+        SPT_HIP(hipStreamSynchronize(s));
+        return SPT_OK;
+    }
     int64_t *pair_off = (int64_t *)dev_alloc(sizeof(int64_t) * (ntiles + 1), s);
     uint32_t *ppair = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
     uint32_t *psub = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
@@ -286,21 +269,30 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     return st;
 }
 
-spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out) {
+// The plan of `mode` for `rank` under the tensor's strategy.  SEGMENT and
+// TABLE plans come from a pass over the nonzeros that synchronises s; they
+// are built only with `build` (spt_tensor_prepare), so an MTTKRP call never
+// synchronises.  The SEGMENT plan holds for every rank; PRIV, DIRECT and
+// REGROUP need only host arithmetic.
+spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out, bool build) {
     ModePlan &p = t->mplan[mode];
     int want = t->plan.strategy[mode];
     const int64_t rows = t->dims[mode];
     int npass = 1, rs = rank, stride = rank + 1;
     if (want == SPT_STRATEGY_AUTO) want = SPT_STRATEGY_SEGMENT;  // measured fastest for every mode size
-    if (p.valid && p.rank == rank && p.strategy == want) {
+    const bool rank_free = want == SPT_STRATEGY_SEGMENT || want == SPT_STRATEGY_DIRECT || want == SPT_STRATEGY_REGROUP;
+    const bool tile_same = want == SPT_STRATEGY_SEGMENT ? p.ts == segment_tile(t, mode)
+                           : (want == SPT_STRATEGY_DIRECT || want == SPT_STRATEGY_REGROUP) ? p.ts == t->plan.tile[mode]
+                                                                                         : true;
+    if (p.valid && p.strategy == want && tile_same && (rank_free || p.rank == rank)) {
         *out = &p;
         return SPT_OK;
     }
-    if (p.rec_off || p.pl_off || p.pl_pos || p.pl_desc || p.pl_row || p.pl_dest) {
-        (void)hipStreamSynchronize(s);  // the previous plan's arrays may still be in use
-        release_mode_plan(t, mode);
-    }
-    p = ModePlan{};
+    const bool device_pass = want == SPT_STRATEGY_SEGMENT || want == SPT_STRATEGY_TABLE;
+    if (device_pass && !build)
+        return fail(SPT_E_INVALID_ARG, "mttkrp: tensor not prepared for mode " + std::to_string(mode) +
+                                           " at rank " + std::to_string(rank) + " (call spt_tensor_prepare)");
+    release_mode_plan(t, mode, s);  // stream-ordered: earlier calls on s still see the old arrays
     p.rank = rank;
     p.strategy = want;
     if (want == SPT_STRATEGY_PRIV) {
@@ -323,8 +315,8 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
         p.sub_per_wg = std::max<int64_t>(1, (nsub + p.nwg - 1) / p.nwg);
         p.nwg = (int)std::max<int64_t>(1, (nsub + p.sub_per_wg - 1) / p.sub_per_wg);
         // counting pass: the same flush decisions as the real kernel, records only counted
-        int64_t *cnt = nullptr;
-        SPT_HIP(hipMalloc(&cnt, sizeof(int64_t) * p.nwg));
+        int64_t *cnt = (int64_t *)dev_alloc(sizeof(int64_t) * p.nwg, s);
+        if (!cnt) return fail(SPT_E_OOM, "plan: record counts");
         TableArgs ta{};
         ta.a = make_args(t, nullptr, rank, mode, nullptr, 0);
         ta.cap = p.cap;
@@ -342,7 +334,8 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
                 st = hip_fail(hipGetLastError(), "plan: record counts");
         }
         if (st != SPT_OK) {
-            (void)hipFree(cnt);
+            dev_free(cnt, s);
+            p = ModePlan{};
             return st;
         }
         int64_t run = 0;
@@ -352,15 +345,17 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
             run += c;
         }
         p.records = run;
-        if (hipMemcpy(cnt, h.data(), sizeof(int64_t) * p.nwg, hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(cnt);
+        if (hipMemcpyAsync(cnt, h.data(), sizeof(int64_t) * p.nwg, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            dev_free(cnt, s);
+            p = ModePlan{};
             return hip_fail(hipGetLastError(), "plan: record offsets");
         }
         p.rec_off = cnt;
     } else if (want == SPT_STRATEGY_SEGMENT) {
         spt_status st = build_segment_plan(t, mode, rank, s, p);
         if (st != SPT_OK) {
-            release_mode_plan(t, mode);
+            release_mode_plan(t, mode, s);
             return st;
         }
     } else {
@@ -368,6 +363,24 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
     }
     p.valid = 1;
     *out = &p;
+    return SPT_OK;
+}
+
+// Every mode's plan for `rank`, and the tile dictionaries when a mode runs
+// the row-cached kernel.
+spt_status prepare_single(Tensor *t, int rank, hipStream_t s) {
+    bool want_dict = false;
+    for (int n = 0; n < t->nmodes; ++n) {
+        ModePlan *p = nullptr;
+        spt_status st = resolve_plan(t, n, rank, s, &p, true);
+        if (st != SPT_OK) return st;
+        want_dict = want_dict || (p->strategy == SPT_STRATEGY_SEGMENT && p->ts == kDictTile);
+    }
+    if (want_dict && t->plan.row_cache != 0)
+        for (int k = 0; k < t->nmodes; ++k) {
+            spt_status st = build_dict_mode(t, k, s, nullptr);
+            if (st != SPT_OK) return st;
+        }
     return SPT_OK;
 }
 
@@ -401,14 +414,11 @@ spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode
         on = g_prof_on;
     }
     if (!on) return run_mttkrp_impl(t, factors, rank, mode, out, s);
-    ModePlan *p = nullptr;
-    spt_status st = resolve_plan(t, mode, rank, s, &p);  // plan building stays outside the timed range
-    if (st != SPT_OK) return st;
     ProfEvent e{mode, nullptr, nullptr};
     SPT_HIP(hipEventCreate(&e.a));
     SPT_HIP(hipEventCreate(&e.b));
     SPT_HIP(hipEventRecord(e.a, s));
-    st = run_mttkrp_impl(t, factors, rank, mode, out, s);
+    spt_status st = run_mttkrp_impl(t, factors, rank, mode, out, s);
     SPT_HIP(hipEventRecord(e.b, s));
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back(e);
@@ -441,13 +451,22 @@ spt_status profile_read(double *ms, int64_t *launches) {
 // Records path shared by SEGMENT and TABLE: the main kernel writes P
 // records (row, R floats) and the reducer sums them per row into out.
 // SEGMENT records come out grouped by row (the plan laid them out); TABLE
-// records are radix-sorted by row first.
+// records are radix-sorted by row first.  The record buffers belong to the
+// call (taken and released in stream order on s).
 spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int64_t rows, float *out, hipStream_t s,
                               bool segment, TableArgs *ta = nullptr, int nwg = 0) {
     const size_t n1 = (size_t)std::max<int64_t>(P, 1);
-    uint64_t *rrow = (uint64_t *)tensor_ws(t, WS_REC_ROW, sizeof(uint64_t) * n1, s);
-    float *rval = (float *)tensor_ws(t, WS_REC_VAL, sizeof(float) * n1 * rank, s);
-    if (!rrow || !rval) return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
+    uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s);
+    float *rval = (float *)dev_alloc(sizeof(float) * n1 * rank, s);
+    uint64_t *keys2 = nullptr;
+    uint32_t *ia = nullptr, *ib = nullptr, *cnt = nullptr;
+    auto release = [&]() {
+        dev_free(rrow, s); dev_free(rval, s); dev_free(keys2, s); dev_free(ia, s); dev_free(ib, s); dev_free(cnt, s);
+    };
+    if (!rrow || !rval) {
+        release();
+        return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
+    }
     spt_status st;
     if (segment) {
         a.rec_row = rrow;
@@ -455,13 +474,17 @@ spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int
         st = launch_mttkrp_seg(a, s);
         if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
         if (st == SPT_OK) st = launch_reduce_records(rrow, nullptr, rval, P, rank, rows, out, s);
+        release();
         return st;
     }
-    uint64_t *keys2 = (uint64_t *)tensor_ws(t, WS_KEYS2, sizeof(uint64_t) * n1, s);
-    uint32_t *ia = (uint32_t *)tensor_ws(t, WS_IDX_A, sizeof(uint32_t) * n1, s);
-    uint32_t *ib = (uint32_t *)tensor_ws(t, WS_IDX_B, sizeof(uint32_t) * n1, s);
-    uint32_t *cnt = (uint32_t *)tensor_ws(t, WS_COUNTS, sizeof(uint32_t) * sort_ws_counts((int64_t)n1), s);
-    if (!keys2 || !ia || !ib || !cnt) return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
+    keys2 = (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s);
+    ia = (uint32_t *)dev_alloc(sizeof(uint32_t) * n1, s);
+    ib = (uint32_t *)dev_alloc(sizeof(uint32_t) * n1, s);
+    cnt = (uint32_t *)dev_alloc(sizeof(uint32_t) * sort_ws_counts((int64_t)n1), s);
+    if (!keys2 || !ia || !ib || !cnt) {
+        release();
+        return fail(SPT_E_OOM, "mttkrp: record workspace allocation failed");
+    }
     ta->rec_row = rrow;
     ta->rec_val = rval;
     st = launch_table(*ta, nwg, s);
@@ -470,13 +493,13 @@ spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int
     if (st == SPT_OK) st = sort_u64_keys_ws(rrow, keys2, ia, ib, cnt, P, t->lbits[a.mode], &srow, &sidx, s);
     if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
     if (st == SPT_OK) st = launch_reduce_records(srow, sidx, rval, P, rank, rows, out, s);
+    release();
     return st;
 }
 
 spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
-    const bool had_plan = t->mplan[mode].valid && t->mplan[mode].rank == rank;
     ModePlan *p = nullptr;
-    spt_status st = resolve_plan(t, mode, rank, s, &p);
+    spt_status st = resolve_plan(t, mode, rank, s, &p, false);
     if (st != SPT_OK) return st;
     const int64_t rows = t->dims[mode];
     if (p->strategy == SPT_STRATEGY_SEGMENT && t->nnz > 0) {
@@ -487,21 +510,13 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
         a.pl_row = p->pl_row;
         a.pl_dest = p->pl_dest;
         a.rec_cap = p->records;
-        // row cache: 4096-nonzero tiles, when the cache holds enough rows
-        // Every non-output mode needs its dictionary.  A mode gets one with its
-        // own plan; missing ones are built here from the second call at this
-        // mode on (a CP-ALS sweep has them all by its last mode).
+        // row cache: 4096-nonzero tiles, when the cache holds enough rows and
+        // every non-output mode has its tile dictionary (spt_tensor_prepare)
         const int cap = p->ts == kDictTile ? dict_cap(t->nmodes, rank) : 0;
         if (cap > 0 && t->plan.row_cache != 0) {
             bool all = true;
-            for (int k = 0; k < t->nmodes; ++k) {
-                if (k == mode) continue;
-                if (!t->dict_slot[k] && had_plan) {
-                    st = build_dict_mode(t, k, s, nullptr);
-                    if (st != SPT_OK) return st;
-                }
-                all = all && t->dict_slot[k] != nullptr;
-            }
+            for (int k = 0; k < t->nmodes; ++k)
+                if (k != mode) all = all && t->dict_slot[k] != nullptr;
             if (all) {
                 for (int o = 0, k = 0; k < t->nmodes; ++k) {
                     if (k == mode) continue;
@@ -515,7 +530,8 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
         }
         return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/true);
     }
-    if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
+    if (t->nnz == 0 || p->strategy == SPT_STRATEGY_SEGMENT || p->strategy == SPT_STRATEGY_DIRECT ||
+        p->strategy == SPT_STRATEGY_REGROUP) {
         st = launch_fill_zero(out, rows * (int64_t)rank, s);
         if (st != SPT_OK || t->nnz == 0) return st;
         return launch_mttkrp(make_args(t, factors, rank, mode, out, std::min(t->plan.tile[mode], 1024)), p->strategy, s);
@@ -529,11 +545,12 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
     ta.ts = p->ts;
     ta.sub_per_wg = p->sub_per_wg;
     if (p->strategy == SPT_STRATEGY_PRIV) {
-        float *part = (float *)tensor_ws(t, WS_PART, sizeof(float) * (size_t)p->nwg * rows * rank, s);
+        float *part = (float *)dev_alloc(sizeof(float) * (size_t)p->nwg * rows * rank, s);
         if (!part) return fail(SPT_E_OOM, "mttkrp: partials allocation failed");
         ta.rec_val = part;
         st = launch_priv(ta, p->nwg, p->npass, s);
         if (st == SPT_OK) st = launch_reduce_priv(part, p->nwg, rows, rank, out, s);
+        dev_free(part, s);
         return st;
     }
     // TABLE

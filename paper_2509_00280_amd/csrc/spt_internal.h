@@ -41,6 +41,9 @@ struct Codec {
     uint32_t run[kMaxRuns];
 };
 
+// The default (ALTO) layout of modes with bit lengths lbits.
+void default_layout(int nmodes, const int *lbits, uint8_t *layout);
+
 // Build the codec of a layout (layout[t] = mode feeding key bit t).
 void make_codec(int nmodes, const int *lbits, const uint8_t *layout, int lp, Codec *c);
 
@@ -77,10 +80,6 @@ struct ModePlan {
     uint32_t *pl_desc = nullptr, *pl_row = nullptr, *pl_dest = nullptr;
 };
 
-// Grow-only device buffers owned by a tensor handle and reused by its MTTKRP
-// calls (records and sort buffers), so steady-state calls allocate nothing.
-enum WsSlot { WS_REC_ROW, WS_REC_VAL, WS_KEYS2, WS_IDX_A, WS_IDX_B, WS_COUNTS, WS_PART, WS_NSLOTS };
-
 struct Tensor {
     int nmodes = 0;
     int64_t nnz = 0;
@@ -99,10 +98,7 @@ struct Tensor {
     ModePlan mplan[kMaxModes];
     // batched SEGMENT plan per mode (tiles of kBatchTile; stream-ordered allocations)
     ModePlan bplan[kMaxModes];
-    void *ws[WS_NSLOTS] = {};
-    size_t ws_bytes[WS_NSLOTS] = {};
-    // tile dictionaries (tiles of kDictTile, built with a mode's SEGMENT plan or
-    // on a row-cached MTTKRP's second call): per mode slot[nnz] u16,
+    // tile dictionaries (tiles of kDictTile, built by spt_tensor_prepare): per mode slot[nnz] u16,
     // row[distinct (tile, row) pairs] u32, off[ntiles + 1]
     uint16_t *dict_slot[kMaxModes] = {};
     uint32_t *dict_row[kMaxModes] = {};
@@ -112,23 +108,22 @@ struct Tensor {
 
 // plan.cpp
 int device_cus();
-spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out);
-// mode-`mode` MTTKRP into out (overwritten), per the tensor's plan
+// plan of `mode` at `rank`; SEGMENT/TABLE plans are built (synchronising s)
+// only when `build` is set, else a missing plan is SPT_E_INVALID_ARG
+spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan **out, bool build);
+// every mode's plan at `rank` and the tile dictionaries (synchronises s)
+spt_status prepare_single(Tensor *t, int rank, hipStream_t s);
+// mode-`mode` MTTKRP into out (overwritten), per the tensor's prepared plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
-void release_plans(Tensor *t);
-// drop the tile dictionaries (after the tensor's last use)
-void release_dict(Tensor *t);
-// release a handle after its last use on stream s (stream-ordered frees)
+// The release functions free in stream order on s (after the work already
+// ordered on s); none synchronises.
+void release_plans(Tensor *t, hipStream_t s);
+void release_dict(Tensor *t, hipStream_t s);
 void tensor_release(Tensor *t, hipStream_t s);
-// drop the cached plan of one mode (the next call at that mode plans again)
-void release_mode_plan(Tensor *t, int mode);
-// drop a batched plan (stream-ordered frees on s)
+void release_mode_plan(Tensor *t, int mode, hipStream_t s);
 void release_batch_plan(Tensor *t, int mode, hipStream_t s);
 bool seg_tile_ok(int tile, int nmodes);
 bool priv_feasible(const Tensor *t, int mode, int rank);
-// workspace slot of at least `bytes` (synchronises s before replacing a smaller buffer)
-void *tensor_ws(Tensor *t, int slot, size_t bytes, hipStream_t s);
-void release_ws(Tensor *t);
 spt_status profile_enable(int on);
 spt_status profile_read(double *ms, int64_t *launches);
 
@@ -303,29 +298,23 @@ struct ModeItems {
     std::vector<ApplyItem> ap_v;
 };
 
-// Grow-only device buffer (synchronises the stream before replacing).
+// Grow-only device buffer; a smaller buffer is released in stream order on
+// the stream that asks for a larger one (no synchronisation).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     void *get(size_t need, hipStream_t s) {
         if (need <= bytes && p) return p;
-        if (p) {
-            (void)hipStreamSynchronize(s);
-            (void)hipFree(p);
-            p = nullptr;
-            bytes = 0;
-        }
+        dev_free(p, s);
+        p = nullptr;
+        bytes = 0;
         need = need < 256 ? 256 : need;
-        if (hipMalloc(&p, need) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return nullptr;
-        }
-        bytes = need;
+        p = dev_alloc(need, s);
+        if (p) bytes = need;
         return p;
     }
-    void release() {
-        if (p) (void)hipFree(p);
+    void release(hipStream_t s) {
+        dev_free(p, s);
         p = nullptr;
         bytes = 0;
     }
@@ -333,15 +322,20 @@ struct DevBuf {
 
 // record and sort buffers of the batched MTTKRP
 struct BatchMttkrpWs {
-    DevBuf rec_row, rec_val, keys2, ia, ib, cnt;
-    void release() {
-        rec_row.release(); rec_val.release(); keys2.release(); ia.release(); ib.release(); cnt.release();
+    DevBuf rec_row, rec_val;
+    void release(hipStream_t s) {
+        rec_row.release(s);
+        rec_val.release(s);
     }
 };
 spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_min, int nmodes_max,
                                    int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
                                    BatchMttkrpWs &ws, hipStream_t s);
 spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s);
+// every mode's batched plan of one tensor (synchronises s)
+spt_status prepare_batched(Tensor *t, hipStream_t s);
+// host-to-device copy through a pinned staging ring (asynchronous)
+spt_status upload_staged(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 class BatchEngine {
 public:
@@ -368,15 +362,15 @@ private:
     int nmodes_max_ = 0, nmodes_min_ = 0;
     std::vector<ModeItems> modes_;
     char *d_items_ = nullptr;
-    size_t items_bytes_ = 0, fit_off_ = 0, init_off_ = 0;
+    size_t fit_off_ = 0, init_off_ = 0;
     int init_count_ = 0, init_rmax_ = 0;
     int64_t init_slices_ = 0;
     DevBuf gram_ws_;  // partial Grams of the batched Gram launches
+    DevBuf items_buf_, M_buf_, fit_buf_, status_buf_, inner_buf_, resid_buf_;
+    std::vector<char> blob_;  // host image of the item arrays (kept until the next upload)
     float *M_all_ = nullptr;
-    size_t M_bytes_ = 0;
     double *fit_all_ = nullptr, *inner_all_ = nullptr, *resid_ = nullptr;
     int *status_all_ = nullptr;
-    size_t fit_cap_ = 0, inner_cap_ = 0, resid_cap_ = 0;
     std::vector<double> hfit_;
     std::vector<int> hstat_;
     BatchMttkrpWs ws_;

@@ -3,13 +3,23 @@
 //
 // The search space is the paper's (Section III-C, Eq. (1)): one bit layout per
 // tensor, i.e. an interleaving in which mode n fills exactly l(n) key bits,
-// low bits of each coordinate first.  The paper learns the layout with a
-// reinforcement-learning agent; here a hill climb seeded at the default
-// (ALTO) interleaving replaces the agent: a move exchanges two adjacent key
-// bits that come from different modes, which keeps every mode's bit count, so
-// every candidate is a valid interleaving.  The objective is the measured
-// all-mode MTTKRP time, each mode at its best plan (strategy and tile).
-// Measurements are cached per (mode lengths, nnz, rank, layout).
+// low bits of each coordinate first; Eq. (1) counts these interleavings as the
+// multinomial coefficient l(p)! / prod_n l(n)!.  The reward is the paper's:
+// the all-mode MTTKRP time of a layout relative to the default (ALTO)
+// interleaving (Section III-C, reward function).  The paper learns the layout
+// with a reinforcement-learning agent; here the agent is replaced by a
+// measured search:
+//   1. the layout the tensor has, and the ALTO layout (the reward baseline);
+//   2. seeded uniform samples of the interleaving space (a uniformly shuffled
+//      multiset of mode ids, which gives every distinct interleaving the same
+//      probability);
+//   3. a hill climb from the best layout so far: a move exchanges two
+//      adjacent key bits of different modes, which keeps every mode's bit
+//      count, so every candidate is a valid interleaving.
+// A layout is measured with each mode at its best plan (strategy and tile).
+// Measurements are cached per (mode lengths, nnz, rank, layout, content
+// fingerprint), the fingerprint taken from the encoded tensor's first and last
+// keys and values and its norm.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,8 +44,10 @@ struct CacheKey {
     int64_t nnz;
     int rank;
     std::vector<uint8_t> layout;
+    uint64_t fingerprint;
     bool operator<(const CacheKey &o) const {
-        return std::tie(dims, nnz, rank, layout) < std::tie(o.dims, o.nnz, o.rank, o.layout);
+        return std::tie(dims, nnz, rank, layout, fingerprint) <
+               std::tie(o.dims, o.nnz, o.rank, o.layout, o.fingerprint);
     }
 };
 
@@ -47,21 +59,43 @@ struct CacheEntry {
 std::mutex g_cache_mu;
 std::map<CacheKey, CacheEntry> g_cache;
 
-CacheKey key_of(const Tensor *t, int rank) {
-    CacheKey k;
-    k.dims.assign(t->dims, t->dims + t->nmodes);
-    k.nnz = t->nnz;
-    k.rank = rank;
-    k.layout.assign(t->layout, t->layout + t->lp);
-    return k;
-}
-
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// ms per call of mode-`mode` MTTKRP under the tensor's current plan: one call
-// to plan and warm up, then `reps` calls between two events.
+uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// Content fingerprint of an encoded tensor: its first and last (up to) 512
+// keys and values and its norm.  Two tensors of one shape and nnz but other
+// nonzeros differ here with overwhelming probability.  Synchronises s.
+spt_status fingerprint(const Tensor *t, hipStream_t s, uint64_t *out) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    h = fnv1a(h, &t->norm_x2, sizeof(double));
+    const int64_t k = std::min<int64_t>(t->nnz, 512);
+    if (k > 0) {
+        std::vector<uint64_t> keys(2 * k);
+        std::vector<float> vals(2 * k);
+        SPT_HIP(hipMemcpyAsync(keys.data(), t->lo, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
+        SPT_HIP(hipMemcpyAsync(keys.data() + k, t->lo + (t->nnz - k), sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
+        SPT_HIP(hipMemcpyAsync(vals.data(), t->vals, sizeof(float) * k, hipMemcpyDeviceToHost, s));
+        SPT_HIP(hipMemcpyAsync(vals.data() + k, t->vals + (t->nnz - k), sizeof(float) * k, hipMemcpyDeviceToHost, s));
+        SPT_HIP(hipStreamSynchronize(s));
+        h = fnv1a(h, keys.data(), sizeof(uint64_t) * keys.size());
+        h = fnv1a(h, vals.data(), sizeof(float) * vals.size());
+    }
+    *out = h;
+    return SPT_OK;
+}
+
+// ms per call of mode-`mode` MTTKRP under the tensor's current (prepared)
+// plan: one warm-up call, then `reps` calls between two events.
 spt_status time_mode(Tensor *t, const float *const *F, int R, int mode, float *out, int reps, hipStream_t s,
                      double *ms) {
     spt_status st = run_mttkrp(t, F, R, mode, out, s);
@@ -85,21 +119,40 @@ spt_status time_mode(Tensor *t, const float *const *F, int R, int mode, float *o
 }
 
 // Best plan of every mode for the tensor's current layout; returns the
-// all-mode time.  Leaves t->plan at the winner.
+// all-mode time.  Leaves t->plan at the winner (prepared).
 spt_status tune_plan(Tensor *t, const float *const *F, int R, float *out, hipStream_t s, spt_plan *best_plan,
-                     double *best_ms) {
+                     double *best_ms, bool *cached) {
+    CacheKey key;
+    key.dims.assign(t->dims, t->dims + t->nmodes);
+    key.nnz = t->nnz;
+    key.rank = R;
+    key.layout.assign(t->layout, t->layout + t->lp);
+    spt_status st = fingerprint(t, s, &key.fingerprint);
+    if (st != SPT_OK) return st;
+    *cached = false;
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_cache.find(key_of(t, R));
+        auto it = g_cache.find(key);
         if (it != g_cache.end()) {
             *best_plan = it->second.plan;
             *best_ms = it->second.ms;
-            t->plan = *best_plan;
-            release_plans(t);
-            return SPT_OK;
+            *cached = true;
         }
     }
-    const int reps = t->nnz > 20'000'000 ? 2 : 4;
+    if (*cached) {
+        for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n, s);
+        t->plan = *best_plan;
+        return prepare_single(t, R, s);
+    }
+    const int reps = t->nnz > 20'000'000 ? 3 : 5;
+    // tile dictionaries for the row-cached candidates (built once per encoding)
+    for (int n = 0; n < t->nmodes; ++n) {
+        t->plan.strategy[n] = SPT_STRATEGY_SEGMENT;
+        t->plan.tile[n] = 4096;
+    }
+    for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n, s);
+    st = prepare_single(t, R, s);
+    if (st != SPT_OK) return st;
     spt_plan plan = t->plan;
     double total = 0.0;
     for (int n = 0; n < t->nmodes; ++n) {
@@ -107,7 +160,7 @@ spt_status tune_plan(Tensor *t, const float *const *F, int R, float *out, hipStr
             int strategy, tile;
         };
         std::vector<Cand> cands;
-        for (int tile : {1024, 2048, 4096})
+        for (int tile : {4096, 2048, 1024})
             if (seg_tile_ok(tile, t->nmodes)) cands.push_back({SPT_STRATEGY_SEGMENT, tile});
         if (priv_feasible(t, n, R)) cands.push_back({SPT_STRATEGY_PRIV, 2048});
         double best = 1e300;
@@ -115,9 +168,10 @@ spt_status tune_plan(Tensor *t, const float *const *F, int R, float *out, hipStr
         for (const Cand &c : cands) {
             t->plan.strategy[n] = c.strategy;
             t->plan.tile[n] = c.tile;
-            release_mode_plan(t, n);
+            ModePlan *p = nullptr;
+            st = resolve_plan(t, n, R, s, &p, true);
             double ms = 0.0;
-            spt_status st = time_mode(t, F, R, n, out, reps, s, &ms);
+            if (st == SPT_OK) st = time_mode(t, F, R, n, out, reps, s, &ms);
             if (st != SPT_OK) return st;
             if (ms < best) {
                 best = ms;
@@ -128,13 +182,15 @@ spt_status tune_plan(Tensor *t, const float *const *F, int R, float *out, hipStr
         plan.tile[n] = win.tile;
         t->plan.strategy[n] = win.strategy;
         t->plan.tile[n] = win.tile;
-        release_mode_plan(t, n);
+        ModePlan *p = nullptr;
+        st = resolve_plan(t, n, R, s, &p, true);
+        if (st != SPT_OK) return st;
         total += best;
     }
     *best_plan = plan;
     *best_ms = total;
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache[key_of(t, R)] = CacheEntry{plan, total};
+    g_cache[key] = CacheEntry{plan, total};
     return SPT_OK;
 }
 
@@ -146,125 +202,145 @@ using namespace spt;
 
 extern "C" {
 
-spt_status spt_autotune(spt_tensor *tp, const float *const *factors, int rank, double budget_ms, double *best_ms_out,
-                        void *stream) {
-    if (!tp || !*tp || !best_ms_out) return fail(SPT_E_INVALID_ARG, "autotune: NULL argument");
+spt_status spt_autotune(spt_tensor *tp, const float *const *factors, int rank, double budget_ms, int random_samples,
+                        uint64_t seed, spt_tune_result *res, void *stream) {
+    if (!tp || !*tp || !res) return fail(SPT_E_INVALID_ARG, "autotune: NULL argument");
     Tensor *t = *tp;
     if (rank < 1 || rank > SPT_MAX_RANK) return fail(SPT_E_INVALID_ARG, "autotune: rank out of range");
+    if (random_samples < 0) return fail(SPT_E_INVALID_ARG, "autotune: random_samples < 0");
     spt_status st = check_factors(t, factors, rank, -1);
     if (st != SPT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const double t_start = now_ms();
     int64_t maxI = 1;
     for (int n = 0; n < t->nmodes; ++n) maxI = std::max(maxI, t->dims[n]);
-    float *out = nullptr;
-    SPT_HIP(hipMalloc(&out, sizeof(float) * maxI * rank));
+    const int lp = t->lp;
+    float *out = (float *)dev_alloc(sizeof(float) * maxI * rank, s);
     uint32_t *coords = nullptr;
     auto cleanup = [&]() {
-        (void)hipStreamSynchronize(s);
-        if (out) (void)hipFree(out);
-        if (coords) (void)hipFree(coords);
+        dev_free(out, s);
+        dev_free(coords, s);
     };
-    spt_plan best_plan{};
-    double best = 0.0;
-    st = tune_plan(t, factors, rank, out, s, &best_plan, &best);
+    if (!out) return fail(SPT_E_OOM, "autotune: output buffer");
+    spt_tune_result r{};
+    // candidates other than the tensor's own layout are encoded from its
+    // decoded coordinates (key order) and its values
+    auto measure = [&](const std::vector<uint8_t> &lay, spt_plan *plan, double *ms) -> spt_status {
+        bool cached = false;
+        if (std::memcmp(lay.data(), t->layout, lp) == 0) {
+            st = tune_plan(t, factors, rank, out, s, plan, ms, &cached);
+        } else {
+            if (!coords) {
+                coords = (uint32_t *)dev_alloc(sizeof(uint32_t) * (size_t)t->nmodes * std::max<int64_t>(t->nnz, 1), s);
+                if (!coords) return fail(SPT_E_OOM, "autotune: coordinate buffer");
+                spt_status d = launch_decode(t, coords, s);
+                if (d != SPT_OK) return d;
+            }
+            spt_tensor c = nullptr;
+            st = spt_encode(t->dims, t->nmodes, coords, t->vals, t->nnz, lay.data(), lp, s, &c);
+            if (st != SPT_OK) return st;
+            st = tune_plan(c, factors, rank, out, s, plan, ms, &cached);
+            tensor_release(c, s);
+        }
+        ++r.candidates;
+        r.cache_hits += cached ? 1 : 0;
+        return st;
+    };
+    std::vector<uint8_t> start(t->layout, t->layout + lp), alto(lp);
+    default_layout(t->nmodes, t->lbits, alto.data());
+    spt_plan best_plan{}, p{};
+    double best = 0.0, ms = 0.0;
+    st = measure(start, &best_plan, &best);
     if (st != SPT_OK) {
         cleanup();
         return st;
     }
-    std::vector<uint8_t> best_layout(t->layout, t->layout + t->lp);
-    const int lp = t->lp;
-    // layout moves need the coordinates: decode once (key order; the values are t->vals)
-    bool moves = lp >= 2 && t->nnz > 0 && t->nmodes >= 2;
-    if (moves && now_ms() - t_start < budget_ms) {
-        if (hipMalloc(&coords, sizeof(uint32_t) * (size_t)t->nmodes * t->nnz) != hipSuccess) {
-            (void)hipGetLastError();
-            cleanup();
-            return fail(SPT_E_OOM, "autotune: coordinate buffer");
+    std::vector<uint8_t> best_layout = start;
+    r.start_ms = best;
+    r.alto_ms = best;
+    auto consider = [&](const std::vector<uint8_t> &lay) -> spt_status {
+        spt_status e = measure(lay, &p, &ms);
+        if (e != SPT_OK) return e;
+        if (ms < best) {
+            best = ms;
+            best_layout = lay;
+            best_plan = p;
         }
-        st = launch_decode(t, coords, s);
-        if (st != SPT_OK) {
-            cleanup();
-            return st;
-        }
-        std::mt19937_64 rng(0x5eed ^ (uint64_t)t->nnz ^ ((uint64_t)lp << 40));
-        std::vector<uint8_t> cur = best_layout;
-        int stale = 0;
-        while (now_ms() - t_start < budget_ms && stale < 3) {
-            // up to four distinct adjacent exchanges of the current layout
-            std::vector<int> pos;
-            for (int i = 0; i + 1 < lp; ++i)
-                if (cur[i] != cur[i + 1]) pos.push_back(i);
-            if (pos.empty()) break;
-            std::shuffle(pos.begin(), pos.end(), rng);
-            pos.resize(std::min<size_t>(pos.size(), 4));
-            bool improved = false;
-            std::vector<uint8_t> round_best;
-            double round_ms = best;
-            spt_plan round_plan{};
-            for (int i : pos) {
-                if (now_ms() - t_start >= budget_ms) break;
-                std::vector<uint8_t> cand = cur;
-                std::swap(cand[i], cand[i + 1]);
-                spt_tensor c = nullptr;
-                st = spt_encode(t->dims, t->nmodes, coords, t->vals, t->nnz, cand.data(), lp, s, &c);
-                if (st != SPT_OK) {
-                    cleanup();
-                    return st;
-                }
-                spt_plan p{};
-                double ms = 0.0;
-                st = tune_plan(c, factors, rank, out, s, &p, &ms);
-                spt_tensor_free(c);
-                if (st != SPT_OK) {
-                    cleanup();
-                    return st;
-                }
-                if (ms < round_ms) {
-                    round_ms = ms;
-                    round_best = cand;
-                    round_plan = p;
-                }
+        return SPT_OK;
+    };
+    if (alto != start) {
+        st = measure(alto, &p, &ms);
+        if (st == SPT_OK) {
+            r.alto_ms = ms;
+            if (ms < best) {
+                best = ms;
+                best_layout = alto;
+                best_plan = p;
             }
-            if (!round_best.empty() && round_ms < 0.99 * best) {
-                best = round_ms;
-                best_layout = round_best;
-                best_plan = round_plan;
-                cur = round_best;
-                improved = true;
-            }
-            stale = improved ? 0 : stale + 1;
         }
     }
-    if (std::memcmp(best_layout.data(), t->layout, lp) != 0) {
+    const bool moves = lp >= 2 && t->nnz > 0 && t->nmodes >= 2;
+    std::mt19937_64 rng(seed);
+    // uniform samples of the interleaving space
+    for (int i = 0; st == SPT_OK && moves && i < random_samples && now_ms() - t_start < budget_ms; ++i) {
+        std::vector<uint8_t> lay = start;
+        std::shuffle(lay.begin(), lay.end(), rng);
+        ++r.random_samples;
+        st = consider(lay);
+    }
+    // hill climb from the best layout so far
+    int stale = 0;
+    std::vector<uint8_t> cur = best_layout;
+    while (st == SPT_OK && moves && now_ms() - t_start < budget_ms && stale < 3) {
+        std::vector<int> pos;
+        for (int i = 0; i + 1 < lp; ++i)
+            if (cur[i] != cur[i + 1]) pos.push_back(i);
+        if (pos.empty()) break;
+        std::shuffle(pos.begin(), pos.end(), rng);
+        pos.resize(std::min<size_t>(pos.size(), 4));
+        const double before = best;
+        for (int i : pos) {
+            if (now_ms() - t_start >= budget_ms) break;
+            std::vector<uint8_t> cand = cur;
+            std::swap(cand[i], cand[i + 1]);
+            st = consider(cand);
+            if (st != SPT_OK) break;
+        }
+        if (best < 0.99 * before) {
+            cur = best_layout;
+            stale = 0;
+        } else {
+            ++stale;
+        }
+    }
+    if (st == SPT_OK && std::memcmp(best_layout.data(), t->layout, lp) != 0) {
         // re-encode in place with the winning layout; perm keeps naming the
         // caller's input order: perm_new = perm_old[perm_rel]
         spt_tensor c = nullptr;
         st = spt_encode(t->dims, t->nmodes, coords, t->vals, t->nnz, best_layout.data(), lp, s, &c);
         uint32_t *perm = nullptr;
-        if (st == SPT_OK && hipMalloc(&perm, sizeof(uint32_t) * std::max<int64_t>(t->nnz, 1)) != hipSuccess) {
-            (void)hipGetLastError();
+        if (st == SPT_OK && !(perm = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max<int64_t>(t->nnz, 1), s)))
             st = fail(SPT_E_OOM, "autotune: perm");
-        }
         if (st == SPT_OK) st = launch_gather_u32(t->perm, c->perm, perm, t->nnz, s);
         if (st == SPT_OK && hipMemcpyAsync(c->perm, perm, sizeof(uint32_t) * t->nnz, hipMemcpyDeviceToDevice, s) != hipSuccess)
             st = hip_fail(hipGetLastError(), "autotune: perm copy");
-        if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "autotune: sync");
-        if (perm) (void)hipFree(perm);
-        if (st != SPT_OK) {
-            if (c) spt_tensor_free(c);
-            cleanup();
-            return st;
+        dev_free(perm, s);
+        if (st == SPT_OK) {
+            std::swap(*static_cast<Tensor *>(t), *static_cast<Tensor *>(c));
+            tensor_release(c, s);  // the old encoding, after the copies above
+        } else if (c) {
+            tensor_release(c, s);
         }
-        release_plans(t);
-        release_ws(t);
-        std::swap(*static_cast<Tensor *>(t), *static_cast<Tensor *>(c));
-        spt_tensor_free(c);  // the old encoding
     }
-    t->plan = best_plan;
-    release_plans(t);
+    if (st == SPT_OK) {
+        for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n, s);
+        t->plan = best_plan;
+        st = prepare_single(t, rank, s);  // the winner is left prepared
+    }
     cleanup();
-    *best_ms_out = best;
+    if (st != SPT_OK) return st;
+    r.best_ms = best;
+    *res = r;
     return SPT_OK;
 }
 

@@ -42,6 +42,19 @@ class Plan(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int * MAX_MODES), ("strategy", ctypes.c_int * MAX_MODES), ("row_cache", ctypes.c_int)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best_ms", ctypes.c_double), ("alto_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int), ("random_samples", ctypes.c_int), ("cache_hits", ctypes.c_int),
+                ("pad", ctypes.c_int)]
+
+
+PREPARE_SINGLE = 1
+PREPARE_BATCHED = 2
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Request(ctypes.Structure):
     _fields_ = [("nmodes", ctypes.c_int), ("dims", ctypes.c_int64 * MAX_MODES), ("nnz", ctypes.c_int64),
                 ("coords", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("init", ctypes.POINTER(ctypes.c_void_p)),
@@ -83,14 +96,18 @@ def lib():
     _sig(L, "spt_tensor_export", st, [_VP, _VP, _VP, _VP, _VP])
     _sig(L, "spt_tensor_decode", st, [_VP, _VP, _VP])
     _sig(L, "spt_tensor_get_plan", st, [_VP, ctypes.POINTER(Plan)])
-    _sig(L, "spt_tensor_set_plan", st, [_VP, ctypes.POINTER(Plan)])
-    _sig(L, "spt_tensor_free", None, [_VP])
+    _sig(L, "spt_tensor_set_plan", st, [_VP, ctypes.POINTER(Plan), _VP])
+    _sig(L, "spt_tensor_prepare", st, [_VP, i, i, _VP])
+    _sig(L, "spt_tensor_free", None, [_VP, _VP])
+    _sig(L, "spt_set_allocator", st, [ALLOC_FN, RELEASE_FN, _VP])
     _sig(L, "spt_mttkrp", st, [_VP, _PP, i, i, _VP, _VP])
     _sig(L, "spt_cp_als", st, [_VP, i, i, d, _PP, _VP, ctypes.POINTER(d), ctypes.POINTER(i), _VP])
+    _sig(L, "spt_als_update", st, [_VP, i, i, i, _VP, i64, _VP, _VP, ctypes.POINTER(i), _VP])
     _sig(L, "spt_mttkrp_batched", st, [_PP, i, ctypes.POINTER(_PP), ctypes.POINTER(i), i, _PP, _VP])
     _sig(L, "spt_cp_als_batched", st, [_PP, i, ctypes.POINTER(i), i, d, ctypes.POINTER(_PP), _PP,
                                        ctypes.POINTER(d), ctypes.POINTER(i), _VP])
-    _sig(L, "spt_autotune", st, [ctypes.POINTER(_VP), _PP, i, d, ctypes.POINTER(d), _VP])
+    _sig(L, "spt_autotune", st, [ctypes.POINTER(_VP), _PP, i, d, i, ctypes.c_uint64, ctypes.POINTER(TuneResult),
+                                 _VP])
     _sig(L, "spt_server_create", st, [ctypes.c_size_t, i, ctypes.POINTER(_VP)])
     _sig(L, "spt_server_submit", st, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
     _sig(L, "spt_server_wait", st, [_VP, ctypes.c_uint64, d, ctypes.POINTER(Result), _PP, _VP])
@@ -122,11 +139,117 @@ def _ptr_array(tensors):
     return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() if t is not None else 0 for t in tensors])
 
 
+# ---------------------------------------------------------------- argument checks
+# The C side sees only pointers, so the binding checks what it can before a
+# call: dtype, shape, one rank for every factor, contiguity and the device.
+# A mismatch raises ValueError and nothing reaches the library.
+
+def _is_torch(x) -> bool:
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(x, torch.Tensor)
+
+
+def check_matrix(name: str, x, rows, cols, dtype: str = "float32", device: str = "cuda"):
+    """A row-major (rows, cols) tensor of ``dtype`` on ``device`` (rows/cols None: any)."""
+    if not _is_torch(x):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(x).__name__}")
+    if str(x.dtype) != f"torch.{dtype}":
+        raise ValueError(f"{name}: dtype must be {dtype}, got {x.dtype}")
+    if x.dim() != 2 or (rows is not None and int(x.shape[0]) != int(rows)) or (
+            cols is not None and int(x.shape[1]) != int(cols)):
+        raise ValueError(f"{name}: shape must be ({rows}, {cols}), got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous (row-major)")
+    if device == "cuda" and not x.is_cuda:
+        raise ValueError(f"{name}: must be a CUDA tensor")
+    return x
+
+
+def check_vector(name: str, x, n, dtype: str, device: str = "cuda"):
+    if not _is_torch(x):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(x).__name__}")
+    if str(x.dtype) != f"torch.{dtype}":
+        raise ValueError(f"{name}: dtype must be {dtype}, got {x.dtype}")
+    if x.dim() != 1 or (n is not None and int(x.shape[0]) != int(n)):
+        raise ValueError(f"{name}: shape must be ({n},), got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if device == "cuda" and not x.is_cuda:
+        raise ValueError(f"{name}: must be a CUDA tensor")
+    return x
+
+
+def check_factors(factors, dims, skip_mode=None, device: str = "cuda") -> int:
+    """Every factor k != skip_mode is float32 (dims[k], R), one R for all; returns R."""
+    if len(factors) != len(dims):
+        raise ValueError(f"factors: expected {len(dims)} matrices, got {len(factors)}")
+    R = None
+    for k, f in enumerate(factors):
+        if f is None:
+            if k == skip_mode:
+                continue
+            raise ValueError(f"factor {k} is None")
+        if not _is_torch(f) or f.dim() != 2:
+            raise ValueError(f"factor {k}: expected a 2-D torch tensor")
+        if R is None:
+            R = int(f.shape[1])
+        check_matrix(f"factor {k}", f, dims[k], R, device="any")
+    if R is None or R < 1:
+        raise ValueError("factors: no rank")
+    for k, f in enumerate(factors):  # the device last, once every shape is known good
+        if f is not None and device == "cuda" and not f.is_cuda:
+            raise ValueError(f"factor {k}: must be a CUDA tensor")
+    return R
+
+
+def check_coo(coords, vals, nmodes: int, device: str = "cuda") -> int:
+    """coords int32/uint32 (nmodes, nnz), vals float32 (nnz,); returns nnz."""
+    if not _is_torch(coords) or str(coords.dtype) not in ("torch.int32", "torch.uint32"):
+        raise ValueError("coords: expected an int32 or uint32 torch tensor")
+    if coords.dim() != 2 or int(coords.shape[0]) != nmodes:
+        raise ValueError(f"coords: shape must be ({nmodes}, nnz), got {tuple(coords.shape)}")
+    nnz = int(coords.shape[1])
+    check_vector("vals", vals, nnz, "float32", device)
+    if not coords.is_contiguous():
+        raise ValueError("coords: must be contiguous")
+    if device == "cuda" and not coords.is_cuda:
+        raise ValueError("coords: must be a CUDA tensor")
+    return nnz
+
+
+def check_request(dims, coords, vals, init):
+    """Host arrays of a server request: coords (nmodes, nnz), vals (nnz,),
+    init[k] (dims[k], rank) with one rank.  Returns the converted arrays and rank."""
+    nm = len(dims)
+    if not 1 <= nm <= MAX_MODES:
+        raise ValueError(f"nmodes must be in 1..{MAX_MODES}")
+    coords = np.ascontiguousarray(coords)
+    if coords.dtype not in (np.uint32, np.int32) or coords.ndim != 2 or coords.shape[0] != nm:
+        raise ValueError(f"coords: expected int32/uint32 of shape ({nm}, nnz), got {coords.dtype} {coords.shape}")
+    coords = coords.view(np.uint32)
+    vals = np.ascontiguousarray(vals)
+    if vals.dtype != np.float32 or vals.shape != (coords.shape[1],):
+        raise ValueError(f"vals: expected float32 of shape ({coords.shape[1]},), got {vals.dtype} {vals.shape}")
+    if len(init) != nm:
+        raise ValueError(f"init: expected {nm} matrices, got {len(init)}")
+    init = [np.ascontiguousarray(f) for f in init]
+    rank = int(init[0].shape[1]) if init[0].ndim == 2 else 0
+    for k, f in enumerate(init):
+        if f.dtype != np.float32 or f.shape != (int(dims[k]), rank):
+            raise ValueError(f"init {k}: expected float32 of shape ({int(dims[k])}, {rank}), got {f.dtype} {f.shape}")
+    return coords, vals, init, rank
+
+
 class Tensor:
     """An encoded sparse tensor living on the GPU (owns an spt_tensor handle)."""
 
     def __init__(self, handle: ctypes.c_void_p):
         self._h = handle
+        self._prepared_rank = None   # rank of the last SPT_PREPARE_SINGLE
+        self._batched = False        # SPT_PREPARE_BATCHED done
 
     @property
     def handle(self):
@@ -180,11 +303,25 @@ class Tensor:
                     strategy if isinstance(strategy, int) else p.strategy[n])
         if row_cache is not None:
             p.row_cache = 1 if row_cache else 0
-        _check(lib().spt_tensor_set_plan(self._h, ctypes.byref(p)))
+        _check(lib().spt_tensor_set_plan(self._h, ctypes.byref(p), _stream(None)))
+        self._prepared_rank = None
 
-    def free(self):
+    def prepare(self, rank: int, batched: bool = False, stream=None):
+        """Build the per-mode MTTKRP state (plans, tile dictionaries) for ``rank``."""
+        what = PREPARE_BATCHED if batched else PREPARE_SINGLE
+        _check(lib().spt_tensor_prepare(self._h, int(rank), what, _stream(stream)))
+        if batched:
+            self._batched = True
+        else:
+            self._prepared_rank = int(rank)
+
+    def ensure_prepared(self, rank: int, stream=None):
+        if self._prepared_rank != int(rank):
+            self.prepare(rank, stream=stream)
+
+    def free(self, stream=None):
         if self._h is not None and self._h.value:
-            lib().spt_tensor_free(self._h)
+            lib().spt_tensor_free(self._h, _stream(stream))
         self._h = None
 
     def __del__(self):
@@ -201,8 +338,8 @@ def encode(dims, coords, vals, layout=None, stream=None) -> Tensor:
     vals:   torch CUDA float32 tensor of shape (nnz,).
     """
     nm = len(dims)
+    nnz = check_coo(coords, vals, nm)
     d = (ctypes.c_int64 * nm)(*[int(x) for x in dims])
-    nnz = int(vals.numel())
     lay = None
     lay_len = 0
     if layout is not None:
@@ -218,11 +355,14 @@ def encode(dims, coords, vals, layout=None, stream=None) -> Tensor:
 def mttkrp(t: Tensor, factors, mode: int, out=None, stream=None):
     """out[I_mode, R] = MTTKRP of mode ``mode`` (factors: list of CUDA float32 [I_k, R])."""
     import torch
-    R = int(factors[0].shape[1] if factors[0] is not None else factors[1].shape[1])
+    dims = t.info()["dims"]
+    R = check_factors(factors, dims, skip_mode=mode)
+    rows = dims[mode] if 0 <= mode < len(dims) else 1  # an invalid mode is rejected by the library
     if out is None:
-        dims = t.info()["dims"]
-        rows = dims[mode] if 0 <= mode < len(dims) else 1  # an invalid mode is rejected by the library
         out = torch.empty((rows, R), dtype=torch.float32, device="cuda")
+    elif 0 <= mode < len(dims):
+        check_matrix("out", out, rows, R)
+    t.ensure_prepared(R, stream)
     _check(lib().spt_mttkrp(t.handle, _ptr_array(factors), R, int(mode), _ptr(out), _stream(stream)))
     return out
 
@@ -230,18 +370,56 @@ def mttkrp(t: Tensor, factors, mode: int, out=None, stream=None):
 def cp_als(t: Tensor, factors, iters: int, tol: float = 0.0, lam=None, stream=None):
     """Run CP-ALS in place on ``factors``; returns (lambda tensor, fit, iterations)."""
     import torch
-    R = int(factors[0].shape[1])
+    R = check_factors(factors, t.info()["dims"])
     if lam is None:
         lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    check_vector("lambda", lam, R, "float64")
     fit = ctypes.c_double()
     its = ctypes.c_int()
     _check(lib().spt_cp_als(t.handle, R, int(iters), float(tol), _ptr_array(factors), _ptr(lam),
                             ctypes.byref(fit), ctypes.byref(its), _stream(stream)))
+    t._prepared_rank = R  # cp_als prepares the tensor for its rank
     return lam, fit.value, its.value
+
+
+def als_update(grams, mode: int, M, C=None, lam=None, stream=None):
+    """One ALS mode update (FP64 solve with ridge retry) of a dense M.
+
+    grams: CUDA float64 (nmodes, R, R); M: CUDA float32 (rows, R).
+    Returns (C, lam, ridge retries)."""
+    import torch
+    if not _is_torch(grams) or str(grams.dtype) != "torch.float64" or grams.dim() != 3 or \
+            grams.shape[1] != grams.shape[2] or not grams.is_contiguous() or not grams.is_cuda:
+        raise ValueError("grams: expected a contiguous CUDA float64 tensor of shape (nmodes, R, R)")
+    nm, R = int(grams.shape[0]), int(grams.shape[1])
+    check_matrix("M", M, None, R)
+    rows = int(M.shape[0])
+    if C is not None:
+        check_matrix("C", C, rows, R)
+    if lam is not None:
+        check_vector("lambda", lam, R, "float64")
+    if C is None:
+        C = torch.empty((rows, R), dtype=torch.float32, device="cuda")
+    if lam is None:
+        lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    retries = ctypes.c_int()
+    _check(lib().spt_als_update(_ptr(grams), nm, int(mode), R, _ptr(M), rows, _ptr(C), _ptr(lam),
+                                ctypes.byref(retries), _stream(stream)))
+    return C, lam, retries.value
 
 
 def mttkrp_batched(tensors, factor_lists, mode: int, outs, stream=None):
     count = len(tensors)
+    if len(factor_lists) != count or len(outs) != count:
+        raise ValueError("tensors, factor_lists and outs must have one entry per tensor")
+    for t, fl, o in zip(tensors, factor_lists, outs):
+        dims = t.info()["dims"]
+        R = check_factors(fl, dims, skip_mode=mode)
+        if 0 <= mode < len(dims):
+            check_matrix("out", o, dims[mode], R)
+    for t in tensors:
+        if not t._batched:
+            t.prepare(1, batched=True, stream=stream)
     hs = (ctypes.c_void_p * count)(*[t.handle.value for t in tensors])
     farrs = [_ptr_array(fl) for fl in factor_lists]
     fptrs = (_PP * count)(*[ctypes.cast(a, _PP) for a in farrs])
@@ -254,12 +432,18 @@ def mttkrp_batched(tensors, factor_lists, mode: int, outs, stream=None):
 def cp_als_batched(tensors, factor_lists, iters: int, tol: float = 0.0, lams=None, stream=None):
     import torch
     count = len(tensors)
+    if len(factor_lists) != count or (lams is not None and len(lams) != count):
+        raise ValueError("tensors, factor_lists and lams must have one entry per tensor")
+    for t, fl in zip(tensors, factor_lists):
+        check_factors(fl, t.info()["dims"])
     hs = (ctypes.c_void_p * count)(*[t.handle.value for t in tensors])
     farrs = [_ptr_array(fl) for fl in factor_lists]
     fptrs = (_PP * count)(*[ctypes.cast(a, _PP) for a in farrs])
     ranks = (ctypes.c_int * count)(*[int(fl[0].shape[1]) for fl in factor_lists])
     if lams is None:
         lams = [torch.empty(int(fl[0].shape[1]), dtype=torch.float64, device="cuda") for fl in factor_lists]
+    for fl, lam in zip(factor_lists, lams):
+        check_vector("lambda", lam, int(fl[0].shape[1]), "float64")
     lptrs = _ptr_array(lams)
     fits = (ctypes.c_double * count)()
     its = (ctypes.c_int * count)()
@@ -268,14 +452,53 @@ def cp_als_batched(tensors, factor_lists, iters: int, tol: float = 0.0, lams=Non
     return lams, list(fits), list(its)
 
 
-def autotune(t: Tensor, factors, budget_ms: float = 2000.0, stream=None):
-    R = int(factors[0].shape[1])
+def autotune(t: Tensor, factors, budget_ms: float = 2000.0, random_samples: int = 4, seed: int = 0, stream=None):
+    """Measured layout and plan search; re-encodes ``t`` in place when another layout wins.
+
+    Returns a dict: best_ms, alto_ms, start_ms (all-mode MTTKRP ms), candidates,
+    random_samples, cache_hits."""
+    R = check_factors(factors, t.info()["dims"])
     h = ctypes.c_void_p(t.handle.value)
-    best = ctypes.c_double()
-    _check(lib().spt_autotune(ctypes.byref(h), _ptr_array(factors), R, float(budget_ms), ctypes.byref(best),
-                              _stream(stream)))
+    res = TuneResult()
+    _check(lib().spt_autotune(ctypes.byref(h), _ptr_array(factors), R, float(budget_ms), int(random_samples),
+                              ctypes.c_uint64(int(seed)), ctypes.byref(res), _stream(stream)))
     t._h = h
-    return best.value
+    t._prepared_rank = R
+    t._batched = False
+    return {"best_ms": res.best_ms, "alto_ms": res.alto_ms, "start_ms": res.start_ms,
+            "candidates": res.candidates, "random_samples": res.random_samples, "cache_hits": res.cache_hits}
+
+
+_ALLOC_HOOKS = None
+
+
+def use_torch_allocator(on: bool = True):
+    """Route every device allocation of the library through PyTorch's caching allocator.
+
+    The hooks take and return memory on the stream the library passes; torch
+    keeps freed blocks for reuse on their allocation stream."""
+    global _ALLOC_HOOKS
+    if not on:
+        _check(lib().spt_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        _ALLOC_HOOKS = None
+        return
+    import torch
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+        except Exception:
+            return None
+
+    def _release(ptr, stream, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+    _check(lib().spt_set_allocator(hooks[0], hooks[1], None))
+    _ALLOC_HOOKS = hooks  # keep the callbacks alive
 
 
 class Server:
@@ -293,12 +516,8 @@ class Server:
         self._meta = {}
 
     def submit(self, dims, coords, vals, init, max_iters: int, tol: float = 0.0) -> int:
-        import numpy as np
         nm = len(dims)
-        coords = np.ascontiguousarray(coords, dtype=np.uint32)
-        vals = np.ascontiguousarray(vals, dtype=np.float32)
-        init = [np.ascontiguousarray(f, dtype=np.float32) for f in init]
-        rank = int(init[0].shape[1])
+        coords, vals, init, rank = check_request(dims, coords, vals, init)
         r = Request()
         r.nmodes = nm
         for k in range(nm):

@@ -38,3 +38,26 @@ def check_encoding(h, t, layout=None):
     assert info["layout"] == enc["layout"]
     assert info["encoded_bytes"] == t.nnz * (8 * enc["key_words"] + 4)
     return enc
+
+
+def cpd_error(F_got, lam_got, F_ref, lam_ref):
+    """Largest per-factor error of two CP decompositions on the same trajectory.
+
+    For every mode the lambda-scaled factor A = C diag(lambda) is compared row
+    by row: max_i ||A_got[i] - A_ref[i]||_inf / max_i ||A_ref[i]||_inf (the
+    row error relative to the factor's largest row).  Returns (max over
+    modes, lambda error max_r |dlambda_r| / max_r lambda_r).
+    """
+    lg = np.asarray(lam_got, dtype=np.float64)
+    lr = np.asarray(lam_ref, dtype=np.float64)
+    errs = []
+    for g, r in zip(F_got, F_ref):
+        A = np.asarray(g, dtype=np.float64) * lg[None, :]
+        B = np.asarray(r, dtype=np.float64) * lr[None, :]
+        errs.append(float(np.abs(A - B).max(initial=0.0) / max(np.abs(B).max(initial=0.0), 1e-300)))
+    return max(errs), float(np.abs(lg - lr).max() / lr.max())
+
+
+def to_host(F):
+    """Device factors to float32 numpy arrays."""
+    return [f.detach().cpu().numpy() for f in F]

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2509_00280_amd import synth
-from _gpu_helpers import check_encoding, factors_dev, mttkrp_error, to_dev
+from _gpu_helpers import check_encoding, cpd_error, factors_dev, mttkrp_error, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -43,13 +43,14 @@ def test_autotune_small_keeps_exact_encoding(spt):
     t, F, R, _ = synth.config("small")
     c, v = to_dev(t)
     h = spt.encode(t.dims, c, v)
-    best = spt.autotune(h, factors_dev(F), budget_ms=600.0)
-    print(f"best all-mode ms {best:.4f} layout {h.info()['layout']}", flush=True)
-    assert best > 0
+    res = spt.autotune(h, factors_dev(F), budget_ms=600.0, random_samples=3, seed=1)
+    print(f"tune {res} layout {h.info()['layout']}", flush=True)
+    assert res["best_ms"] > 0 and res["best_ms"] <= min(res["alto_ms"], res["start_ms"])
+    assert res["random_samples"] <= 3 and res["candidates"] >= 1
     _check_after_tune(spt, h, t, F)
-    # the winner is cached per (shape, nnz, rank, layout): a zero-budget call returns it
-    again = spt.autotune(h, factors_dev(F), budget_ms=0.0)
-    assert again == best
+    # the winner is cached per (shape, nnz, rank, layout, content): a zero-budget call returns it
+    again = spt.autotune(h, factors_dev(F), budget_ms=0.0, random_samples=0)
+    assert again["best_ms"] == res["best_ms"] and again["cache_hits"] >= 1
 
 
 def test_autotune_from_poor_layout(spt):
@@ -61,9 +62,20 @@ def test_autotune_from_poor_layout(spt):
     blocked = [n for n in range(3) for _ in range(lb[n])]
     c, v = to_dev(t)
     h = spt.encode(t.dims, c, v, layout=blocked)
-    best = spt.autotune(h, factors_dev(F), budget_ms=1500.0)
-    print(f"best {best:.4f} ms, layout moved: {h.info()['layout'] != blocked}", flush=True)
+    res = spt.autotune(h, factors_dev(F), budget_ms=1500.0, random_samples=4, seed=2)
+    print(f"tune {res}, layout moved: {h.info()['layout'] != blocked}", flush=True)
+    assert res["start_ms"] >= res["best_ms"]
     _check_after_tune(spt, h, t, F)
+
+
+def test_autotune_cache_distinguishes_contents(spt):
+    """Two tensors of one shape and nnz (one the label-shuffled other) are measured separately."""
+    t = synth.distinct_coo(17, (400, 300, 50), 40_000, [("zipf", 1.2), ("zipf", 1.2), "uniform"], "u01")
+    ts = synth.shuffle_labels(t, 5)
+    F = synth.normal_factors(18, t.dims, 16)
+    r1 = spt.autotune(spt.encode(t.dims, *to_dev(t)), factors_dev(F), budget_ms=0.0, random_samples=0)
+    r2 = spt.autotune(spt.encode(ts.dims, *to_dev(ts)), factors_dev(F), budget_ms=0.0, random_samples=0)
+    assert r1["cache_hits"] == 0 and r2["cache_hits"] == 0
 
 
 def _requests(count, seed=5, ranks=(8, 16, 32)):
@@ -89,14 +101,18 @@ def test_server_matches_single_tensor_cp_als(spt):
         h = spt.encode(t.dims, c, v)
         Fs = factors_dev(F)
         lam_s, fit_s, _ = spt.cp_als(h, Fs, iters)
-        print(f"nnz {t.nnz} R {R}: served fit {res['fit']:.8f} single {fit_s:.8f}", flush=True)
+        e, el = cpd_error(Fo, lam, to_host(Fs), lam_s.cpu().numpy())
+        print(f"nnz {t.nnz} R {R}: served fit {res['fit']:.8f} single {fit_s:.8f} factor err {e:.2e}", flush=True)
         assert abs(res["fit"] - fit_s) <= TOL_FIT
-        np.testing.assert_allclose(lam, lam_s.cpu().numpy(), rtol=1e-2)
+        assert e <= TOL_ROW and el <= TOL_ROW
         for n in range(t.nmodes):
             np.testing.assert_allclose(np.linalg.norm(Fo[n].astype(np.float64), axis=0), 1.0, rtol=1e-5)
     t, F, R = reqs[0]
     ref = oracle.cp_als(t.coords, t.vals, t.dims, F, iters=iters)
-    assert abs(results[0][0]["fit"] - ref["fit"]) <= TOL_FIT
+    res, Fo, lam = results[0]
+    e, el = cpd_error(Fo, lam, ref["factors"], ref["lam"])
+    assert abs(res["fit"] - ref["fit"]) <= TOL_FIT
+    assert e <= TOL_ROW and el <= TOL_ROW
 
 
 def test_server_one_slot_tol_and_budget(spt):

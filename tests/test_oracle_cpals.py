@@ -109,6 +109,63 @@ def test_tol_stops_early_and_zero_norm_rejected():
         oracle.cp_als(coords, np.zeros(100, np.float32), dims, F0, iters=2)
 
 
+def _rotated(eigs, angle):
+    """Symmetric 2x2 matrix Q diag(eigs) Q^T with Q the rotation by ``angle``."""
+    c, s = np.cos(angle), np.sin(angle)
+    Q = np.array([[c, -s], [s, c]])
+    return Q @ np.diag(eigs) @ Q.T, Q
+
+
+def _ridge_case(neg_mult, k_expected):
+    """V with eigenvalues (1, -neg_mult * delta_1): plain Cholesky fails; the ridge
+    delta_k = 1e-12 tr(V)/R * 1e3^(k-1) of retry k makes it positive definite first at
+    k_expected.  Returns the update and the closed-form M (V + delta_k I)^-1."""
+    R = 2
+    # delta_1 depends on tr(V), which depends on the negative eigenvalue: solve the fixed point
+    d1 = 1e-12 * 1.0 / R
+    for _ in range(5):
+        d1 = 1e-12 * (1.0 - neg_mult * d1) / R
+    V, Q = _rotated([1.0, -neg_mult * d1], 0.6)
+    base = 1e-12 * np.trace(V) / R
+    grams = [np.eye(R), V]               # mode 0: V is the Hadamard product of the other Grams
+    M = np.array([[1.0, 2.0], [-0.5, 0.25], [3.0, -1.0]])
+    Lc, k = oracle._cholesky_ridge(V)
+    assert k == k_expected
+    dk = base * 1e3 ** (k - 1)
+    # closed form of (V + dk I)^-1 through the eigen-decomposition
+    w = np.array([1.0, -neg_mult * d1]) + dk
+    inv = Q @ np.diag(1.0 / w) @ Q.T
+    C, lam = oracle.als_update(M, grams, 0)
+    return C * lam[None, :], M @ inv, w
+
+
+def test_ridge_retry_first_ridge_closed_form():
+    # eigenvalue -delta_1/2: fails plain, passes with delta_1 (the ridge is 1e-12 tr(V)/R)
+    got, want, w = _ridge_case(0.5, 1)
+    assert w.min() > 0
+    # cond(V + delta_1 I) ~ 4e12, so the Cholesky solve carries ~1e-3 relative error;
+    # a wrong ridge scale (factor 2 or 1e3) or sign is far outside it
+    np.testing.assert_allclose(got, want, rtol=5e-3)
+
+
+def test_ridge_retry_second_ridge_closed_form():
+    # eigenvalue -10 delta_1: still indefinite with delta_1, positive with delta_2 = 1e3 delta_1
+    got, want, _ = _ridge_case(10.0, 2)
+    np.testing.assert_allclose(got, want, rtol=1e-5)
+
+
+def test_ridge_gives_up_after_three_retries():
+    R = 2
+    V, _ = _rotated([1.0, -1e-3], 0.3)   # far below -delta_3 = -1e-6 tr(V)/R
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle._cholesky_ridge(V)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.als_update(np.ones((3, R)), [np.eye(R), V], 0)
+    # a positive definite V takes no ridge
+    _, k = oracle._cholesky_ridge(np.array([[2.0, 1.0], [1.0, 2.0]]))
+    assert k == 0
+
+
 def test_ridge_retry_on_singular_gram():
     # two identical columns make V singular; the ridge retry must still return a finite update
     dims = (5, 4, 3)
