@@ -219,6 +219,24 @@ void spt_tensor_free(spt_tensor t, void *stream);
 spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
                       void *stream);
 
+/*
+ * spt_mttkrp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments, result and kernels, with the record workspace of the
+ * SEGMENT strategy in a fixed device array of the library
+ * (SPT_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends) instead of
+ * memory taken from the allocator.  It calls no allocating routine.  The
+ * tensor must be prepared (SPT_PREPARE_SINGLE) and its plan for `mode` must
+ * be SEGMENT (or AUTO), DIRECT or REGROUP; a workspace above the maximum
+ * (records x (8 + 4 rank) bytes, about 0.1 records per nonzero) is rejected
+ * with SPT_E_INVALID_ARG.  Every call on one GPU shares the array: calls that
+ * overlap on one GPU (on different streams or threads) race, so the caller
+ * orders them.  Asynchronous, free of synchronisation.
+ */
+#define SPT_NOALLOC_SCRATCH_BYTES (64u << 20)
+spt_status spt_mttkrp_noalloc(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
+                              void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* CP-ALS (Section II-B; the update follows Kolda and Bader's ALS).        */
 /* ---------------------------------------------------------------------- */

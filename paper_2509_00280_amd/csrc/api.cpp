@@ -397,6 +397,18 @@ spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int m
     return run_mttkrp(t, factors, rank, mode, out, (hipStream_t)stream);
 }
 
+spt_status spt_mttkrp_noalloc(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
+                              void *stream) {
+    if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
+    if (mode < 0 || mode >= t->nmodes) return fail(SPT_E_INVALID_ARG, "mode out of range");
+    if (rank < 1 || rank > SPT_MAX_RANK) return fail(SPT_E_INVALID_ARG, "rank must be in 1..256");
+    if (!out) return fail(SPT_E_INVALID_ARG, "out is NULL");
+    if (!aligned16(out)) return fail(SPT_E_INVALID_ARG, "out not 16-byte aligned");
+    spt_status st = check_factors(t, factors, rank, mode);
+    if (st != SPT_OK) return st;
+    return run_mttkrp_noalloc(t, factors, rank, mode, out, (hipStream_t)stream);
+}
+
 spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *const *factors, double *lambda,
                       double *fit_out, int *iters_out, void *stream) {
     if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");

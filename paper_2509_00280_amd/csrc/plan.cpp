@@ -561,3 +561,96 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
 }
 
 }  // namespace spt
+
+// ---------------------------------------------------------------- no-allocation MTTKRP
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops): the record workspace of the SEGMENT strategy lives in
+// a fixed device array.  Host code never passes `scratch` itself to a kernel
+// (its name is a host-side stand-in); it uses the device address taken once
+// per device with hipGetSymbolAddress.  Every call on one GPU shares that
+// array, so calls that overlap on one GPU race.
+namespace spt {
+namespace {
+constexpr size_t kScratchBytes = SPT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+spt_status scratch_ptr(void **out) {
+    int dev = 0;
+    SPT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPT_E_DEVICE, "mttkrp_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "mttkrp_noalloc: scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPT_OK;
+}
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kScratchBytes; }
+
+// The SEGMENT (and DIRECT/REGROUP) paths of run_mttkrp_impl with the records
+// in the fixed array instead of call-owned buffers.  Nothing here allocates.
+spt_status run_mttkrp_noalloc(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
+    ModePlan *p = nullptr;
+    spt_status st = resolve_plan(t, mode, rank, s, &p, false);
+    if (st != SPT_OK) return st;
+    const int64_t rows = t->dims[mode];
+    if (t->nnz == 0 || p->strategy == SPT_STRATEGY_DIRECT || p->strategy == SPT_STRATEGY_REGROUP) {
+        st = launch_fill_zero(out, rows * (int64_t)rank, s);
+        if (st != SPT_OK || t->nnz == 0) return st;
+        return launch_mttkrp(make_args(t, factors, rank, mode, out, std::min(t->plan.tile[mode], 1024)), p->strategy, s);
+    }
+    if (p->strategy != SPT_STRATEGY_SEGMENT)
+        return fail(SPT_E_INVALID_ARG, "mttkrp_noalloc: only the SEGMENT, DIRECT and REGROUP strategies run without allocation");
+    const int64_t P = p->records;
+    const size_t row_bytes = ((sizeof(uint64_t) * (size_t)std::max<int64_t>(P, 1)) + 255) & ~size_t(255);
+    const size_t need = row_bytes + sizeof(float) * (size_t)std::max<int64_t>(P, 1) * rank;
+    if (need > kScratchBytes)
+        return fail(SPT_E_INVALID_ARG, "mttkrp_noalloc: " + std::to_string(P) + " records of rank " + std::to_string(rank) +
+                                           " need " + std::to_string(need) + " bytes of scratch, above the " +
+                                           std::to_string(kScratchBytes) + "-byte maximum");
+    void *base = nullptr;
+    st = scratch_ptr(&base);
+    if (st != SPT_OK) return st;
+    MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
+    a.pl_pos = p->pl_pos;
+    a.pl_off = p->pl_off;
+    a.pl_desc = p->pl_desc;
+    a.pl_row = p->pl_row;
+    a.pl_dest = p->pl_dest;
+    a.rec_cap = P;
+    const int cap = p->ts == kDictTile ? dict_cap(t->nmodes, rank) : 0;
+    if (cap > 0 && t->plan.row_cache != 0) {
+        bool all = true;
+        for (int k = 0; k < t->nmodes; ++k)
+            if (k != mode) all = all && t->dict_slot[k] != nullptr;
+        if (all) {
+            for (int o = 0, k = 0; k < t->nmodes; ++k) {
+                if (k == mode) continue;
+                a.d_slot[o] = t->dict_slot[k];
+                a.d_row[o] = t->dict_row[k];
+                a.d_off[o] = t->dict_off[k];
+                ++o;
+            }
+            a.d_cap = cap;
+        }
+    }
+    // every record the plan lays out is written by the main kernel before the
+    // reduction reads it, so the array needs no clearing between calls
+    a.rec_row = (uint64_t *)base;
+    a.rec_val = (float *)((char *)base + row_bytes);
+    st = launch_mttkrp_seg(a, s);
+    if (st == SPT_OK) st = launch_fill_zero(out, rows * (int64_t)rank, s);
+    if (st == SPT_OK) st = launch_reduce_records(a.rec_row, nullptr, a.rec_val, P, rank, rows, out, s);
+    return st;
+}
+
+}  // namespace spt

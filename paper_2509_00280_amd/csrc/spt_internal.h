@@ -115,6 +115,9 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 spt_status prepare_single(Tensor *t, int rank, hipStream_t s);
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's prepared plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+// the same with the record workspace in the library's fixed device array
+spt_status run_mttkrp_noalloc(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+size_t noalloc_scratch_bytes();
 // The release functions free in stream order on s (after the work already
 // ordered on s); none synchronises.
 void release_plans(Tensor *t, hipStream_t s);

@@ -101,6 +101,7 @@ def lib():
     _sig(L, "spt_tensor_free", None, [_VP, _VP])
     _sig(L, "spt_set_allocator", st, [ALLOC_FN, RELEASE_FN, _VP])
     _sig(L, "spt_mttkrp", st, [_VP, _PP, i, i, _VP, _VP])
+    _sig(L, "spt_mttkrp_noalloc", st, [_VP, _PP, i, i, _VP, _VP])
     _sig(L, "spt_cp_als", st, [_VP, i, i, d, _PP, _VP, ctypes.POINTER(d), ctypes.POINTER(i), _VP])
     _sig(L, "spt_als_update", st, [_VP, i, i, i, _VP, i64, _VP, _VP, ctypes.POINTER(i), _VP])
     _sig(L, "spt_mttkrp_batched", st, [_PP, i, ctypes.POINTER(_PP), ctypes.POINTER(i), i, _PP, _VP])
@@ -364,6 +365,17 @@ def mttkrp(t: Tensor, factors, mode: int, out=None, stream=None):
         check_matrix("out", out, rows, R)
     t.ensure_prepared(R, stream)
     _check(lib().spt_mttkrp(t.handle, _ptr_array(factors), R, int(mode), _ptr(out), _stream(stream)))
+    return out
+
+
+def mttkrp_noalloc(t: Tensor, factors, mode: int, out, stream=None):
+    """``mttkrp`` into a caller-given ``out`` through the entry point that allocates nothing
+    (its workspace is the library's fixed per-GPU array; the tensor must be prepared)."""
+    dims = t.info()["dims"]
+    R = check_factors(factors, dims, skip_mode=mode)
+    if 0 <= mode < len(dims):
+        check_matrix("out", out, dims[mode], R)
+    _check(lib().spt_mttkrp_noalloc(t.handle, _ptr_array(factors), R, int(mode), _ptr(out), _stream(stream)))
     return out
 
 
