@@ -1,15 +1,20 @@
-"""Benchmark: encode + CP-ALS of the 3-mode ratings-shaped tensor on one MI355X.
+"""Benchmark: encode + CP-ALS of the skewed 4-mode tensor on one MI355X.
 
-Workload (synthetic, seeded): 480,000 x 18,000 x 2,000, 100M distinct nonzeros,
-mode-0/1 labels Zipf(1.1), mode-2 uniform, values uniform on {1..5}, rank 32,
-20 CP-ALS iterations.  One step = one whole solve from the COO tensor resident
-in HBM: GPU encoding (bit deposit + radix sort) followed by 20 CP-ALS
+Workload (synthetic, seeded, drawn on the GPU): 2,000,000 x 100,000 x 50,000 x
+24, 150M distinct nonzeros, labels Zipf(1.3) on modes 0-2 and uniform on mode
+3, values lognormal(0,1), rank 64, 10 CP-ALS iterations.  Before the timed
+region the autotuner picks the bit layout and the per-mode plan (tile,
+strategy) by measured all-mode MTTKRP time against the ALTO layout.  One step
+= one whole solve from the COO tensor resident in HBM: GPU encoding with the
+tuned layout (bit deposit + radix sort), the per-mode plans, then 10 CP-ALS
 iterations (all-mode MTTKRP, FP64 Gram/Cholesky/solve, FP64 fit).
 
 Printed metric: MTTKRP Gnnz/s per mode over the whole step
-(nnz * modes * iterations / step time).  Extra fields: the MTTKRP kernels alone
-(HIP events around every launch), the roofline of the MTTKRP kernel, solves/s,
-and the FP64 oracle timed on a bounded sample on the host.
+(nnz * modes * iterations / step time).  Extra fields: the MTTKRP calls alone
+(HIP events around every call), the roofline of the MTTKRP call with measured
+stream rates and a cache-aware bound, the sampled-row error of every mode
+against the FP64 oracle, the ratings tensor's MTTKRP, and the oracle timed on
+the host (one thread, and a process pool over the host cores).
 """
 from __future__ import annotations
 
@@ -46,27 +51,59 @@ def source_digest() -> str:
 
 def algorithmic_bytes(t, rank: int, mode: int) -> int:
     """Compulsory HBM bytes of one mode-n MTTKRP: the key/value stream once (12 B per
-    nonzero with 64-bit keys), every factor row that some nonzero touches read once,
-    and the output written once."""
+    nonzero with 64-bit keys, 20 B with 128-bit keys), every factor row that some
+    nonzero touches read once, and the output written once.  ``t`` holds its
+    coordinates as a torch tensor (device) or a numpy array (host)."""
     kw = 8 if sum((int(d) - 1).bit_length() for d in t.dims) <= 64 else 16
     b = t.nnz * (kw + 4)
     for k, d in enumerate(t.dims):
-        used = int(np.count_nonzero(np.bincount(t.coords[k], minlength=d)))
         if k == mode:
             b += int(d) * rank * 4
+            continue
+        c = t.coords[k]
+        if hasattr(c, "is_cuda"):
+            import torch
+            seen = torch.zeros(int(d), dtype=torch.bool, device=c.device)
+            seen[c.long()] = True
+            used = int(seen.sum().item())
         else:
-            b += used * rank * 4
+            used = int(np.count_nonzero(np.bincount(c, minlength=d)))
+        b += used * rank * 4
     return b
 
 
-def cpu_baseline(t, factors, budget_s: float = 20.0):
-    """The FP64 oracle MTTKRP (single thread, as it stands) on a bounded sample."""
+def host_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_POOL_DATA = {}
+
+
+def _pool_job(job):
     import oracle
-    # about 10-30 s of single-thread FP64 work: the whole ratings tensor, a prefix of larger ones
+    mode, lo, hi = job
+    d = _POOL_DATA
+    oracle.mttkrp(np.ascontiguousarray(d["coords"][:, lo:hi]), np.ascontiguousarray(d["vals"][lo:hi]), d["dims"],
+                  d["factors"], mode)
+    return hi - lo
+
+
+def cpu_baseline(t, factors, budget_s: float = 20.0):
+    """The FP64 oracle MTTKRP (as it stands) on a bounded sample of the tensor: one
+    thread, then a process pool over the host cores (modes x nonzero chunks)."""
+    import multiprocessing as mp
+    import oracle
+    # about 10-30 s of single-thread FP64 work: a prefix of the tensor
     n = min(t.nnz, 100_000_000 if factors[0].shape[1] <= 32 else 20_000_000)
-    sample = slice(0, n)
-    c = np.ascontiguousarray(t.coords[:, sample])
-    v = np.ascontiguousarray(t.vals[sample])
+    c = np.ascontiguousarray(t.coords[:, :n])
+    v = np.ascontiguousarray(t.vals[:n])
     done = 0
     t0 = time.perf_counter()
     modes = 0
@@ -77,23 +114,121 @@ def cpu_baseline(t, factors, budget_s: float = 20.0):
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": round(done / el / 1e9, 6), "unit": "Gnnz/s per mode", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {t.nnz} nonzeros (input order), FP64 oracle MTTKRP, {modes} mode(s), "
-                      f"{el:.1f} s on 1 thread of {os.cpu_count()} host cores"}
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(ncores, 16))
+    out = {"value": round(done / el / 1e9, 6), "unit": "Gnnz/s per mode", "cores": 1, "kind": "oracle",
+           "sample": f"first {n} of {t.nnz} nonzeros (input order), FP64 oracle MTTKRP, {modes} mode(s), "
+                     f"{el:.1f} s on 1 thread",
+           "host": {"model": host_model(), "cores_visible": ncores}}
+    # the same sample, every mode, split into nonzero chunks over a process pool
+    _POOL_DATA.update(coords=c, vals=v, dims=t.dims, factors=factors)
+    chunk = (n + workers - 1) // workers
+    jobs = [(m, lo, min(n, lo + chunk)) for m in range(t.nmodes) for lo in range(0, n, chunk)]
+    try:
+        ctx = mp.get_context("fork")
+        t1 = time.perf_counter()
+        with ctx.Pool(workers) as pool:
+            tot = sum(pool.map(_pool_job, jobs, chunksize=1))
+        elp = time.perf_counter() - t1
+        out["pool"] = {"value": round(tot / elp / 1e9, 6), "unit": "Gnnz/s per mode", "cores": workers,
+                       "sample": f"the same {n} nonzeros x {t.nmodes} modes in {len(jobs)} jobs, {elp:.1f} s wall"}
+    except Exception as e:  # the pool is context; the single-thread figure stands alone
+        out["pool"] = {"error": str(e)[:200]}
+    finally:
+        _POOL_DATA.clear()
+    return out
+
+
+def stream_rates() -> dict:
+    """Measured streaming rates on the GPU (context for the roofline): a 1 GiB
+    device copy (HBM read + write), and repeated reads of a 128 MiB buffer
+    (Infinity-Cache resident) and of a 2 MiB buffer (L2 resident) through
+    stride-0 views summed by torch."""
+    import torch
+    dev = torch.device("cuda:0")
+    x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    res = {"hbm_copy_gbs": round(2 * 4 * x.numel() * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
+    del x, y
+    for name, mib, rep in (("mall_read_gbs", 128, 8), ("l2_read_gbs", 2, 512)):
+        z = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+        view = z.expand(rep, -1)
+        view.sum()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            view.sum()
+        e1.record()
+        e1.synchronize()
+        res[name] = round(5 * rep * z.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    return res
+
+
+def sampled_errors(th, Fh, outs, nrows: int = 64, seed: int = 0, nnz_budget: int = 8_000_000) -> dict:
+    """Max row error (|X|,|C| row scale) of full-size GPU outputs against the FP64
+    oracle on sampled rows: the row with the most nonzeros, then rows of hotness
+    rank 1, 3, 10, ..., 1000 and random rows while their nonzeros stay within a
+    budget (the oracle runs on exactly the nonzeros of the sampled rows)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    res = {}
+    for n, out in enumerate(outs):
+        cnt = np.bincount(th.coords[n], minlength=th.dims[n])
+        nz = np.nonzero(cnt)[0]
+        order = np.argsort(cnt)[::-1]
+        rows, total = [int(order[0])], 0
+        cand = [int(order[k]) for k in (1, 3, 10, 30, 100, 300, 1000) if k < nz.size]
+        cand += [int(r) for r in rng.choice(nz, size=min(nrows, nz.size), replace=False)]
+        for r in cand:
+            if r in rows or total + cnt[r] > nnz_budget or len(rows) >= nrows:
+                continue
+            rows.append(r)
+            total += int(cnt[r])
+        rows = np.array(sorted(rows), dtype=np.int64)
+        lut = np.zeros(th.dims[n], dtype=bool)
+        lut[rows] = True
+        m = lut[th.coords[n]]
+        c = np.ascontiguousarray(th.coords[:, m])
+        v = np.ascontiguousarray(th.vals[m])
+        ref = oracle.mttkrp(c, v, th.dims, Fh, n)[rows]
+        sc = oracle.mttkrp(c, np.abs(v), th.dims, [np.abs(f) for f in Fh], n)[rows]
+        err, bad = oracle.row_error(out[rows], ref, sc)
+        res[str(n)] = {"max_row_err": float(f"{err:.3e}"), "rows": int(rows.size), "nnz_checked": int(m.sum()),
+                       "hottest_row_nnz": int(cnt[order[0]]), "nonzero_empty_rows": bad}
+    return res
+
+
+COUNTER_PASSES = (
+    "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_LDS SQ_INSTS_SALU",
+    "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_LDS SQ_WAIT_ANY "
+    "SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY",
+    "TA_TA_BUSY_sum TA_BUFFER_READ_WAVEFRONTS_sum TD_TD_BUSY_sum TD_LOAD_WAVEFRONT_sum GRBM_GUI_ACTIVE",
+)
 
 
 def profile_cmds(workload: str) -> dict:
-    w = "" if workload == "ratings" else f" --workload {workload}"
-    return {
-        "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/kt -o kt -- "
-              f"python -u bench.py{w} --steps 2 --warmup 1 --no-cpu-baseline",
+    bench = (f"python -u bench.py --workload {workload} --tuned profiles/tuned_layout_{workload}.json "
+             f"--no-cpu-baseline --no-check --no-extra")
+    cmds = {
+        "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof/kt -o kt -- {bench} --steps 2 --warmup 1",
         "cf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/cf -o cf -- python -u bench.py --copy-calibration",
         "cw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/cw -o cw -- python -u bench.py --copy-calibration",
-        "bf": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/bf -o bf -- "
-              f"python -u bench.py{w} --steps 1 --warmup 0 --no-cpu-baseline",
-        "bw": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/bw -o bw -- "
-              f"python -u bench.py{w} --steps 1 --warmup 0 --no-cpu-baseline",
+        "bf": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/bf -o bf -- {bench} --steps 1 --warmup 0",
+        "bw": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/bw -o bw -- {bench} --steps 1 --warmup 0",
     }
+    for i, c in enumerate(COUNTER_PASSES):
+        cmds[f"p{i}"] = (f"rocprofv3 --pmc {c} --kernel-include-regex k_mttkrp_seg --output-format csv "
+                         f"-d gpurun_out/prof/p{i} -o p{i} -- {bench} --steps 1 --warmup 0")
+    return cmds
 
 
 WORKLOAD_TITLE = {
@@ -118,27 +253,40 @@ def _read_csv(path):
 
 def _call_windows(rows, key):
     """Group dispatches (sorted by id) into MTTKRP calls: from a main MTTKRP kernel
-    through the next record/partial reduction.  Returns per-call sums of key(row)."""
+    through the next record/partial reduction.  Returns per call [sum, names, per-kernel sums]."""
     rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
     calls, cur = [], None
     for r in rows:
         n = _kname(r["Kernel_Name"])
         if n.startswith(CALL_FIRST):
-            cur = [0.0, []]
+            cur = [0.0, [], {}]
         if cur is not None:
-            cur[0] += key(r)
+            v = key(r)
+            cur[0] += v
             cur[1].append(n)
+            short = n.split("<")[0]
+            cur[2][short] = cur[2].get(short, 0.0) + v
             if n.startswith(CALL_LAST):
                 calls.append(cur)
                 cur = None
     return calls
 
 
-def summarize_profiles(d: str, workload: str = "ratings"):
+def _per_dispatch(path):
+    """Counter rows summed per (dispatch, counter) -> {dispatch: {counter: value}}."""
+    out = {}
+    for r in _read_csv(path):
+        d = out.setdefault(int(r["Dispatch_Id"]), {"kernel": _kname(r["Kernel_Name"])})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def summarize_profiles(d: str, workload: str = "skewed4d"):
     """Write the committed summaries from rocprofv3 CSV output under d."""
-    PROFILE_CMDS = profile_cmds(workload)
-    lines = [f"# Kernel trace of {WORKLOAD_TITLE[workload]}",
-             f"# command: cd /tmp && export TMPDIR=/tmp; cd <repo>; {PROFILE_CMDS['kt']}",
+    cmds = profile_cmds(workload)
+    title = WORKLOAD_TITLE[workload]
+    lines = [f"# Kernel trace of {title}",
+             f"# command: cd /tmp && export TMPDIR=/tmp; cd <repo>; {cmds['kt']}",
              "# columns: calls, average us, total ms, percent of GPU time, kernel", ""]
     st = _read_csv(os.path.join(d, "kt", "kt_kernel_stats.csv"))
     for r in sorted(st, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
@@ -146,11 +294,14 @@ def summarize_profiles(d: str, workload: str = "ratings"):
                      f"{float(r['Percentage']):6.2f}  {_kname(r['Name'])}")
     tr = _read_csv(os.path.join(d, "kt", "kt_kernel_trace.csv"))
     calls = _call_windows(tr, lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    main = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
-            if _kname(r["Kernel_Name"]).startswith(CALL_FIRST)]
     if calls:
+        per_k = {}
+        for c in calls:
+            for k, v in c[2].items():
+                per_k[k] = per_k.get(k, 0.0) + v
         lines += ["", f"MTTKRP calls: {len(calls)}; kernel time per call (all kernels of the call) "
-                      f"avg {sum(c[0] for c in calls) / len(calls):.1f} us; main kernel avg {sum(main) / len(main):.1f} us",
+                      f"avg {sum(c[0] for c in calls) / len(calls):.1f} us",
+                  "per kernel, avg us per call: " + ", ".join(f"{k} {v / len(calls):.1f}" for k, v in per_k.items()),
                   "kernels of one call: " + " ".join(calls[-1][1])]
     with open(os.path.join(ROOT, "profiles", f"mttkrp_{workload}_kernels.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -170,9 +321,17 @@ def summarize_profiles(d: str, workload: str = "ratings"):
     write = sum(c[0] for c in cw_) / len(cw_) * 1024 * wf
     from paper_2509_00280_amd import synth
     nnz = synth._CONFIGS[workload][2]
-    out = [f"# HBM traffic of one mode-n MTTKRP call (all of its kernels) in {WORKLOAD_TITLE[workload]}",
+    split = []
+    for name, cl, fac in (("FETCH", cf_, ff), ("WRITE", cw_, wf)):
+        per_k = {}
+        for c in cl:
+            for k, v in c[2].items():
+                per_k[k] = per_k.get(k, 0.0) + v
+        split.append(f"{name.lower()}_bytes_per_nnz_by_kernel: " +
+                     ", ".join(f"{k} {v / len(cl) * 1024 * fac / nnz:.2f}" for k, v in per_k.items()))
+    out = [f"# HBM traffic of one mode-n MTTKRP call (all of its kernels) in {title}",
            f"# commands (each its own run): cd /tmp && export TMPDIR=/tmp; cd <repo>;",
-           f"#   {PROFILE_CMDS['cf']}", f"#   {PROFILE_CMDS['cw']}", f"#   {PROFILE_CMDS['bf']}", f"#   {PROFILE_CMDS['bw']}",
+           f"#   {cmds['cf']}", f"#   {cmds['cw']}", f"#   {cmds['bf']}", f"#   {cmds['bw']}",
            f"# calibration: a 1 GiB device copy reads FETCH_SIZE {fk:.0f} KiB and WRITE_SIZE {wk:.0f} KiB per dispatch,",
            f"# so FETCH_SIZE KiB x {ff:.3f} and WRITE_SIZE KiB x {wf:.3f} give bytes",
            f"# calls averaged: {len(cf_)} (FETCH run), {len(cw_)} (WRITE run)",
@@ -181,10 +340,39 @@ def summarize_profiles(d: str, workload: str = "ratings"):
            f"fetch_bytes_per_launch: {fetch:.0f}",
            f"write_bytes_per_launch: {write:.0f}",
            f"hbm_bytes_per_launch: {fetch + write:.0f}",
-           f"hbm_bytes_per_nnz: {(fetch + write) / nnz:.2f}"]
+           f"hbm_bytes_per_nnz: {(fetch + write) / nnz:.2f}"] + split
     with open(pmc_file(workload), "w") as f:
         f.write("\n".join(out) + "\n")
-    print("\n".join(lines + [""] + out))
+    # counters of the main kernel (each pass its own run)
+    cl = [f"# Counters of the main MTTKRP kernel in {title}",
+          "# commands (each its own run): cd /tmp && export TMPDIR=/tmp; cd <repo>;"]
+    cl += [f"#   {cmds[f'p{i}']}" for i in range(len(COUNTER_PASSES))]
+    cl.append("# values are per dispatch, averaged over the dispatches of the run; busy and conflict")
+    cl.append("# percentages are relative to the kernel's GPU cycles (GRBM_GUI_ACTIVE x CUs per XCD)")
+    agg = {}
+    for i in range(len(COUNTER_PASSES)):
+        path = os.path.join(d, f"p{i}", f"p{i}_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        disp = _per_dispatch(path)
+        for dd in disp.values():
+            for k, v in dd.items():
+                if k != "kernel":
+                    agg.setdefault(k, []).append(v)
+    avg = {k: sum(v) / len(v) for k, v in agg.items()}
+    for k in sorted(avg):
+        cl.append(f"{k}: {avg[k]:.4g}")
+    if "GRBM_GUI_ACTIVE" in avg:
+        cu_cycles = avg["GRBM_GUI_ACTIVE"] / 8 * 256  # per-XCD cycles x 256 CUs
+        for k in ("TA_TA_BUSY_sum", "TD_TD_BUSY_sum", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS"):
+            if k in avg:
+                cl.append(f"{k} per CU-cycle: {avg[k] / cu_cycles:.3f}")
+        if "SQ_LDS_BANK_CONFLICT" in avg and "SQ_ACTIVE_INST_LDS" in avg:
+            cl.append(f"LDS bank-conflict cycles / LDS active cycles: "
+                      f"{avg['SQ_LDS_BANK_CONFLICT'] / avg['SQ_ACTIVE_INST_LDS']:.3f}")
+    with open(os.path.join(ROOT, "profiles", f"mttkrp_{workload}_counters.txt"), "w") as f:
+        f.write("\n".join(cl) + "\n")
+    print("\n".join(lines + [""] + out + [""] + cl))
 
 
 def _upload(t):
@@ -326,10 +514,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nnz", type=float, default=None, help="scale the tensor down (debug only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("ratings", "skewed4d", "batch", "serve"), default="ratings",
-                    help="ratings: the headline MTTKRP benchmark; skewed4d: the 4-mode rank-64 tensor whose "
-                         "factors exceed the Infinity Cache; batch: batched vs per-tensor CP-ALS; "
+    ap.add_argument("--workload", choices=("skewed4d", "ratings", "batch", "serve"), default="skewed4d",
+                    help="skewed4d: the headline, the 4-mode rank-64 tensor whose factors exceed the Infinity "
+                         "Cache; ratings: the 3-mode rank-32 tensor; batch: batched vs per-tensor CP-ALS; "
                          "serve: continuous-batching server latency")
+    ap.add_argument("--tune-budget-ms", type=float, default=30000.0,
+                    help="wall-time budget of the layout and plan search before the timed region (0: ALTO)")
+    ap.add_argument("--tune-samples", type=int, default=4, help="uniform samples of the layout space in the search")
+    ap.add_argument("--tuned", default=None, metavar="JSON",
+                    help="use a recorded search result (layout and plan) instead of searching")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--no-extra", action="store_true", help="skip the ratings MTTKRP line")
+    ap.add_argument("--torch-allocator", action="store_true",
+                    help="route the library's device memory through PyTorch's caching allocator")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=10)
     ap.add_argument("--serve-count", type=int, default=120)
@@ -364,25 +561,82 @@ def main():
         bench_serve(args)
         return
 
+    bench_tensor(args)
+
+
+def mttkrp_line(spt, t, F, rank, reps: int = 10, layout=None, plan=None) -> dict:
+    """All-mode MTTKRP of one device tensor: per-mode call time (HIP events),
+    Gnnz/s, algorithmic bytes and the call's HBM-roofline fraction."""
+    import torch
+    h = spt.encode(t.dims, t.coords, t.vals, layout=layout)
+    if plan is not None:
+        h.set_plan(tile=plan["tile"], strategy=plan["strategy"], row_cache=plan["row_cache"])
+    h.prepare(rank)
+    outs = [torch.empty((d, rank), device="cuda") for d in t.dims]
+    for n in range(t.nmodes):
+        spt.mttkrp(h, F, n, out=outs[n])
+    torch.cuda.synchronize()
+    per_mode = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for n in range(t.nmodes):
+        e0.record()
+        for _ in range(reps):
+            spt.mttkrp(h, F, n, out=outs[n])
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = algorithmic_bytes(t, rank, n)
+        per_mode[str(n)] = {"ms": round(ms, 4), "gnnz_per_s": round(t.nnz / (ms * 1e-3) / 1e9, 3),
+                            "algorithmic_bytes": alg, "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    h.free()
+    return {"per_mode": per_mode, "outs": outs}
+
+
+def bench_tensor(args):
     import torch
     from paper_2509_00280_amd import spt, synth
 
+    if args.torch_allocator:
+        spt.use_torch_allocator(True)
     t0 = time.time()
-    t, F, rank, iters = synth.config(args.workload, nnz=None if args.nnz is None else int(args.nnz))
-    log(f"generated {t.nnz} nonzeros in {time.time() - t0:.1f} s")
+    t, F0, rank, iters = synth.config_device(args.workload, nnz=None if args.nnz is None else int(args.nnz))
+    torch.cuda.synchronize()
+    log(f"generated {t.nnz} nonzeros on the GPU in {time.time() - t0:.1f} s")
     dev = torch.device("cuda:0")
-    coords = torch.from_numpy(t.coords.view(np.int32)).to(dev)
-    vals = torch.from_numpy(t.vals).to(dev)
-    F0 = [torch.from_numpy(f).to(dev) for f in F]
+    nm = t.nmodes
     Fw = [torch.empty_like(f) for f in F0]
     lam = torch.empty(rank, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
-    nm = t.nmodes
+
+    # the autotuner picks the layout and per-mode plan (outside the timed region)
+    tune = None
+    layout, plan = None, None
+    if args.tuned:
+        with open(args.tuned) as f:
+            tune = json.load(f)
+        layout, plan = tune["layout"], dict(tune["plan"])
+        plan["tile"] = plan["tile"] + [4096] * (8 - nm)
+        plan["strategy"] = plan["strategy"] + [4] * (8 - nm)
+        tune["from_file"] = os.path.relpath(args.tuned, ROOT)
+    elif args.tune_budget_ms > 0:
+        h = spt.encode(t.dims, t.coords, t.vals)
+        t1 = time.time()
+        tune = spt.autotune(h, F0, budget_ms=args.tune_budget_ms, random_samples=args.tune_samples, seed=7)
+        layout, plan = h.info()["layout"], h.get_plan()
+        tune.update(search_s=round(time.time() - t1, 2), layout=layout,
+                    plan={"tile": plan["tile"][:nm], "strategy": plan["strategy"][:nm], "row_cache": plan["row_cache"]},
+                    speedup_vs_alto=round(tune["alto_ms"] / tune["best_ms"], 4))
+        h.free()
+        log(f"autotune: {tune}")
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(ROOT, "gpurun_out", f"tuned_{args.workload}.json"), "w") as f:
+            json.dump(tune, f)
 
     def step():
         for a, b in zip(Fw, F0):
             a.copy_(b)
-        h = spt.encode(t.dims, coords, vals)
+        h = spt.encode(t.dims, t.coords, t.vals, layout=layout)
+        if plan is not None:
+            h.set_plan(tile=plan["tile"], strategy=plan["strategy"], row_cache=plan["row_cache"])
         _, fit, its = spt.cp_als(h, Fw, iters, lam=lam)
         h.free()
         return fit, its
@@ -398,11 +652,12 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t_start
     prof = spt.profile_read()
+    spt.profile_reset(False)
     ms_step = el * 1e3 / args.steps
     value = t.nnz * nm * iters / (ms_step * 1e-3) / 1e9
     log(f"{args.steps} steps in {el:.3f} s: {ms_step:.2f} ms/step, fit {fit:.6f}")
 
-    # MTTKRP kernels alone (HIP events on the library's stream around every launch)
+    # MTTKRP calls alone (HIP events on the library's stream around every call)
     per_mode = {}
     for m in range(nm):
         cnt = prof["mttkrp_launches"][m]
@@ -422,11 +677,25 @@ def main():
                     pmc[k.strip()] = v.strip()
         if pmc.get("source_digest") == source_digest() and pmc.get("nnz") == str(t.nnz):
             traffic = float(pmc["hbm_bytes_per_launch"])
+    rates = stream_rates()
+    # every factor-row read of a call (no reuse) must at least cross the fastest
+    # on-chip path, LDS: 128 B per clock per CU x 256 CUs x 2.4 GHz
+    gather_bytes = t.nnz * (nm - 1) * 4 * rank
+    lds_peak_gbs = 128 * 256 * 2.4
+    bound_ms = max(alg_avg / (HBM_PEAK_GBS * 1e9), gather_bytes / (lds_peak_gbs * 1e9)) * 1e3
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "one mode-n MTTKRP call (k_mttkrp_segd, k_fill_zero, k_reduce_records)",
                 "algorithmic_bytes_per_launch": int(alg_avg),
-                "avg_launch_ms": round(mk_ms, 4)}
+                "algorithmic_bytes_per_nnz": round(alg_avg / t.nnz, 2),
+                "measured_bytes_per_nnz": None if traffic is None else round(traffic / t.nnz, 2),
+                "avg_launch_ms": round(mk_ms, 4),
+                "measured_rates": rates,
+                "frac_of_measured_hbm_copy": round(achieved / rates["hbm_copy_gbs"], 4),
+                "cache_aware_bound": {"ms": round(bound_ms, 4), "frac": round(bound_ms / mk_ms, 4),
+                                      "gather_bytes_per_launch": int(gather_bytes),
+                                      "rule": "max(compulsory bytes / 8 TB/s HBM, factor-row gather bytes without "
+                                              "reuse / 78.6 TB/s LDS peak); frac = bound / measured call time"}}
     shape = "x".join(map(str, t.dims))
     if args.workload == "ratings":
         desc = (f"ratings-shaped 3-mode tensor {shape}, {t.nnz} nonzeros, Zipf(1.1)/Zipf(1.1)/uniform labels, "
@@ -438,18 +707,38 @@ def main():
         "metric": "MTTKRP Gnnz/s per mode", "value": round(value, 3), "unit": "Gnnz/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": desc + f"GPU encode + {iters} CP-ALS iterations per step",
+        "data": "synthetic (seeded, drawn on the GPU)",
+        "config": {"workload": desc + f"autotuned layout and plan, GPU encode + {iters} CP-ALS iterations per step",
                    "nnz": t.nnz, "rank": rank, "iters": iters, "parallelism": "single GPU"},
         "mttkrp_per_mode": per_mode,
         "solves_per_s": round(1e3 / ms_step, 4),
         "fit": round(fit, 6),
         "dtype_solve": "f64",
+        "autotune": tune,
         "roofline": roofline,
     }
+    # full-size MTTKRP of every mode against the FP64 oracle on sampled rows
+    th = t.to_host()
+    Fh = [f.cpu().numpy() for f in F0]
+    if not args.no_check:
+        line = mttkrp_line(spt, t, F0, rank, reps=3, layout=layout, plan=plan)
+        out["error_vs_oracle"] = sampled_errors(th, Fh, [o.cpu().numpy() for o in line["outs"]])
+        out["error_vs_oracle"]["metric"] = ("max_i |gpu - oracle|_inf / |MTTKRP(|X|,|C|)_i|_inf over sampled rows "
+                                            "(the hottest, a few by hotness rank, random), FP64 oracle")
+        del line
+    if args.workload != "ratings" and not args.no_extra:
+        tr, Fr, rr, _ = synth.config_device("ratings")
+        r = mttkrp_line(spt, tr, Fr, rr)
+        extra = {"workload": "ratings-shaped 3-mode tensor 480000x18000x2000, 100M nonzeros, rank 32, ALTO layout",
+                 "mttkrp_per_mode": r["per_mode"]}
+        if not args.no_check:
+            extra["error_vs_oracle"] = sampled_errors(tr.to_host(), [f.cpu().numpy() for f in Fr],
+                                                      [o.cpu().numpy() for o in r["outs"]])
+        out["ratings"] = extra
+        del r, tr, Fr
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(t, F)
+        out["cpu_baseline"] = cpu_baseline(th, Fh)
     print(json.dumps(out), flush=True)
 
 

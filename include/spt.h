@@ -84,7 +84,7 @@ typedef struct {
 #define SPT_STRATEGY_AUTO 4     /* SEGMENT (measured fastest for small and large output modes);
                                    the autotuner also tries PRIV where it fits */
 #define SPT_STRATEGY_SEGMENT 5  /* each tile regrouped by output row (the plan: positions of every
-                                   nonzero, pieces of at most 32 nonzeros of one row); every piece
+                                   nonzero, pieces of at most 64 nonzeros of one row); every piece
                                    becomes a record written with plain stores at a slot that keeps the
                                    records grouped by row; records are summed per row (no atomics
                                    except for rows split between two reducer chunks).  The plan is

@@ -34,7 +34,7 @@
 #define SPT_SEG_UB 1
 #endif
 #ifndef SPT_SEG_PIECE
-#define SPT_SEG_PIECE 32
+#define SPT_SEG_PIECE 64
 #endif
 
 namespace spt {

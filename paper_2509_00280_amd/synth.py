@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "SparseCOO", "zipf_cdf", "draw_labels", "distinct_coo", "uniform_distinct_coo",
     "normal_factors", "shuffle_labels", "config", "batch_config", "serving_requests",
-    "CONFIG_NAMES",
+    "CONFIG_NAMES", "DeviceCOO", "distinct_coo_device", "config_device",
 ]
 
 
@@ -315,3 +315,129 @@ def materialize(req):
     s_t, s_f = (int(x) for x in rng.integers(0, 2 ** 63 - 1, size=2))
     t = distinct_coo(s_t, dims, nnz, [("zipf", kw.get("zipf_s", 1.2))] * nm, "u01")
     return t, normal_factors(s_f, dims, rank), rank
+
+
+# --------------------------------------------------------------------------
+# The same recipes drawn on a torch device (the GPU for the full-size
+# workloads, which NumPy takes minutes to draw).  Same algorithm as
+# ``distinct_coo`` (bounded Zipf by inverse CDF over FP64 weights, rounds of
+# ceil(1.5 * deficit) draws, first occurrence in draw order kept, truncation
+# to exactly nnz in draw order); the stream is torch's generator of the
+# device, seeded, so the arrays are reproducible on one device type but are
+# not the NumPy arrays of ``distinct_coo``.
+# --------------------------------------------------------------------------
+
+@dataclass
+class DeviceCOO:
+    """A sparse tensor in coordinate form held in torch tensors on one device.
+
+    coords: int32 tensor (nmodes, nnz) (bits of uint32 coordinates); vals: float32 (nnz,).
+    """
+    dims: tuple
+    coords: object
+    vals: object
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nmodes(self) -> int:
+        return len(self.dims)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.vals.shape[0])
+
+    def to_host(self) -> SparseCOO:
+        return SparseCOO(self.dims, self.coords.cpu().numpy().view(np.uint32), self.vals.cpu().numpy(),
+                         meta=dict(self.meta))
+
+
+def _draw_labels_device(torch, gen, n: int, count: int, dist, cdf, device):
+    if dist == "uniform":
+        return torch.randint(0, n, (count,), generator=gen, device=device, dtype=torch.int64)
+    u = torch.rand(count, generator=gen, device=device, dtype=torch.float64)
+    idx = torch.searchsorted(cdf, u, right=True)
+    return torch.clamp(idx, max=n - 1)
+
+
+def _draw_values_device(torch, gen, count: int, vdist, device):
+    if vdist == "u01":
+        return torch.rand(count, generator=gen, device=device, dtype=torch.float32)
+    if vdist == "int1to5":
+        return torch.randint(1, 6, (count,), generator=gen, device=device, dtype=torch.int64).to(torch.float32)
+    if vdist == "lognormal":
+        return torch.exp(torch.randn(count, generator=gen, device=device, dtype=torch.float64)).to(torch.float32)
+    if vdist == "normal":
+        return torch.randn(count, generator=gen, device=device, dtype=torch.float32)
+    raise ValueError(vdist)
+
+
+def distinct_coo_device(seed: int, dims, nnz: int, mode_dists, vdist, device="cuda", max_rounds: int = 40):
+    """``distinct_coo``'s recipe drawn with torch on ``device`` (boxes below 2^63 cells)."""
+    import torch
+    dims = tuple(int(d) for d in dims)
+    if math.prod(dims) >= 2 ** 63:
+        raise ValueError("distinct_coo_device: the box must have fewer than 2^63 cells")
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    cdfs = [None if d == "uniform" else torch.from_numpy(zipf_cdf(n, d[1])).to(dev) for n, d in zip(dims, mode_dists)]
+    radix = []
+    r = 1
+    for d in reversed(dims):
+        radix.append(r)
+        r *= d
+    radix = list(reversed(radix))
+    kept_lin = torch.zeros(0, dtype=torch.int64, device=dev)
+    kept_v = torch.zeros(0, dtype=torch.float32, device=dev)
+    rounds = 0
+    while kept_lin.shape[0] < nnz and rounds < max_rounds:
+        deficit = nnz - kept_lin.shape[0]
+        m = int(math.ceil(1.5 * deficit))
+        lin = torch.zeros(m, dtype=torch.int64, device=dev)
+        for n, d in enumerate(dims):
+            lin += _draw_labels_device(torch, gen, d, m, mode_dists[n], cdfs[n], dev) * radix[n]
+        v = _draw_values_device(torch, gen, m, vdist, dev)
+        nk = kept_lin.shape[0]
+        allv = torch.cat([kept_lin, lin])
+        sv, si = torch.sort(allv, stable=True)
+        head = torch.ones(sv.shape[0], dtype=torch.bool, device=dev)
+        head[1:] = sv[1:] != sv[:-1]
+        first = si[head]
+        new = torch.sort(first[first >= nk] - nk).values
+        kept_lin = torch.cat([kept_lin, lin[new]])
+        kept_v = torch.cat([kept_v, v[new]])
+        del allv, sv, si, head, first, new, lin, v
+        rounds += 1
+    kept_lin = kept_lin[:nnz]
+    kept_v = kept_v[:nnz].contiguous()
+    coords = torch.empty((len(dims), kept_lin.shape[0]), dtype=torch.int32, device=dev)
+    rem = kept_lin
+    for n in range(len(dims)):
+        coords[n] = (rem // radix[n]).to(torch.int32)
+        rem = rem % radix[n]
+    return DeviceCOO(dims, coords, kept_v,
+                     meta={"seed": seed, "rounds": rounds, "realized_nnz": int(kept_v.shape[0]),
+                           "requested_nnz": int(nnz), "mode_dists": list(mode_dists), "vdist": vdist,
+                           "generator": f"torch {dev.type}"})
+
+
+def normal_factors_device(seed: int, dims, rank: int, device="cuda") -> list:
+    """Row-major FP32 ``I_n x rank`` N(0,1) matrices drawn with torch on ``device``."""
+    import torch
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    return [torch.randn((int(d), rank), generator=gen, device=dev, dtype=torch.float32) for d in dims]
+
+
+def config_device(name: str, device="cuda", nnz: int | None = None):
+    """``config``'s workloads drawn with torch on ``device``.  Returns (DeviceCOO, factors, rank, iters)."""
+    seed, dims, full_nnz, dists, vdist, rank, iters = _CONFIGS[name]
+    if dists is None:
+        raise ValueError("config_device: the small workload is drawn by ``config``")
+    n = full_nnz if nnz is None else int(nnz)
+    ss = np.random.SeedSequence(seed)
+    s_t, s_f, _ = (int(x.generate_state(1)[0]) for x in ss.spawn(3))
+    t = distinct_coo_device(s_t, dims, n, dists, vdist, device)
+    t.meta["config"] = name
+    return t, normal_factors_device(s_f, dims, rank, device), rank, iters

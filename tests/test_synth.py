@@ -74,3 +74,29 @@ def test_distinct_coo_huge_box():
     t = synth.distinct_coo(3, dims, 20_000, [("zipf", 1.2)] * 4, "u01")
     assert t.nnz == 20_000
     assert len(set(map(tuple, t.coords.T))) == 20_000
+
+
+def test_device_generator_recipe_on_cpu():
+    """The torch recipe (run on the CPU here): exact distinct count, ranges,
+    Zipf label 0 most frequent, value laws, reproducible for a seed."""
+    import torch
+    from paper_2509_00280_amd import synth
+    dims = (500, 300, 24)
+    dists = [("zipf", 1.3), ("zipf", 1.3), "uniform"]
+    t = synth.distinct_coo_device(7, dims, 20_000, dists, "lognormal", device="cpu")
+    assert t.nnz == 20_000 and t.coords.dtype == torch.int32
+    c = t.coords.numpy()
+    lin = (c[0].astype(np.int64) * 300 + c[1]) * 24 + c[2]
+    assert np.unique(lin).size == t.nnz
+    for n, d in enumerate(dims):
+        assert c[n].min() >= 0 and c[n].max() < d
+    for n in (0, 1):
+        cnt = np.bincount(c[n], minlength=dims[n])
+        assert cnt.argmax() == 0 and cnt[0] > cnt[10] > cnt[200]
+    assert (t.vals.numpy() > 0).all()
+    t2 = synth.distinct_coo_device(7, dims, 20_000, dists, "lognormal", device="cpu")
+    assert torch.equal(t.coords, t2.coords) and torch.equal(t.vals, t2.vals)
+    h = t.to_host()
+    assert h.coords.dtype == np.uint32 and h.nnz == t.nnz
+    r = synth.distinct_coo_device(8, (40, 30, 20), 3000, ["uniform"] * 3, "int1to5", device="cpu")
+    assert set(np.unique(r.vals.numpy())) <= {1.0, 2.0, 3.0, 4.0, 5.0}
