@@ -382,6 +382,55 @@ def _upload(t):
     return c, v
 
 
+def bench_layouts(args):
+    """The layout search with the paper's reward (Section III-C): for every
+    tensor, original and label-shuffled (Section IV-A), the all-mode MTTKRP time
+    of the ALTO layout and of the best layout the search finds (each mode at its
+    best plan), and their ratio, the speedup over ALTO.  Tensors: the ratings and
+    skewed 4-mode workloads, and synthetic stand-ins with the shapes of Table I
+    (nonzeros capped at --layout-nnz-cap, rank 16 as in the paper)."""
+    import torch
+    from paper_2509_00280_amd import spt, synth
+    items = []
+    for name in args.layout_tensors:
+        for shuffle in (False, True):
+            t0 = time.time()
+            if name in ("ratings", "skewed4d"):
+                t, F, rank, _ = synth.config_device(name, shuffle=shuffle)
+            else:
+                full = synth.TABLE1[name][1]
+                t, F, rank = synth.table1_config(name, nnz=min(full, args.layout_nnz_cap), device="cuda",
+                                                 shuffle=shuffle)
+            torch.cuda.synchronize()
+            gen_s = time.time() - t0
+            h = spt.encode(t.dims, t.coords, t.vals)
+            info = h.info()
+            t1 = time.time()
+            res = spt.autotune(h, F, budget_ms=args.tune_budget_ms, random_samples=args.tune_samples, seed=17)
+            rec = {"tensor": name, "shuffled": shuffle, "dims": list(t.dims), "nnz": t.nnz, "rank": rank,
+                   "key_bits": info["lp"], "alto_ms": round(res["alto_ms"], 4), "best_ms": round(res["best_ms"], 4),
+                   "speedup_vs_alto": round(res["alto_ms"] / res["best_ms"], 4),
+                   "candidates": res["candidates"], "random_samples": res["random_samples"],
+                   "layout_changed": h.info()["layout"] != info["layout"],
+                   "alto_gnnz_per_s_per_mode": round(t.nnz * t.nmodes / (res["alto_ms"] * 1e-3) / 1e9, 2),
+                   "search_s": round(time.time() - t1, 1), "generate_s": round(gen_s, 1)}
+            log(json.dumps(rec))
+            items.append(rec)
+            h.free()
+            del t, F, h
+            torch.cuda.empty_cache()
+    sp = [r["speedup_vs_alto"] for r in items]
+    geo = float(np.exp(np.mean(np.log(sp)))) if sp else None
+    out = {"metric": "all-mode MTTKRP speedup of the searched layout over ALTO", "value": round(geo, 4),
+           "unit": "x (geomean)", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded, drawn on the GPU)",
+           "config": {"workload": "layout search: ratings, skewed 4-mode and Table I-shaped tensors, original and "
+                                  "label-shuffled", "tune_budget_ms": args.tune_budget_ms,
+                      "tune_samples": args.tune_samples, "nnz_cap": args.layout_nnz_cap},
+           "tensors": items}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """256 independent tensors (3 or 4 modes, 1e4..5e6 nonzeros, Zipf(1.2)
     labels, ranks 16/32): lock-step batched CP-ALS against the plain
@@ -514,7 +563,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nnz", type=float, default=None, help="scale the tensor down (debug only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("skewed4d", "ratings", "batch", "serve"), default="skewed4d",
+    ap.add_argument("--workload", choices=("skewed4d", "ratings", "batch", "serve", "layouts"), default="skewed4d",
                     help="skewed4d: the headline, the 4-mode rank-64 tensor whose factors exceed the Infinity "
                          "Cache; ratings: the 3-mode rank-32 tensor; batch: batched vs per-tensor CP-ALS; "
                          "serve: continuous-batching server latency")
@@ -524,6 +573,9 @@ def main():
     ap.add_argument("--tuned", default=None, metavar="JSON",
                     help="use a recorded search result (layout and plan) instead of searching")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--layout-tensors", nargs="*", default=None,
+                    help="layouts workload: tensors to search (default: ratings, skewed4d and every Table I shape)")
+    ap.add_argument("--layout-nnz-cap", type=int, default=150_000_000)
     ap.add_argument("--no-extra", action="store_true", help="skip the ratings MTTKRP line")
     ap.add_argument("--torch-allocator", action="store_true",
                     help="route the library's device memory through PyTorch's caching allocator")
@@ -559,6 +611,14 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "layouts":
+        from paper_2509_00280_amd import synth
+        if args.layout_tensors is None:
+            args.layout_tensors = ["ratings", "skewed4d"] + list(synth.TABLE1)
+        if args.tune_budget_ms == 30000.0:
+            args.tune_budget_ms = 8000.0
+        bench_layouts(args)
         return
 
     bench_tensor(args)

@@ -372,53 +372,70 @@ def _draw_values_device(torch, gen, count: int, vdist, device):
 
 
 def distinct_coo_device(seed: int, dims, nnz: int, mode_dists, vdist, device="cuda", max_rounds: int = 40):
-    """``distinct_coo``'s recipe drawn with torch on ``device`` (boxes below 2^63 cells)."""
+    """``distinct_coo``'s recipe drawn with torch on ``device``.  Boxes of 2^63
+    cells or more are numbered with one int64 word per group of modes."""
     import torch
     dims = tuple(int(d) for d in dims)
-    if math.prod(dims) >= 2 ** 63:
-        raise ValueError("distinct_coo_device: the box must have fewer than 2^63 cells")
     dev = torch.device(device)
     gen = torch.Generator(device=dev)
     gen.manual_seed(int(seed))
     cdfs = [None if d == "uniform" else torch.from_numpy(zipf_cdf(n, d[1])).to(dev) for n, d in zip(dims, mode_dists)]
-    radix = []
-    r = 1
-    for d in reversed(dims):
-        radix.append(r)
-        r *= d
-    radix = list(reversed(radix))
-    kept_lin = torch.zeros(0, dtype=torch.int64, device=dev)
+    groups = _mode_groups(dims)
+    kept_c = torch.zeros((len(dims), 0), dtype=torch.int32, device=dev)
+    kept_w = [torch.zeros(0, dtype=torch.int64, device=dev) for _ in groups]
     kept_v = torch.zeros(0, dtype=torch.float32, device=dev)
     rounds = 0
-    while kept_lin.shape[0] < nnz and rounds < max_rounds:
-        deficit = nnz - kept_lin.shape[0]
+    while kept_v.shape[0] < nnz and rounds < max_rounds:
+        deficit = nnz - kept_v.shape[0]
         m = int(math.ceil(1.5 * deficit))
-        lin = torch.zeros(m, dtype=torch.int64, device=dev)
-        for n, d in enumerate(dims):
-            lin += _draw_labels_device(torch, gen, d, m, mode_dists[n], cdfs[n], dev) * radix[n]
+        c = torch.stack([_draw_labels_device(torch, gen, d, m, mode_dists[n], cdfs[n], dev).to(torch.int32)
+                         for n, d in enumerate(dims)])
         v = _draw_values_device(torch, gen, m, vdist, dev)
-        nk = kept_lin.shape[0]
-        allv = torch.cat([kept_lin, lin])
-        sv, si = torch.sort(allv, stable=True)
-        head = torch.ones(sv.shape[0], dtype=torch.bool, device=dev)
-        head[1:] = sv[1:] != sv[:-1]
-        first = si[head]
+        w = []
+        for g in groups:
+            lin = torch.zeros(m, dtype=torch.int64, device=dev)
+            for n in g:
+                lin = lin * dims[n] + c[n].to(torch.int64)
+            w.append(lin)
+        nk = kept_v.shape[0]
+        allw = [torch.cat([a, b]) for a, b in zip(kept_w, w)]
+        # lexicographic order of the words, equal keys in index order (stable sorts, last word first)
+        order = torch.arange(allw[0].shape[0], device=dev)
+        for word in reversed(allw):
+            order = order[torch.sort(word[order], stable=True).indices]
+        head = torch.ones(order.shape[0], dtype=torch.bool, device=dev)
+        if order.shape[0] > 1:
+            diff = torch.zeros(order.shape[0] - 1, dtype=torch.bool, device=dev)
+            for word in allw:
+                ws = word[order]
+                diff |= ws[1:] != ws[:-1]
+            head[1:] = diff
+        first = order[head]
         new = torch.sort(first[first >= nk] - nk).values
-        kept_lin = torch.cat([kept_lin, lin[new]])
+        kept_c = torch.cat([kept_c, c[:, new]], dim=1)
+        kept_w = [torch.cat([a, b[new]]) for a, b in zip(kept_w, w)]
         kept_v = torch.cat([kept_v, v[new]])
-        del allv, sv, si, head, first, new, lin, v
+        del allw, order, head, first, new, c, v, w
         rounds += 1
-    kept_lin = kept_lin[:nnz]
-    kept_v = kept_v[:nnz].contiguous()
-    coords = torch.empty((len(dims), kept_lin.shape[0]), dtype=torch.int32, device=dev)
-    rem = kept_lin
-    for n in range(len(dims)):
-        coords[n] = (rem // radix[n]).to(torch.int32)
-        rem = rem % radix[n]
-    return DeviceCOO(dims, coords, kept_v,
-                     meta={"seed": seed, "rounds": rounds, "realized_nnz": int(kept_v.shape[0]),
+    coords = kept_c[:, :nnz].contiguous()
+    return DeviceCOO(dims, coords, kept_v[:nnz].contiguous(),
+                     meta={"seed": seed, "rounds": rounds, "realized_nnz": int(coords.shape[1]),
                            "requested_nnz": int(nnz), "mode_dists": list(mode_dists), "vdist": vdist,
                            "generator": f"torch {dev.type}"})
+
+
+def shuffle_labels_device(t: DeviceCOO, seed: int) -> DeviceCOO:
+    """``shuffle_labels`` with torch on the tensor's device: an independent uniform
+    permutation of the labels of every mode (the shuffled experiments, Section IV-A)."""
+    import torch
+    dev = t.coords.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    c = torch.empty_like(t.coords)
+    for n, d in enumerate(t.dims):
+        p = torch.randperm(d, generator=gen, device=dev).to(torch.int32)
+        c[n] = p[t.coords[n].long()]
+    return DeviceCOO(t.dims, c, t.vals.clone(), meta=dict(t.meta, shuffled=seed))
 
 
 def normal_factors_device(seed: int, dims, rank: int, device="cuda") -> list:
@@ -430,14 +447,61 @@ def normal_factors_device(seed: int, dims, rank: int, device="cuda") -> list:
     return [torch.randn((int(d), rank), generator=gen, device=dev, dtype=torch.float32) for d in dims]
 
 
-def config_device(name: str, device="cuda", nnz: int | None = None):
+# Shapes and nonzero counts of the sparse tensors of the paper's evaluation
+# (Table I), for synthetic stand-ins: the data sets themselves are not used.
+TABLE1 = {
+    "darpa": ((22_500, 22_500, 23_800_000), 28_400_000),
+    "fb-m": ((23_300_000, 23_300_000, 166), 99_600_000),
+    "flickr-4d": ((319_700, 28_200_000, 1_600_000, 731), 112_900_000),
+    "flickr-3d": ((319_700, 28_200_000, 1_600_000), 112_900_000),
+    "deli-4d": ((532_900, 17_300_000, 2_500_000, 1_400), 140_100_000),
+    "deli-3d": ((532_900, 17_300_000, 2_500_000), 140_100_000),
+    "nell-1": ((2_900_000, 2_100_000, 25_500_000), 143_600_000),
+    "amazon": ((4_800_000, 1_800_000, 1_800_000), 1_700_000_000),
+    "patents": ((46, 239_200, 239_200), 3_600_000_000),
+    "reddit": ((8_200_000, 177_000, 8_100_000), 4_700_000_000),
+}
+TABLE1_SEED = 11
+
+
+def table1_config(name: str, nnz: int | None = None, rank: int = 16, zipf_s: float = 1.1, device=None,
+                  shuffle: bool = False):
+    """A synthetic stand-in for one Table I tensor: its mode lengths, ``nnz``
+    distinct nonzeros (default: its count), Zipf(s) labels on every mode (the
+    power-law mode distributions of such data; the paper gives shapes and
+    counts only), U(0,1) values, rank-16 N(0,1) factors (the paper's rank).
+    ``device`` None draws with NumPy; else with torch on that device.
+    Returns (tensor, factors, rank)."""
+    dims, full = TABLE1[name]
+    n = full if nnz is None else int(nnz)
+    idx = list(TABLE1).index(name)
+    ss = np.random.SeedSequence([TABLE1_SEED, idx])
+    s_t, s_f, s_sh = (int(x.generate_state(1)[0]) for x in ss.spawn(3))
+    dists = [("zipf", zipf_s)] * len(dims)
+    if device is None:
+        t = distinct_coo(s_t, dims, n, dists, "u01")
+        if shuffle:
+            t = shuffle_labels(t, s_sh)
+        F = normal_factors(s_f, dims, rank)
+    else:
+        t = distinct_coo_device(s_t, dims, n, dists, "u01", device)
+        if shuffle:
+            t = shuffle_labels_device(t, s_sh)
+        F = normal_factors_device(s_f, dims, rank, device)
+    t.meta["table1"] = name
+    return t, F, rank
+
+
+def config_device(name: str, device="cuda", nnz: int | None = None, shuffle: bool = False):
     """``config``'s workloads drawn with torch on ``device``.  Returns (DeviceCOO, factors, rank, iters)."""
     seed, dims, full_nnz, dists, vdist, rank, iters = _CONFIGS[name]
     if dists is None:
         raise ValueError("config_device: the small workload is drawn by ``config``")
     n = full_nnz if nnz is None else int(nnz)
     ss = np.random.SeedSequence(seed)
-    s_t, s_f, _ = (int(x.generate_state(1)[0]) for x in ss.spawn(3))
+    s_t, s_f, s_sh = (int(x.generate_state(1)[0]) for x in ss.spawn(3))
     t = distinct_coo_device(s_t, dims, n, dists, vdist, device)
+    if shuffle:
+        t = shuffle_labels_device(t, s_sh)
     t.meta["config"] = name
     return t, normal_factors_device(s_f, dims, rank, device), rank, iters

@@ -61,3 +61,25 @@ def cpd_error(F_got, lam_got, F_ref, lam_ref):
 def to_host(F):
     """Device factors to float32 numpy arrays."""
     return [f.detach().cpu().numpy() for f in F]
+
+
+def mttkrp_error_compact(t, factors, mode, got):
+    """mttkrp_error for tensors with huge modes: the oracle runs on the tensor with
+    every mode relabelled to its touched rows (factor rows taken along), which
+    gives the same rows; every untouched output row must be exactly zero."""
+    coords = np.empty_like(t.coords)
+    F = []
+    for k in range(t.nmodes):
+        u, inv = np.unique(t.coords[k], return_inverse=True)
+        coords[k] = inv.astype(np.uint32)
+        F.append(np.ascontiguousarray(factors[k][u]))
+        if k == mode:
+            rows = u
+    dims = [f.shape[0] for f in F]
+    ref = oracle.mttkrp(coords, t.vals, dims, F, mode)
+    scale = oracle.mttkrp(coords, np.abs(t.vals), dims, [np.abs(f) for f in F], mode)
+    err, bad = oracle.row_error(got[rows], ref, scale)
+    mask = np.ones(got.shape[0], dtype=bool)
+    mask[rows] = False
+    bad += int(np.count_nonzero(np.abs(got[mask]).max(axis=1, initial=0.0) != 0)) if mask.any() else 0
+    return err, bad

@@ -100,3 +100,30 @@ def test_device_generator_recipe_on_cpu():
     assert h.coords.dtype == np.uint32 and h.nnz == t.nnz
     r = synth.distinct_coo_device(8, (40, 30, 20), 3000, ["uniform"] * 3, "int1to5", device="cpu")
     assert set(np.unique(r.vals.numpy())) <= {1.0, 2.0, 3.0, 4.0, 5.0}
+
+
+def test_device_generator_wide_box_and_shuffle_on_cpu():
+    """Boxes of 2^63 cells or more dedup on two words; the shuffle is a per-mode bijection."""
+    import torch
+    from paper_2509_00280_amd import synth
+    dims = (3_000_000, 2_500_000, 1_000_000, 4_000)  # 3e22 cells
+    t = synth.distinct_coo_device(5, dims, 30_000, [("zipf", 1.2)] * 4, "u01", device="cpu")
+    c = t.coords.numpy().astype(np.int64)
+    keys = set(zip(*c))
+    assert t.nnz == 30_000 and len(keys) == t.nnz
+    s = synth.shuffle_labels_device(t, 9)
+    cs = s.coords.numpy().astype(np.int64)
+    for n in range(4):
+        pairs = set(zip(c[n], cs[n]))
+        assert len({a for a, _ in pairs}) == len(pairs) == len({b for _, b in pairs})  # a bijection on used labels
+    assert torch.equal(s.vals, t.vals)
+
+
+def test_table1_shapes():
+    from paper_2509_00280_amd import synth
+    assert len(synth.TABLE1) == 10
+    t, F, R = synth.table1_config("flickr-4d", nnz=5000)
+    assert t.dims == (319_700, 28_200_000, 1_600_000, 731) and t.nnz == 5000 and R == 16
+    assert [f.shape for f in F] == [(d, 16) for d in t.dims]
+    wide = [n for n, (d, _) in synth.TABLE1.items() if sum((x - 1).bit_length() for x in d) > 64]
+    assert sorted(wide) == sorted(["flickr-4d", "flickr-3d", "deli-4d", "deli-3d", "nell-1", "amazon"])
