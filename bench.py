@@ -375,6 +375,47 @@ def summarize_profiles(d: str, workload: str = "skewed4d"):
     print("\n".join(lines + [""] + out + [""] + cl))
 
 
+def summarize_f64(d: str, fetch_factor: float = 2.0, write_factor: float = 1.0):
+    """profiles/mttkrp_f64_table3_traffic.txt from the FETCH_SIZE and WRITE_SIZE runs of
+    ``bench.py --workload f64 --f64-reps 1`` under d (calibration factors of a plain
+    1 GiB device copy on the same GPU, as in the skewed tensor's traffic summary)."""
+    out = json.load(open(os.path.join(d, "bench.json")))
+    items = out["tensors"]
+    res = {}
+    for c, fac in (("FETCH_SIZE", fetch_factor), ("WRITE_SIZE", write_factor)):
+        calls = _call_windows(_read_csv(os.path.join(d, c, "p_counter_collection.csv")),
+                              lambda r: float(r["Counter_Value"]))
+        pos = 0
+        for it in items:
+            n = 2 * len(it["dims"])  # one warm-up call and one timed call per mode
+            sel = calls[pos:pos + n]
+            pos += n
+            res.setdefault(it["tensor"], {})[c] = sum(x[0] for x in sel) / len(sel) * 1024 * fac
+    lines = ["# FP64 MTTKRP (FP64 values and factors, rank 16: the paper's precision) on synthetic stand-ins",
+             "# with the Table I shapes of the three tensors of Table III, measured HBM bytes per nonzero and mode",
+             "# beside Table III's memory volumes per nonzero and mode (GB / (nnz x 3), CPU, ReLATE / ALTO).",
+             "# commands (each its own run): cd /tmp && export TMPDIR=/tmp; cd <repo>;",
+             "#   python -u bench.py --workload f64",
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/f64/FETCH_SIZE -o p -- "
+             "python -u bench.py --workload f64 --f64-reps 1",
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/f64/WRITE_SIZE -o p -- "
+             "python -u bench.py --workload f64 --f64-reps 1",
+             f"# byte factors: FETCH_SIZE KiB x {fetch_factor}, WRITE_SIZE KiB x {write_factor} (1 GiB copy calibration)",
+             f"# source_digest: {source_digest()}", "",
+             f"{'tensor':8s} {'nnz':>10s} {'Gnnz/s/mode':>11s} {'alg B/nnz':>9s} {'meas B/nnz':>10s} "
+             f"{'Table III ReLATE / ALTO B/nnz':>30s}"]
+    for it in items:
+        r = res[it["tensor"]]
+        meas = (r["FETCH_SIZE"] + r["WRITE_SIZE"]) / it["nnz"]
+        g = np.mean([m["gnnz_per_s"] for m in it["per_mode"].values()])
+        t3 = it["paper_table3_bytes_per_nnz_mode_relate_alto"]
+        lines.append(f"{it['tensor']:8s} {it['nnz']:10d} {g:11.2f} {it['algorithmic_bytes_per_nnz_mode']:9.2f} "
+                     f"{meas:10.2f} {t3[0]:>17.1f} / {t3[1]:<10.1f}")
+    with open(os.path.join(ROOT, "profiles", "mttkrp_f64_table3_traffic.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _upload(t):
     import torch
     c = torch.from_numpy(np.ascontiguousarray(t.coords).view(np.int32)).cuda()
@@ -427,6 +468,73 @@ def bench_layouts(args):
            "config": {"workload": "layout search: ratings, skewed 4-mode and Table I-shaped tensors, original and "
                                   "label-shuffled", "tune_budget_ms": args.tune_budget_ms,
                       "tune_samples": args.tune_samples, "nnz_cap": args.layout_nnz_cap},
+           "tensors": items}
+    print(json.dumps(out), flush=True)
+
+
+# Table III of the paper: memory volume of one all-mode MTTKRP iteration per
+# nonzero and mode (GB / (nnz x 3), FP64, CPU; the unit is the survey's reading)
+TABLE3_BYTES_PER_NNZ_MODE = {"deli-3d": (125.8, 222.3), "patents": (16.4, 16.3), "reddit": (31.1, 50.8)}
+
+
+def bench_f64(args):
+    """FP64 MTTKRP (the paper's precision: FP64 values and factors, rank 16) on
+    synthetic stand-ins with the Table I shapes whose memory volumes Table III
+    prints, next to those volumes (ReLATE / ALTO on the paper's CPU)."""
+    import torch
+    from paper_2509_00280_amd import spt, synth
+    items = []
+    for name in args.f64_tensors:
+        full = synth.TABLE1[name][1]
+        t, F32, rank = synth.table1_config(name, nnz=min(full, args.layout_nnz_cap), device="cuda")
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1234)
+        vals64 = torch.rand(t.nnz, generator=gen, device="cuda", dtype=torch.float64)
+        F = [f.to(torch.float64) for f in F32]
+        h = spt.encode(t.dims, t.coords, t.vals)
+        spt.attach_f64(h, vals64)
+        h.prepare(rank)
+        outs = [torch.empty((d, rank), dtype=torch.float64, device="cuda") for d in t.dims]
+        for n in range(t.nmodes):
+            spt.mttkrp_f64(h, F, n, out=outs[n])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        per = {}
+        tot = 0.0
+        for n in range(t.nmodes):
+            e0.record()
+            for _ in range(args.f64_reps):
+                spt.mttkrp_f64(h, F, n, out=outs[n])
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / args.f64_reps
+            tot += ms
+            per[str(n)] = {"ms": round(ms, 4), "gnnz_per_s": round(t.nnz / (ms * 1e-3) / 1e9, 3)}
+        # compulsory bytes of an FP64 call: 8 B key + 8 B value per nonzero, touched factor rows and the output
+        kw = 8 if sum((int(d) - 1).bit_length() for d in t.dims) <= 64 else 16
+        alg = []
+        for n in range(t.nmodes):
+            b = t.nnz * (kw + 8) + int(t.dims[n]) * rank * 8
+            for k, d in enumerate(t.dims):
+                if k != n:
+                    seen = torch.zeros(int(d), dtype=torch.bool, device="cuda")
+                    seen[t.coords[k].long()] = True
+                    b += int(seen.sum().item()) * rank * 8
+            alg.append(b)
+        rec = {"tensor": name, "dims": list(t.dims), "nnz": t.nnz, "rank": rank, "per_mode": per,
+               "all_mode_ms": round(tot, 4),
+               "algorithmic_bytes_per_nnz_mode": round(sum(alg) / len(alg) / t.nnz, 2),
+               "paper_table3_bytes_per_nnz_mode_relate_alto": TABLE3_BYTES_PER_NNZ_MODE.get(name)}
+        log(json.dumps(rec))
+        items.append(rec)
+        h.free()
+        del t, F, F32, outs, vals64, h
+        torch.cuda.empty_cache()
+    out = {"metric": "FP64 MTTKRP Gnnz/s per mode", "unit": "Gnnz/s", "n_gpus": 1, "higher_is_better": True,
+           "value": round(float(np.mean([np.mean([m["gnnz_per_s"] for m in r["per_mode"].values()]) for r in items])), 3),
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded, drawn on the GPU)",
+           "config": {"workload": "FP64 MTTKRP on Table I-shaped stand-ins " + ", ".join(args.f64_tensors),
+                      "nnz_cap": args.layout_nnz_cap},
            "tensors": items}
     print(json.dumps(out), flush=True)
 
@@ -563,7 +671,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nnz", type=float, default=None, help="scale the tensor down (debug only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("skewed4d", "ratings", "batch", "serve", "layouts"), default="skewed4d",
+    ap.add_argument("--workload", choices=("skewed4d", "ratings", "batch", "serve", "layouts", "f64"),
+                    default="skewed4d",
                     help="skewed4d: the headline, the 4-mode rank-64 tensor whose factors exceed the Infinity "
                          "Cache; ratings: the 3-mode rank-32 tensor; batch: batched vs per-tensor CP-ALS; "
                          "serve: continuous-batching server latency")
@@ -576,6 +685,8 @@ def main():
     ap.add_argument("--layout-tensors", nargs="*", default=None,
                     help="layouts workload: tensors to search (default: ratings, skewed4d and every Table I shape)")
     ap.add_argument("--layout-nnz-cap", type=int, default=150_000_000)
+    ap.add_argument("--f64-tensors", nargs="*", default=["deli-3d", "patents", "reddit"])
+    ap.add_argument("--f64-reps", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true", help="skip the ratings MTTKRP line")
     ap.add_argument("--torch-allocator", action="store_true",
                     help="route the library's device memory through PyTorch's caching allocator")
@@ -590,7 +701,10 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, args.workload)
+        if args.workload == "f64":
+            summarize_f64(args.summarize_profiles)
+        else:
+            summarize_profiles(args.summarize_profiles, args.workload)
         return
     if args.copy_calibration:
         import torch
@@ -611,6 +725,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "f64":
+        bench_f64(args)
         return
     if args.workload == "layouts":
         from paper_2509_00280_amd import synth

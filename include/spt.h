@@ -237,6 +237,27 @@ spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int m
 spt_status spt_mttkrp_noalloc(spt_tensor t, const float *const *factors, int rank, int mode, float *out,
                               void *stream);
 
+/*
+ * FP64 values for the FP64 MTTKRP (the paper's precision: FP64 values and
+ * factors, 64-bit keys; Section IV-A).  vals: device, nnz FP64 values in the
+ * caller's input order (the order of spt_encode's coords); they are copied
+ * into key order.  Replaces earlier FP64 values; spt_autotune keeps them.
+ * Asynchronous.  Errors: SPT_E_INVALID_ARG, SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_tensor_attach_f64(spt_tensor t, const double *vals, void *stream);
+
+/*
+ * spt_mttkrp in FP64: out[i_mode, :] += v * prod_{k != mode} factors[k][i_k, :]
+ * with FP64 values (spt_tensor_attach_f64), FP64 factors (host array of
+ * device pointers, row-major I_k x rank) and FP64 accumulation into out
+ * (device, I_mode x rank, overwritten).  It runs the tensor's SEGMENT plan
+ * (the mode's strategy must be SEGMENT or AUTO; the tensor prepared) with
+ * FP64 records.  Asynchronous and free of synchronisation.
+ * 1 <= rank <= SPT_MAX_RANK.  Errors: SPT_E_INVALID_ARG, SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_mttkrp_f64(spt_tensor t, const double *const *factors, int rank, int mode, double *out,
+                          void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* CP-ALS (Section II-B; the update follows Kolda and Bader's ALS).        */
 /* ---------------------------------------------------------------------- */

@@ -61,6 +61,8 @@ def _lib():
             ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.oracle_mttkrp_f64vals.restype = ctypes.c_int
+        lib.oracle_mttkrp_f64vals.argtypes = lib.oracle_mttkrp.argtypes
         _LIB = lib
     return _LIB
 
@@ -217,6 +219,26 @@ def mttkrp(coords: np.ndarray, vals: np.ndarray, dims, factors, mode: int) -> np
                               out.ctypes.data)
     if rc != 0:
         raise ValueError(f"oracle_mttkrp failed ({rc})")
+    return out
+
+
+def mttkrp_f64vals(coords: np.ndarray, vals: np.ndarray, dims, factors, mode: int) -> np.ndarray:
+    """``mttkrp`` with FP64 values (the paper's precision), see ``oracle.c``."""
+    dims_a = (ctypes.c_int64 * len(dims))(*[int(d) for d in dims])
+    coords = np.ascontiguousarray(coords, dtype=np.uint32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    f64 = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+    rank = int(f64[0].shape[1])
+    for n, f in enumerate(f64):
+        if f.shape != (int(dims[n]), rank):
+            raise ValueError("factor shape mismatch")
+    ptrs = (ctypes.c_void_p * len(f64))(*[f.ctypes.data for f in f64])
+    out = np.empty((int(dims[mode]), rank), dtype=np.float64)
+    nnz = int(vals.shape[0])
+    rc = _lib().oracle_mttkrp_f64vals(len(dims), dims_a, nnz, coords.ctypes.data if nnz else None,
+                                      vals.ctypes.data if nnz else None, ptrs, rank, int(mode), out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_mttkrp_f64vals failed ({rc})")
     return out
 
 

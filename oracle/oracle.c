@@ -54,3 +54,36 @@ int oracle_mttkrp(int nmodes, const int64_t *dims, int64_t nnz,
     free(row);
     return 0;
 }
+
+/*
+ * The same definition with FP64 values (the paper's precision, Section IV-A:
+ * FP64 values and factors).  Identical loops; only the value type differs.
+ */
+int oracle_mttkrp_f64vals(int nmodes, const int64_t *dims, int64_t nnz,
+                          const uint32_t *coords, const double *vals,
+                          const double *const *factors, int rank, int mode,
+                          double *out)
+{
+    if (nmodes < 1 || mode < 0 || mode >= nmodes || rank < 1)
+        return -1;
+    memset(out, 0, sizeof(double) * (size_t)dims[mode] * (size_t)rank);
+    double *row = (double *)malloc(sizeof(double) * (size_t)rank);
+    if (!row)
+        return -2;
+    for (int64_t e = 0; e < nnz; ++e) {
+        for (int r = 0; r < rank; ++r)
+            row[r] = vals[e];
+        for (int k = 0; k < nmodes; ++k) {
+            if (k == mode)
+                continue;
+            const double *f = factors[k] + (int64_t)coords[(int64_t)k * nnz + e] * rank;
+            for (int r = 0; r < rank; ++r)
+                row[r] *= f[r];
+        }
+        double *o = out + (int64_t)coords[(int64_t)mode * nnz + e] * rank;
+        for (int r = 0; r < rank; ++r)
+            o[r] += row[r];
+    }
+    free(row);
+    return 0;
+}

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspt.so")
-SOURCES = ["api.cpp", "plan.cpp", "encode.hip", "mttkrp.hip", "mttkrp_table.hip", "mttkrp_seg.hip", "dense.hip", "batch.cpp", "server.cpp", "tune.cpp"]
+SOURCES = ["api.cpp", "plan.cpp", "encode.hip", "mttkrp.hip", "mttkrp_table.hip", "mttkrp_seg.hip", "mttkrp_f64.hip", "dense.hip", "batch.cpp", "server.cpp", "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-munsafe-fp-atomics",

@@ -377,6 +377,7 @@ void tensor_release(Tensor *t, hipStream_t s) {
     dev_free(t->lo, s);
     dev_free(t->hi, s);
     dev_free(t->vals, s);
+    dev_free(t->vals64, s);
     dev_free(t->perm, s);
     delete static_cast<spt_tensor_s *>(t);
 }
@@ -395,6 +396,33 @@ spt_status spt_mttkrp(spt_tensor t, const float *const *factors, int rank, int m
     spt_status st = check_factors(t, factors, rank, mode);
     if (st != SPT_OK) return st;
     return run_mttkrp(t, factors, rank, mode, out, (hipStream_t)stream);
+}
+
+spt_status spt_tensor_attach_f64(spt_tensor t, const double *vals, void *stream) {
+    if (!t || (t->nnz > 0 && !vals)) return fail(SPT_E_INVALID_ARG, "attach_f64: NULL argument");
+    if (t->nnz == 0) return SPT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double *v = (double *)dev_alloc(sizeof(double) * t->nnz, s);
+    if (!v) return fail(SPT_E_OOM, "attach_f64: values");
+    // key order: element j is the input element perm[j]
+    spt_status st = launch_gather_f64(vals, t->perm, v, t->nnz, s);
+    if (st != SPT_OK) {
+        dev_free(v, s);
+        return st;
+    }
+    dev_free(t->vals64, s);
+    t->vals64 = v;
+    return SPT_OK;
+}
+
+spt_status spt_mttkrp_f64(spt_tensor t, const double *const *factors, int rank, int mode, double *out, void *stream) {
+    if (!t) return fail(SPT_E_INVALID_ARG, "NULL tensor");
+    if (mode < 0 || mode >= t->nmodes) return fail(SPT_E_INVALID_ARG, "mode out of range");
+    if (rank < 1 || rank > SPT_MAX_RANK) return fail(SPT_E_INVALID_ARG, "rank must be in 1..256");
+    if (!out || !aligned16(out)) return fail(SPT_E_INVALID_ARG, "out is NULL or not 16-byte aligned");
+    spt_status st = check_factors(t, (const float *const *)factors, rank, mode);
+    if (st != SPT_OK) return st;
+    return run_mttkrp_f64(t, factors, rank, mode, out, (hipStream_t)stream);
 }
 
 spt_status spt_mttkrp_noalloc(spt_tensor t, const float *const *factors, int rank, int mode, float *out,

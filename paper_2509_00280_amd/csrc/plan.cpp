@@ -562,6 +562,43 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
 
 }  // namespace spt
 
+namespace spt {
+// FP64 MTTKRP over the tensor's SEGMENT plan with call-owned FP64 records.
+spt_status run_mttkrp_f64(Tensor *t, const double *const *factors, int rank, int mode, double *out, hipStream_t s) {
+    if (!t->vals64 && t->nnz > 0) return fail(SPT_E_INVALID_ARG, "mttkrp_f64: no FP64 values (spt_tensor_attach_f64)");
+    ModePlan *p = nullptr;
+    spt_status st = resolve_plan(t, mode, rank, s, &p, false);
+    if (st != SPT_OK) return st;
+    if (p->strategy != SPT_STRATEGY_SEGMENT)
+        return fail(SPT_E_INVALID_ARG, "mttkrp_f64: runs the SEGMENT plan (strategy SEGMENT or AUTO)");
+    const int64_t rows = t->dims[mode];
+    if (t->nnz == 0) return launch_fill_zero((float *)out, 2 * rows * (int64_t)rank, s);  // FP64 zeros: zero bits
+    if (!f64_tile_ok(p->ts, t->nmodes)) return fail(SPT_E_INVALID_ARG, "mttkrp_f64: the plan's tile does not fit LDS");
+    MttkrpArgs a = make_args(t, nullptr, rank, mode, nullptr, p->ts);
+    a.pl_pos = p->pl_pos;
+    a.pl_off = p->pl_off;
+    a.pl_desc = p->pl_desc;
+    a.pl_row = p->pl_row;
+    a.pl_dest = p->pl_dest;
+    a.rec_cap = p->records;
+    const size_t n1 = (size_t)std::max<int64_t>(p->records, 1);
+    uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s);
+    double *rval = (double *)dev_alloc(sizeof(double) * n1 * rank, s);
+    if (!rrow || !rval) {
+        dev_free(rrow, s);
+        dev_free(rval, s);
+        return fail(SPT_E_OOM, "mttkrp_f64: record workspace");
+    }
+    a.rec_row = rrow;
+    st = launch_mttkrp_seg_f64(a, t->vals64, factors, rval, s);
+    if (st == SPT_OK) st = launch_fill_zero((float *)out, 2 * rows * (int64_t)rank, s);
+    if (st == SPT_OK) st = launch_reduce_records_f64(rrow, rval, p->records, rank, rows, out, s);
+    dev_free(rrow, s);
+    dev_free(rval, s);
+    return st;
+}
+}  // namespace spt
+
 // ---------------------------------------------------------------- no-allocation MTTKRP
 // For callers that cannot allocate device memory (code under graph capture,
 // tight serving loops): the record workspace of the SEGMENT strategy lives in

@@ -92,6 +92,7 @@ struct Tensor {
     uint64_t *lo = nullptr;   // nnz key words (bits 0..63)
     uint64_t *hi = nullptr;   // nnz key words (bits 64..127), only when key_words == 2
     float *vals = nullptr;    // nnz values in key order
+    double *vals64 = nullptr; // nnz FP64 values in key order (spt_tensor_attach_f64), else null
     uint32_t *perm = nullptr; // input index of each element
     double norm_x2 = 0.0;
     spt_plan plan{};
@@ -115,6 +116,8 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 spt_status prepare_single(Tensor *t, int rank, hipStream_t s);
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's prepared plan
 spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+// FP64 MTTKRP (FP64 values, factors, records and accumulation) on the SEGMENT plan
+spt_status run_mttkrp_f64(Tensor *t, const double *const *factors, int rank, int mode, double *out, hipStream_t s);
 // the same with the record workspace in the library's fixed device array
 spt_status run_mttkrp_noalloc(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
 size_t noalloc_scratch_bytes();
@@ -196,6 +199,13 @@ spt_status launch_emit_plan(const MttkrpArgs &a, const PlanOut &o, hipStream_t s
 spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first, uint32_t *dest,
                              int64_t n, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
+// mttkrp_f64.hip
+bool f64_tile_ok(int tile, int nmodes);
+spt_status launch_mttkrp_seg_f64(const MttkrpArgs &a, const double *vals64, const double *const *F, double *rec_val,
+                                 hipStream_t s);
+spt_status launch_reduce_records_f64(const uint64_t *srow, const double *rec, int64_t P, int R, int64_t rows,
+                                     double *out, hipStream_t s);
+spt_status launch_gather_f64(const double *src, const uint32_t *idx, double *dst, int64_t n, hipStream_t s);
 // Tile dictionary of mode a.mode (tiles of kDictTile): off from the counting
 // pass (distinct rows per tile, exclusive prefix), rows and slots written.
 spt_status launch_emit_dict(const MttkrpArgs &a, const int64_t *off, uint32_t *rows, uint16_t *slots, hipStream_t s);

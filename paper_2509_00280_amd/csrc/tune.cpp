@@ -321,6 +321,12 @@ spt_status spt_autotune(spt_tensor *tp, const float *const *factors, int rank, d
         uint32_t *perm = nullptr;
         if (st == SPT_OK && !(perm = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max<int64_t>(t->nnz, 1), s)))
             st = fail(SPT_E_OOM, "autotune: perm");
+        // FP64 values follow the new key order (c->perm is still relative to t's order)
+        if (st == SPT_OK && t->vals64) {
+            c->vals64 = (double *)dev_alloc(sizeof(double) * std::max<int64_t>(t->nnz, 1), s);
+            st = c->vals64 ? launch_gather_f64(t->vals64, c->perm, c->vals64, t->nnz, s)
+                           : fail(SPT_E_OOM, "autotune: FP64 values");
+        }
         if (st == SPT_OK) st = launch_gather_u32(t->perm, c->perm, perm, t->nnz, s);
         if (st == SPT_OK && hipMemcpyAsync(c->perm, perm, sizeof(uint32_t) * t->nnz, hipMemcpyDeviceToDevice, s) != hipSuccess)
             st = hip_fail(hipGetLastError(), "autotune: perm copy");

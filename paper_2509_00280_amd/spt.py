@@ -102,6 +102,8 @@ def lib():
     _sig(L, "spt_set_allocator", st, [ALLOC_FN, RELEASE_FN, _VP])
     _sig(L, "spt_mttkrp", st, [_VP, _PP, i, i, _VP, _VP])
     _sig(L, "spt_mttkrp_noalloc", st, [_VP, _PP, i, i, _VP, _VP])
+    _sig(L, "spt_tensor_attach_f64", st, [_VP, _VP, _VP])
+    _sig(L, "spt_mttkrp_f64", st, [_VP, _PP, i, i, _VP, _VP])
     _sig(L, "spt_cp_als", st, [_VP, i, i, d, _PP, _VP, ctypes.POINTER(d), ctypes.POINTER(i), _VP])
     _sig(L, "spt_als_update", st, [_VP, i, i, i, _VP, i64, _VP, _VP, ctypes.POINTER(i), _VP])
     _sig(L, "spt_mttkrp_batched", st, [_PP, i, ctypes.POINTER(_PP), ctypes.POINTER(i), i, _PP, _VP])
@@ -365,6 +367,36 @@ def mttkrp(t: Tensor, factors, mode: int, out=None, stream=None):
         check_matrix("out", out, rows, R)
     t.ensure_prepared(R, stream)
     _check(lib().spt_mttkrp(t.handle, _ptr_array(factors), R, int(mode), _ptr(out), _stream(stream)))
+    return out
+
+
+def attach_f64(t: Tensor, vals, stream=None):
+    """Attach FP64 values (CUDA float64, input order) for ``mttkrp_f64``."""
+    nnz = t.info()["nnz"]
+    check_vector("vals", vals, nnz, "float64")
+    _check(lib().spt_tensor_attach_f64(t.handle, _ptr(vals), _stream(stream)))
+
+
+def mttkrp_f64(t: Tensor, factors, mode: int, out=None, stream=None):
+    """FP64 MTTKRP (FP64 values, factors and accumulation): factors CUDA float64 [I_k, R]."""
+    import torch
+    dims = t.info()["dims"]
+    if len(factors) != len(dims):
+        raise ValueError(f"factors: expected {len(dims)} matrices")
+    R = None
+    for k, f in enumerate(factors):
+        if f is None and k == mode:
+            continue
+        if R is None:
+            R = int(f.shape[1])
+        check_matrix(f"factor {k}", f, dims[k], R, dtype="float64")
+    rows = dims[mode] if 0 <= mode < len(dims) else 1
+    if out is None:
+        out = torch.empty((rows, R), dtype=torch.float64, device="cuda")
+    elif 0 <= mode < len(dims):
+        check_matrix("out", out, rows, R, dtype="float64")
+    t.ensure_prepared(R, stream)
+    _check(lib().spt_mttkrp_f64(t.handle, _ptr_array(factors), R, int(mode), _ptr(out), _stream(stream)))
     return out
 
 

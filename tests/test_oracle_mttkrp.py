@@ -111,3 +111,25 @@ def test_row_error_metric():
     assert abs(err - 1e-4) < 1e-12 and bad == 0
     _, bad = oracle.row_error(np.array([[1.0, -1.0], [0.0, 1e-30]]), ref, scale)
     assert bad == 1
+
+
+def test_f64_values_brute_force_and_fp32_agreement():
+    """The FP64-valued oracle: brute force (dense unfolding x Khatri-Rao) with
+    values not representable in FP32, and equality with the FP32-valued routine
+    when the values are FP32-exact."""
+    rng = np.random.default_rng(12)
+    dims = (5, 4, 3)
+    X = rng.standard_normal(dims) / 3.0            # FP64 values, not FP32-exact
+    X[rng.random(dims) < 0.4] = 0.0
+    coords = np.stack(np.nonzero(X)).astype(np.uint32)
+    vals = X[tuple(coords)]
+    F = [rng.standard_normal((d, 3)) for d in dims]
+    for mode in range(3):
+        got = oracle.mttkrp_f64vals(coords, vals, dims, F, mode)
+        others = [k for k in range(3) if k != mode]
+        Xn = np.moveaxis(X, mode, 0).reshape(dims[mode], -1)       # C order: last mode fastest
+        K = np.einsum("ir,jr->ijr", F[others[0]], F[others[1]]).reshape(-1, 3)  # forward KRP, second fastest
+        np.testing.assert_allclose(got, Xn @ K, rtol=1e-12, atol=1e-13)
+        v32 = vals.astype(np.float32)
+        np.testing.assert_array_equal(oracle.mttkrp_f64vals(coords, v32.astype(np.float64), dims, F, mode),
+                                      oracle.mttkrp(coords, v32, dims, F, mode))
