@@ -422,6 +422,19 @@ spt_status spt_server_wait(spt_server s, uint64_t ticket, double timeout_s, spt_
 /* Server clock (seconds), for callers that time arrivals. */
 double spt_server_now(spt_server s);
 
+/*
+ * The server's admission policy run against a modelled executor, on the host
+ * only (capacity planning; no device work): request i of `bytes[i]` device
+ * bytes arrives at arrive[i] (host array, sorted) and, once admitted, runs for
+ * service[i] seconds.  Admission is in arrival order while a slot is free and
+ * the bytes fit the unused budget; a request above the whole budget is
+ * rejected on reaching the head of the queue (status SPT_E_OOM).  Host
+ * outputs: admit_out[i], done_out[i] (seconds) and status_out[i].
+ */
+spt_status spt_server_simulate(size_t hbm_budget_bytes, int max_slots, int count, const size_t *bytes,
+                               const double *arrive, const double *service, double *admit_out, double *done_out,
+                               int *status_out);
+
 /* Stop accepting, finish active work, join the worker and free everything. */
 void spt_server_destroy(spt_server s);
 

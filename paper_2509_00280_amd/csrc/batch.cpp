@@ -530,10 +530,16 @@ spt_status BatchEngine::rebuild() {
     return SPT_OK;
 }
 
-spt_status BatchEngine::step() {
+void BatchEngine::drop_done() { dirty_ = true; }
+
+spt_status BatchEngine::step(bool *before_kernels) {
+    if (before_kernels) *before_kernels = false;
     if (dirty_) {
         spt_status st = rebuild();
-        if (st != SPT_OK) return st;
+        if (st != SPT_OK) {
+            if (before_kernels) *before_kernels = true;
+            return st;
+        }
     }
     const int A = (int)active_.size();
     if (A == 0) return SPT_OK;

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <utility>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -70,14 +71,38 @@ size_t estimate_bytes(const spt_request &r) {
     return b;
 }
 
+// Admission by HBM budget and free slots, in arrival order: the head request
+// is admitted when a slot is free and its bytes fit the unused budget,
+// rejected at once when it exceeds the whole budget, and otherwise waits
+// (later requests wait behind it).  Shared by the server and by
+// spt_server_simulate, which drives it with a modelled executor.
+struct AdmissionPolicy {
+    size_t budget = 0;
+    int max_slots = 1;
+    size_t used = 0;
+    int slots = 0;
+    enum Decision { WAIT, ADMIT, REJECT };
+    Decision decide(size_t bytes) const {
+        if (bytes > budget) return REJECT;
+        return (slots < max_slots && used + bytes <= budget) ? ADMIT : WAIT;
+    }
+    void admit(size_t bytes) {
+        used += bytes;
+        ++slots;
+    }
+    void release(size_t bytes) {
+        used -= bytes;
+        --slots;
+    }
+};
+
 }  // namespace
 }  // namespace spt
 
 using namespace spt;
 
 struct spt_server_s {
-    size_t budget = 0;
-    int max_slots = 1;
+    AdmissionPolicy policy;
     hipStream_t compute = nullptr, side = nullptr;
     int device = 0;
     std::chrono::steady_clock::time_point t0;
@@ -86,8 +111,6 @@ struct spt_server_s {
     std::deque<std::shared_ptr<Job>> pending, ready;
     std::map<uint64_t, std::shared_ptr<Job>> jobs;
     uint64_t next_ticket = 1;
-    size_t used = 0;
-    int slots = 0;
     bool stop = false;
     std::thread admit_thr, work_thr;
 
@@ -161,18 +184,14 @@ struct spt_server_s {
                 cv_admit.wait(lk, [&] {
                     if (stop && pending.empty()) return true;
                     if (pending.empty()) return false;
-                    const auto &h = pending.front();
-                    return h->bytes > budget || (slots < max_slots && used + h->bytes <= budget);
+                    return policy.decide(pending.front()->bytes) != AdmissionPolicy::WAIT;
                 });
                 if (pending.empty()) return;  // stopping
                 j = pending.front();
                 pending.pop_front();
-                if (j->bytes <= budget) {
-                    used += j->bytes;
-                    ++slots;
-                }
+                if (policy.decide(j->bytes) == AdmissionPolicy::ADMIT) policy.admit(j->bytes);
             }
-            if (j->bytes > budget) {
+            if (j->bytes > policy.budget) {
                 set_error("server: request exceeds the HBM budget");
                 finish(j, SPT_E_OOM);
                 continue;
@@ -184,8 +203,7 @@ struct spt_server_s {
                 release_device(*j, side);
                 {
                     std::lock_guard<std::mutex> lk(mu);
-                    used -= j->bytes;
-                    --slots;
+                    policy.release(j->bytes);
                 }
                 cv_admit.notify_all();
                 finish(j, st);
@@ -207,7 +225,7 @@ struct spt_server_s {
             std::vector<std::shared_ptr<Job>> joining;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return !ready.empty() || !active.empty() || (stop && pending.empty() && slots == 0); });
+                cv_work.wait(lk, [&] { return !ready.empty() || !active.empty() || (stop && pending.empty() && policy.slots == 0); });
                 if (ready.empty() && active.empty()) return;  // stopping, nothing left
                 while (!ready.empty()) {
                     joining.push_back(ready.front());
@@ -232,11 +250,25 @@ struct spt_server_s {
                 active.push_back(j);
             }
             if (eng.any_active()) {
-                spt_status st = eng.step();
+                bool before_kernels = false;
+                spt_status st = eng.step(&before_kernels);
+                if (st != SPT_OK && before_kernels && !joining.empty()) {
+                    // the step failed while re-planning for the requests that just
+                    // joined (e.g. their workspace does not fit): those requests
+                    // retire with the error, the others run the step without them
+                    for (auto &j : joining) {
+                        if (j->m.done) continue;
+                        j->m.done = true;
+                        j->m.err = st;
+                    }
+                    eng.drop_done();
+                    st = eng.step(&before_kernels);
+                }
                 if (st != SPT_OK)
                     for (auto &j : active) {
+                        if (j->m.done) continue;
                         j->m.done = true;
-                        if (j->m.err == SPT_OK) j->m.err = st;
+                        j->m.err = st;
                     }
             }
             std::vector<std::shared_ptr<Job>> still;
@@ -272,8 +304,7 @@ struct spt_server_s {
         release_device(j, compute);
         {
             std::lock_guard<std::mutex> lk(mu);
-            used -= j.bytes;
-            --slots;
+            policy.release(j.bytes);
             j.res.status = st;
             j.res.t_done = now();
             j.finished = true;
@@ -290,8 +321,8 @@ spt_status spt_server_create(size_t hbm_budget_bytes, int max_slots, spt_server 
     if (!out || max_slots < 1 || hbm_budget_bytes == 0) return fail(SPT_E_INVALID_ARG, "server: bad arguments");
     auto *s = new (std::nothrow) spt_server_s();
     if (!s) return fail(SPT_E_OOM, "server: host allocation");
-    s->budget = hbm_budget_bytes;
-    s->max_slots = max_slots;
+    s->policy.budget = hbm_budget_bytes;
+    s->policy.max_slots = max_slots;
     s->t0 = std::chrono::steady_clock::now();
     if (hipGetDevice(&s->device) != hipSuccess ||
         hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess ||
@@ -367,6 +398,62 @@ spt_status spt_server_wait(spt_server s, uint64_t ticket, double timeout_s, spt_
 }
 
 double spt_server_now(spt_server s) { return s ? s->now() : 0.0; }
+
+spt_status spt_server_simulate(size_t hbm_budget_bytes, int max_slots, int count, const size_t *bytes,
+                               const double *arrive, const double *service, double *admit_out, double *done_out,
+                               int *status_out) {
+    if (max_slots < 1 || hbm_budget_bytes == 0 || count < 0 ||
+        (count > 0 && (!bytes || !arrive || !service || !admit_out || !done_out || !status_out)))
+        return fail(SPT_E_INVALID_ARG, "server_simulate: bad arguments");
+    for (int i = 1; i < count; ++i)
+        if (arrive[i] < arrive[i - 1]) return fail(SPT_E_INVALID_ARG, "server_simulate: arrivals must be sorted");
+    AdmissionPolicy pol;
+    pol.budget = hbm_budget_bytes;
+    pol.max_slots = max_slots;
+    // the modelled executor: an admitted request finishes `service` seconds later
+    std::multimap<double, int> running;  // done time -> request
+    std::deque<int> queue;
+    int next = 0;
+    double now = 0.0;
+    std::vector<double> admit(count, 0.0), done(count, 0.0);
+    std::vector<int> status(count, SPT_OK);
+    while (next < count || !queue.empty() || !running.empty()) {
+        // admit from the queue head while the policy allows at the current time
+        while (!queue.empty()) {
+            const int h = queue.front();
+            const auto d = pol.decide(bytes[h]);
+            if (d == AdmissionPolicy::WAIT) break;
+            queue.pop_front();
+            admit[h] = now;
+            if (d == AdmissionPolicy::REJECT) {
+                status[h] = SPT_E_OOM;
+                done[h] = now;
+                continue;
+            }
+            pol.admit(bytes[h]);
+            running.emplace(now + service[h], h);
+        }
+        // next event: an arrival or a completion (completions first at equal times)
+        const double ta = next < count ? arrive[next] : 1e300;
+        const double tc = running.empty() ? 1e300 : running.begin()->first;
+        if (tc <= ta) {
+            now = tc;
+            const int r = running.begin()->second;
+            running.erase(running.begin());
+            done[r] = now;
+            pol.release(bytes[r]);
+        } else {
+            now = ta;
+            queue.push_back(next++);
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        admit_out[i] = admit[i];
+        done_out[i] = done[i];
+        status_out[i] = status[i];
+    }
+    return SPT_OK;
+}
 
 void spt_server_destroy(spt_server s) {
     if (!s) return;

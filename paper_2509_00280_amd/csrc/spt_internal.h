@@ -360,8 +360,12 @@ public:
     spt_status add(Member *m);
     // leaves now (the stream is synchronised first)
     void remove(Member *m);
-    // one CP-ALS iteration of every active member; synchronises the stream
-    spt_status step();
+    // one CP-ALS iteration of every active member; synchronises the stream.
+    // *before_kernels (if given) is set when a failure came before any kernel
+    // of the step was launched (while re-planning for changed members).
+    spt_status step(bool *before_kernels = nullptr);
+    // remove the members marked done from the batch (their state is released)
+    void drop_done();
     bool any_active() const;
     const std::vector<Member *> &members() const { return members_; }
 

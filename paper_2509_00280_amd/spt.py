@@ -115,6 +115,7 @@ def lib():
     _sig(L, "spt_server_submit", st, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
     _sig(L, "spt_server_wait", st, [_VP, ctypes.c_uint64, d, ctypes.POINTER(Result), _PP, _VP])
     _sig(L, "spt_server_now", d, [_VP])
+    _sig(L, "spt_server_simulate", st, [ctypes.c_size_t, i, i, _VP, _VP, _VP, _VP, _VP, _VP])
     _sig(L, "spt_server_destroy", None, [_VP])
     _sig(L, "spt_profile_enable", st, [i])
     _sig(L, "spt_profile_read", st, [ctypes.POINTER(d), ctypes.POINTER(i64)])
@@ -608,6 +609,24 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def server_simulate(hbm_budget_bytes: int, max_slots: int, bytes_, arrive, service):
+    """The server's admission policy against a modelled executor (host only).
+    Returns (admit times, done times, statuses) as numpy arrays."""
+    b = np.ascontiguousarray(bytes_, dtype=np.uint64)
+    a = np.ascontiguousarray(arrive, dtype=np.float64)
+    sv = np.ascontiguousarray(service, dtype=np.float64)
+    n = int(b.shape[0])
+    if a.shape != (n,) or sv.shape != (n,):
+        raise ValueError("bytes, arrive and service must have one entry per request")
+    adm = np.empty(n, np.float64)
+    done = np.empty(n, np.float64)
+    stt = np.empty(n, np.int32)
+    _check(lib().spt_server_simulate(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_slots), n,
+                                     b.ctypes.data, a.ctypes.data, sv.ctypes.data, adm.ctypes.data,
+                                     done.ctypes.data, stt.ctypes.data))
+    return adm, done, stt
 
 
 def profile_reset(on: bool = True):

@@ -505,3 +505,21 @@ def config_device(name: str, device="cuda", nnz: int | None = None, shuffle: boo
         t = shuffle_labels_device(t, s_sh)
     t.meta["config"] = name
     return t, normal_factors_device(s_f, dims, rank, device), rank, iters
+
+
+def materialize_device(req, device="cuda"):
+    """``materialize``'s recipe (same shape draw: modes, nnz, dims, rank) with the
+    tensor and initial factors drawn by torch on ``device`` and returned on the host."""
+    kw = dict(req["batch_kw"])
+    rng = np.random.default_rng(np.random.SeedSequence([req["shape_seed"], req["index"]]))
+    lo_n, hi_n = np.log(kw.get("nnz_range", (10_000, 5_000_000))[0]), np.log(kw.get("nnz_range", (10_000, 5_000_000))[1])
+    lo_d, hi_d = np.log(kw.get("dim_range", (50, 200_000))[0]), np.log(kw.get("dim_range", (50, 200_000))[1])
+    nm = 3 if rng.random() < 0.5 else 4
+    nnz = int(np.floor(np.exp(rng.uniform(lo_n, hi_n))))
+    dims = tuple(int(np.floor(np.exp(rng.uniform(lo_d, hi_d)))) for _ in range(nm))
+    ranks = req["ranks"]
+    rank = int(ranks[int(rng.integers(0, len(ranks)))])
+    s_t, s_f = (int(x) for x in rng.integers(0, 2 ** 63 - 1, size=2))
+    t = distinct_coo_device(s_t, dims, nnz, [("zipf", kw.get("zipf_s", 1.2))] * nm, "u01", device).to_host()
+    F = [f.cpu().numpy() for f in normal_factors_device(s_f, dims, rank, device)]
+    return t, F, rank

@@ -139,3 +139,39 @@ def test_server_one_slot_tol_and_budget(spt):
     # one slot: each request is admitted only after the previous one finished
     for a, b in zip(results, results[1:]):
         assert b["t_admit"] >= a["t_done"] - 1e-6
+
+
+def test_server_isolates_failing_requests(spt):
+    """A request with an out-of-range coordinate and one with a NaN initial factor
+    retire with their errors; the requests beside them finish and match the
+    single-tensor path and the oracle."""
+    iters = 6
+    reqs = _requests(4, seed=9)
+    srv = spt.Server(8 << 30, 8)
+    try:
+        good = [srv.submit(t.dims, t.coords, t.vals, F, iters) for t, F, R in reqs[:2]]
+        t, F, R = reqs[2]
+        bad_c = t.coords.copy()
+        bad_c[1, 5] = t.dims[1]  # one coordinate out of range
+        k_range = srv.submit(t.dims, bad_c, t.vals, F, iters)
+        t, F, R = reqs[3]
+        Fn = [f.copy() for f in F]
+        Fn[1][2, 1] = np.nan  # factor 0 is overwritten before it is read; factor 1 enters mode 0's solve
+        k_nan = srv.submit(t.dims, t.coords, t.vals, Fn, iters)
+        good += [srv.submit(t.dims, t.coords, t.vals, F, iters) for t, F, R in reqs[:2]]
+        res_good = [srv.wait(k, timeout_s=60.0) for k in good]
+        r_range, _, _ = srv.wait(k_range, timeout_s=60.0)
+        r_nan, _, _ = srv.wait(k_nan, timeout_s=60.0)
+    finally:
+        srv.close()
+    assert r_range["status"] == -2 and r_nan["status"] == -6
+    for (t, F, R), (res, Fo, lam) in zip(reqs[:2] * 2, res_good):
+        assert res["status"] == 0 and res["iters"] == iters
+        h = spt.encode(t.dims, *to_dev(t))
+        Fs = factors_dev(F)
+        lam_s, fit_s, _ = spt.cp_als(h, Fs, iters)
+        e, el = cpd_error(Fo, lam, to_host(Fs), lam_s.cpu().numpy())
+        assert abs(res["fit"] - fit_s) <= TOL_FIT and e <= TOL_ROW and el <= TOL_ROW
+    t, F, R = reqs[0]
+    ref = oracle.cp_als(t.coords, t.vals, t.dims, F, iters=iters)
+    assert abs(res_good[0][0]["fit"] - ref["fit"]) <= TOL_FIT
