@@ -323,11 +323,12 @@ __global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles
             lv[b][q] = col < R ? lam[col] : 0.0;
         }
     for (int e = g; e < cnt; e += GROUPS) {
-        float p[NB][VEC];
+        // the product of the factor entries in FP64 (each FP32 entry widened first)
+        double p[NB][VEC];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) p[b][q] = 1.f;
+            for (int q = 0; q < VEC; ++q) p[b][q] = 1.0;
 #pragma unroll
         for (int k = 0; k < NMAX; ++k) {
             if (k < a.nmodes) {
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles
 #pragma unroll
                         for (int q = 0; q < VEC; ++q) x[q] = 0.f;
 #pragma unroll
-                    for (int q = 0; q < VEC; ++q) p[b][q] *= x[q];
+                    for (int q = 0; q < VEC; ++q) p[b][q] *= (double)x[q];
                 }
             }
         }
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) part += lv[b][q] * (double)p[b][q];
+            for (int q = 0; q < VEC; ++q) part += lv[b][q] * p[b][q];
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
         if (j == 0) {
