@@ -68,7 +68,8 @@ __global__ __launch_bounds__(NT) void k_mttkrp_seg_f64(MttkrpArgs a, const doubl
     constexpr int NG = NT / G;
     const int g = tid / G, j = tid % G;
     for (int k = g; k < npieces; k += NG) {
-        const uint32_t d = a.pl_desc[k0 + k], prow = a.pl_row[k0 + k], dest = a.pl_dest[k0 + k];
+        const spt_u4 pc = reinterpret_cast<const spt_u4 *>(a.pl_piece)[k0 + k];
+        const uint32_t d = pc.x, prow = pc.y, dest = pc.z;
         const int p0 = (int)(d & 0xFFFFu), p1 = min(p0 + (int)(d >> 16), T);
         if (dest >= (uint64_t)a.rec_cap || p0 >= p1) continue;
         double acc[NB];
@@ -202,6 +203,7 @@ spt_status launch_mttkrp_seg_f64(const MttkrpArgs &a, const double *vals64, cons
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
     if (ntiles == 0) return SPT_OK;
     if (!f64_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "mttkrp_f64: tile does not fit LDS");
+    if (!a.pl_pos || !a.pl_off || !a.pl_piece) return fail(SPT_E_INVALID_ARG, "mttkrp_f64: no plan");
     if (a.rank > 256) return fail(SPT_E_INVALID_ARG, "mttkrp_f64: rank above 256");
     if (a.tile == 1024) return launch_f64_n<256>(a, vals64, F, ntiles, rec_val, s);
     if (a.tile == 2048) return launch_f64_n<512>(a, vals64, F, ntiles, rec_val, s);

@@ -43,6 +43,7 @@ namespace {
 
 constexpr int kPiece = SPT_SEG_PIECE;  // nonzeros per piece (L)
 constexpr int kUnroll = SPT_SEG_UB;    // nonzeros in flight per lane group
+constexpr int kUnrollDict = 2;       // the same, row-cached walk
 #ifndef SPT_SEGP_NT4096
 #define SPT_SEGP_NT4096 1024
 #endif
@@ -219,13 +220,14 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 // mode's gathers are issued).
 // DICT: a crdg entry with kDictHit set is the LDS slot of a row held in
 // `cache` (non-output mode o, slot s at cache[(o * cap + s) * R]); any other
-// entry is a global row.
+// entry is a global row.  Every lane reads its step's rows from LDS first,
+// then the lanes whose row is global load it over the LDS value.
 template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces, bool DICT = false>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__restrict__ crdg,
                                          const float *__restrict__ valg, int npieces, const Pieces &pieces,
                                          uint64_t *__restrict__ rec_row, float *__restrict__ rec_val, int ld,
                                          int64_t row_base, const float *__restrict__ cache = nullptr, int cap = 0) {
-    constexpr int UB = kUnroll;
+    constexpr int UB = DICT ? kUnrollDict : kUnroll;
     constexpr int NO = NMAX - 1;  // non-output modes at most
     const int j = threadIdx.x % G;
     static_assert(NFIX == 0 || NFIX == NMAX, "a fixed mode count is the maximum");
@@ -286,45 +288,73 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
 #pragma unroll
                         for (int u = 0; u < UB; ++u) row[o][u] = crdg[o * T + pp[u]];
                 float xv[NO][UB][NB][VEC];
+                if constexpr (DICT) {
+                    // Every lane first reads LDS (a miss reads the last cached
+                    // row, a clamped slot), then the misses load their rows
+                    // globally into the same registers.  A global load into the
+                    // registers of an LDS read waits for that read; with all LDS
+                    // reads of the step issued first the loads wait for one LDS
+                    // round trip, and no branch splits hits from misses.
 #pragma unroll
-                for (int o = 0; o < NO; ++o) {
-                    if (o < no) {
+                    for (int o = 0; o < NO; ++o) {
 #pragma unroll
                         for (int u = 0; u < UB; ++u) {
+                            const uint32_t sl = min(row[o][u] - kDictHit, (uint32_t)(cap - 1));
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 const int c = (b * G + j) * VEC;
-                                if constexpr (DICT) {
-                                    const uint32_t rv = row[o][u];
-                                    if (EXACT || c < R) {
-                                        if (rv & kDictHit) {
-                                            // row stride: a compile-time shift when the groups cover R exactly
-                                            const int rs = EXACT ? G * VEC * NB : R;
-                                            const float *cp = cache + ((size_t)(o * cap) + (rv & ~kDictHit)) * rs + c;
-                                            if constexpr (VEC == 4) {
-                                                const float4 t4 = *reinterpret_cast<const float4 *>(cp);
-                                                xv[o][u][b][0] = t4.x;
-                                                xv[o][u][b][1] = t4.y;
-                                                xv[o][u][b][2] = t4.z;
-                                                xv[o][u][b][3] = t4.w;
-                                            } else {
+                                if (o < no && (EXACT || c < R)) {
+                                    // row stride: a compile-time shift when the groups cover R exactly
+                                    const int rs = EXACT ? G * VEC * NB : R;
+                                    const float *cp = cache + ((size_t)(o * cap) + sl) * rs + c;
+                                    if constexpr (VEC == 4) {
+                                        const float4 t4 = *reinterpret_cast<const float4 *>(cp);
+                                        xv[o][u][b][0] = t4.x;
+                                        xv[o][u][b][1] = t4.y;
+                                        xv[o][u][b][2] = t4.z;
+                                        xv[o][u][b][3] = t4.w;
+                                    } else {
 #pragma unroll
-                                                for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = cp[v];
-                                            }
-                                        } else {
-                                            load_row_vec<VEC>(fb[o], rv, c, xv[o][u][b]);
-                                        }
+                                        for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = cp[v];
+                                    }
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) {
+                        if (o < no) {
+#pragma unroll
+                            for (int u = 0; u < UB; ++u) {
+                                const uint32_t rv = row[o][u];
+#pragma unroll
+                                for (int b = 0; b < NB; ++b) {
+                                    const int c = (b * G + j) * VEC;
+                                    if (EXACT || c < R) {
+                                        if (!(rv & kDictHit)) load_row_vec<VEC>(fb[o], rv, c, xv[o][u][b]);
                                     } else {
 #pragma unroll
                                         for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
                                     }
-                                    continue;
                                 }
-                                if (EXACT || c < R) {
-                                    load_row_vec<VEC>(fb[o], row[o][u], c, xv[o][u][b]);
-                                } else {
+                            }
+                        }
+                    }
+                } else {
 #pragma unroll
-                                    for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
+                    for (int o = 0; o < NO; ++o) {
+                        if (o < no) {
+#pragma unroll
+                            for (int u = 0; u < UB; ++u) {
+#pragma unroll
+                                for (int b = 0; b < NB; ++b) {
+                                    const int c = (b * G + j) * VEC;
+                                    if (EXACT || c < R) {
+                                        load_row_vec<VEC>(fb[o], row[o][u], c, xv[o][u][b]);
+                                    } else {
+#pragma unroll
+                                        for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
+                                    }
                                 }
                             }
                         }
@@ -412,12 +442,31 @@ struct PlanPieces {
     }
 };
 
+// The same from the packed plan of one tensor: one 16-byte load per piece.
+template <int T>
+struct PackedPieces {
+    const spt_u4 *__restrict__ pk;
+    int64_t k0, cap;
+    using Raw = spt_u4;
+    __device__ __forceinline__ Raw fetch(int k) const { return pk[k0 + k]; }
+    __device__ __forceinline__ bool decode(int, const Raw &q, int &p0, int &p1, uint32_t &row, int64_t &pos) const {
+        p0 = (int)(q.x & 0xFFFFu);
+        p1 = min(p0 + (int)(q.x >> 16), T);
+        row = q.y;
+        pos = q.z;
+        return q.z < cap && p0 < p1;
+    }
+};
+
 // Planned SEGMENT kernel.  The plan holds, per nonzero, its position in the
 // tile's row-grouped order (u16) and, per piece, (start | length << 16, row,
 // record), with the records of one row contiguous.  A tile is staged by one
 // scatter of values and non-output coordinates to their positions; there is
 // no hashing, no atomic and no scan at run time.
-template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
+// PACKED: the pieces come from a.pl_piece (one tensor, records from 0);
+// otherwise from a.pl_desc / pl_row / pl_dest with records from rec_base
+// (a batched member).
+template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, bool PACKED>
 __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, char *lds, uint64_t *__restrict__ rec_row,
                                           float *__restrict__ rec_val, int ld, int64_t rec_base, int64_t row_base) {
     constexpr int PER = T / NT;  // nonzeros staged per thread
@@ -484,9 +533,14 @@ __device__ __forceinline__ void segp_tile(const MttkrpArgs &a, int64_t tile, cha
     for (int u = 0; u < PER; ++u)
         if (tid + u * NT < cnt) valg[ps[u]] = v[u];
     __syncthreads();
-    seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(a, crdg, valg, npieces,
-                                          PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, rec_base},
-                                          rec_row, rec_val, ld, row_base);
+    if constexpr (PACKED)
+        seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(
+            a, crdg, valg, npieces, PackedPieces<T>{reinterpret_cast<const spt_u4 *>(a.pl_piece), k0, a.rec_cap},
+            rec_row, rec_val, ld, row_base);
+    else
+        seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(
+            a, crdg, valg, npieces, PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, rec_base}, rec_row,
+            rec_val, ld, row_base);
 }
 
 template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
@@ -494,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp(MttkrpArgs a, int64_t ntiles
     extern __shared__ __align__(16) char lds[];
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    segp_tile<NT, T, G, VEC, NB, NMAX, NFIX, EXACT>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
+    segp_tile<NT, T, G, VEC, NB, NMAX, NFIX, EXACT, true>(a, tile, lds, a.rec_row, a.rec_val, a.rank, 0, 0);
 }
 
 // ---------------------------------------------------------------- row cache
@@ -620,24 +674,58 @@ __device__ __forceinline__ void segd_tile(const MttkrpArgs &a, int64_t tile, cha
     const int64_t base = tile * (int64_t)T;
     const int64_t rem = a.nnz - base;
     const int cnt = rem < T ? (int)rem : T;
+    // every thread stages PER consecutive nonzeros: one 16-byte load of
+    // values and one 8-byte load per u16 stream (tiles start at multiples of
+    // T, so the vectors are aligned); the last tile's ragged end goes element
+    // by element
+    static_assert(PER == 4, "row-cached staging loads 4 nonzeros per thread");
+    const int e0 = tid * PER;
     float v[PER];
     uint32_t q[PER];
     uint32_t sl[NO][PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int e = tid + u * NT;
         v[u] = 0.f;
         q[u] = 0;
 #pragma unroll
         for (int o = 0; o < NO; ++o) sl[o][u] = 0;
-        if (e < cnt) {
-            v[u] = __builtin_nontemporal_load(a.vals + base + e);
-            q[u] = a.pl_pos[base + e] & (T - 1);
+    }
+    if (e0 + PER <= cnt) {
+        const spt_f4 x = __builtin_nontemporal_load(reinterpret_cast<const spt_f4 *>(a.vals + base + e0));
+        const spt_u2 w = __builtin_nontemporal_load(reinterpret_cast<const spt_u2 *>(a.pl_pos + base + e0));
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+        q[0] = w.x & 0xFFFFu;
+        q[1] = w.x >> 16;
+        q[2] = w.y & 0xFFFFu;
+        q[3] = w.y >> 16;
 #pragma unroll
-            for (int o = 0; o < NO; ++o)
-                if (o < no) sl[o][u] = __builtin_nontemporal_load(a.d_slot[o] + base + e);
+        for (int o = 0; o < NO; ++o) {
+            if (o < no) {
+                const spt_u2 d = __builtin_nontemporal_load(reinterpret_cast<const spt_u2 *>(a.d_slot[o] + base + e0));
+                sl[o][0] = d.x & 0xFFFFu;
+                sl[o][1] = d.x >> 16;
+                sl[o][2] = d.y & 0xFFFFu;
+                sl[o][3] = d.y >> 16;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + u;
+            if (e < cnt) {
+                v[u] = a.vals[base + e];
+                q[u] = a.pl_pos[base + e];
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    if (o < no) sl[o][u] = a.d_slot[o][base + e];
+            }
         }
     }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) q[u] &= (uint32_t)(T - 1);  // a position inside the tile
     // copy the cached rows: the first min(distinct, cap) of each dictionary
     int64_t dbase[NO];
     int dn[NO], dlast[NO];
@@ -682,24 +770,35 @@ __device__ __forceinline__ void segd_tile(const MttkrpArgs &a, int64_t tile, cha
             }
         }
     }
-    // scatter: cached rows by slot, the others by global row
+    // scatter: cached rows by slot, the others by global row.  The global
+    // rows of all PER nonzeros are loaded before the first LDS store, so
+    // the thread waits for them once.
+    uint32_t grow[NO][PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        if (tid + u * NT < cnt) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            grow[o][u] = 0;
+            if (o < no && e0 + u < cnt) grow[o][u] = a.d_row[o][dbase[o] + min(sl[o][u], (uint32_t)dlast[o])];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (e0 + u < cnt) {
             valg[q[u]] = v[u];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
                 if (o < no) {
                     const uint32_t si = min(sl[o][u], (uint32_t)dlast[o]);
-                    crdg[o * T + q[u]] = (int)si < dn[o] ? (si | kDictHit) : a.d_row[o][dbase[o] + si];
+                    crdg[o * T + q[u]] = (int)si < dn[o] ? (si | kDictHit) : grow[o][u];
                 }
             }
         }
     }
     __syncthreads();
-    seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT, PlanPieces<T>, true>(
-        a, crdg, valg, (int)(k1 - k0), PlanPieces<T>{a.pl_desc, a.pl_row, a.pl_dest, k0, a.rec_cap, 0}, a.rec_row,
-        a.rec_val, a.rank, 0, cache, cap);
+    seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT, PackedPieces<T>, true>(
+        a, crdg, valg, (int)(k1 - k0), PackedPieces<T>{reinterpret_cast<const spt_u4 *>(a.pl_piece), k0, a.rec_cap},
+        a.rec_row, a.rec_val, a.rank, 0, cache, cap);
 }
 
 template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>
@@ -734,7 +833,7 @@ __global__ __launch_bounds__(NT) void k_mttkrp_segp_batched(const SegItem *__res
     if (it >= total_tiles) return;
     const int b = seg_item_of(items, count, it);
     const SegItem &item = items[b];
-    segp_tile<NT, 4 * NT, G, VEC, NB, NMAX, NFIX, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
+    segp_tile<NT, 4 * NT, G, VEC, NB, NMAX, NFIX, false, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
                                            item.row_base);
 }
 
@@ -869,12 +968,19 @@ __global__ __launch_bounds__(256) void k_piece_dest_batched(const SegItem *__res
     }
 }
 
-// dest[k] = first record of piece k's pair + its index within the pair
-__global__ __launch_bounds__(256) void k_piece_dest(const uint32_t *__restrict__ ppair, const uint32_t *__restrict__ psub,
-                                                    const uint32_t *__restrict__ pair_first, uint32_t *__restrict__ dest,
-                                                    int64_t n) {
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
-        dest[k] = pair_first[ppair[k]] + psub[k];
+// packed[k] = {desc[k], prow[k], first record of piece k's pair + its index within the pair, 0}
+__global__ __launch_bounds__(256) void k_piece_pack(const uint32_t *__restrict__ ppair, const uint32_t *__restrict__ psub,
+                                                    const uint32_t *__restrict__ pair_first,
+                                                    const uint32_t *__restrict__ desc, const uint32_t *__restrict__ prow,
+                                                    spt_u4 *__restrict__ packed, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        spt_u4 q;
+        q.x = desc[k];
+        q.y = prow[k];
+        q.z = pair_first[ppair[k]] + psub[k];
+        q.w = 0u;
+        packed[k] = q;
+    }
 }
 
 // pieces | distinct rows << 32 of a tile after the hashing stage
@@ -1009,11 +1115,12 @@ spt_status launch_emit_plan(const MttkrpArgs &a, const PlanOut &o, hipStream_t s
     return launch_emit_nt<1024>(a, ntiles, o, s);
 }
 
-spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first, uint32_t *dest,
-                             int64_t n, hipStream_t s) {
+spt_status launch_piece_pack(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first,
+                             const uint32_t *desc, const uint32_t *prow, uint32_t *packed, int64_t n, hipStream_t s) {
     if (n == 0) return SPT_OK;
     const int64_t g = std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_piece_dest, dim3((unsigned)g), dim3(256), 0, s, ppair, psub, pair_first, dest, n);
+    hipLaunchKernelGGL(k_piece_pack, dim3((unsigned)g), dim3(256), 0, s, ppair, psub, pair_first, desc, prow,
+                       reinterpret_cast<spt_u4 *>(packed), n);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
@@ -1060,6 +1167,7 @@ spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
     const int64_t ntiles = (a.nnz + a.tile - 1) / a.tile;
     if (ntiles == 0) return SPT_OK;
     if (!seg_tile_ok(a.tile, a.nmodes)) return fail(SPT_E_INVALID_ARG, "segment: tile does not fit LDS");
+    if (!a.pl_pos || !a.pl_off || !a.pl_piece) return fail(SPT_E_INVALID_ARG, "segment: no plan");
     if (a.tile == 1024) return launch_seg_tile<256, 1024>(a, ntiles, s);
     if (a.tile == 2048) return launch_seg_tile<512, 2048>(a, ntiles, s);
     return launch_seg_tile<kSegpThreads4096, 4096>(a, ntiles, s);

@@ -85,8 +85,7 @@ int device_cus() {
 
 void release_mode_plan(Tensor *t, int n, hipStream_t s) {
     ModePlan &p = t->mplan[n];
-    for (void *q : {(void *)p.rec_off, (void *)p.pl_pos, (void *)p.pl_off, (void *)p.pl_desc, (void *)p.pl_row,
-                    (void *)p.pl_dest})
+    for (void *q : {(void *)p.rec_off, (void *)p.pl_pos, (void *)p.pl_off, (void *)p.pl_piece})
         dev_free(q, s);
     p = ModePlan{};
 }
@@ -218,10 +217,8 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     const size_t n1 = (size_t)std::max<int64_t>(t->nnz, 1), k1 = (size_t)std::max<int64_t>(pieces, 1),
                  q1 = (size_t)std::max<int64_t>(pairs, 1);
     p.pl_pos = (uint16_t *)dev_alloc(sizeof(uint16_t) * n1, s);
-    p.pl_desc = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
-    p.pl_row = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
-    p.pl_dest = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
-    if (!p.pl_pos || !p.pl_desc || !p.pl_row || !p.pl_dest) {
+    p.pl_piece = (uint32_t *)dev_alloc(sizeof(uint32_t) * 4 * k1, s);
+    if (!p.pl_pos || !p.pl_piece) {
         (void)hipStreamSynchronize(s);  // the host offsets must outlive their copy
         return fail(SPT_E_OOM, "plan: arrays");
     }
@@ -230,6 +227,8 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
         return SPT_OK;
     }
     int64_t *pair_off = (int64_t *)dev_alloc(sizeof(int64_t) * (ntiles + 1), s);
+    uint32_t *desc = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
+    uint32_t *prow = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
     uint32_t *ppair = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
     uint32_t *psub = (uint32_t *)dev_alloc(sizeof(uint32_t) * k1, s);
     uint64_t *keys = (uint64_t *)dev_alloc(sizeof(uint64_t) * q1, s);
@@ -238,7 +237,7 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     uint32_t *ia = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
     uint32_t *ib = (uint32_t *)dev_alloc(sizeof(uint32_t) * q1, s);
     uint32_t *cnt = (uint32_t *)dev_alloc(sizeof(uint32_t) * std::max(sort_ws_counts(pairs), exclusive_scan_ws(pairs)), s);
-    spt_status st = (pair_off && ppair && psub && keys && keys2 && np && ia && ib && cnt)
+    spt_status st = (pair_off && desc && prow && ppair && psub && keys && keys2 && np && ia && ib && cnt)
                         ? SPT_OK
                         : fail(SPT_E_OOM, "plan: workspace");
     if (st == SPT_OK &&
@@ -246,7 +245,7 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
         st = hip_fail(hipGetLastError(), "plan: pair offsets");
     MttkrpArgs a = make_args(t, nullptr, rank, mode, nullptr, p.ts);
     a.pl_off = p.pl_off;
-    PlanOut o{pair_off, p.pl_pos, p.pl_desc, p.pl_row, ppair, psub, keys, np};
+    PlanOut o{pair_off, p.pl_pos, desc, prow, ppair, psub, keys, np};
     if (st == SPT_OK) st = launch_emit_plan(a, o, s);
     uint64_t *sk = nullptr;
     uint32_t *sidx = nullptr;
@@ -258,10 +257,10 @@ spt_status build_segment_plan(Tensor *t, int mode, int rank, hipStream_t s, Mode
     if (st == SPT_OK) st = launch_gather_u32(np, sidx, np_sorted, pairs, s);
     if (st == SPT_OK) st = launch_exclusive_scan_u32(np_sorted, tmp, pairs, cnt, s);
     if (st == SPT_OK) st = launch_scatter_u32(tmp, sidx, pair_first, pairs, s);
-    if (st == SPT_OK) st = launch_piece_dest(ppair, psub, pair_first, p.pl_dest, pieces, s);
+    if (st == SPT_OK) st = launch_piece_pack(ppair, psub, pair_first, desc, prow, p.pl_piece, pieces, s);
     if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess) st = hip_fail(hipGetLastError(), "plan: build");
-    for (void *q : {(void *)pair_off, (void *)ppair, (void *)psub, (void *)keys, (void *)keys2, (void *)np, (void *)ia,
-                    (void *)ib, (void *)cnt})
+    for (void *q : {(void *)pair_off, (void *)desc, (void *)prow, (void *)ppair, (void *)psub, (void *)keys,
+                    (void *)keys2, (void *)np, (void *)ia, (void *)ib, (void *)cnt})
         dev_free(q, s);
     // the counting pass gave this mode's distinct rows per tile: its tile
     // dictionary costs one more pass
@@ -506,9 +505,7 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
         MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
         a.pl_pos = p->pl_pos;
         a.pl_off = p->pl_off;
-        a.pl_desc = p->pl_desc;
-        a.pl_row = p->pl_row;
-        a.pl_dest = p->pl_dest;
+        a.pl_piece = p->pl_piece;
         a.rec_cap = p->records;
         // row cache: 4096-nonzero tiles, when the cache holds enough rows and
         // every non-output mode has its tile dictionary (spt_tensor_prepare)
@@ -577,9 +574,7 @@ spt_status run_mttkrp_f64(Tensor *t, const double *const *factors, int rank, int
     MttkrpArgs a = make_args(t, nullptr, rank, mode, nullptr, p->ts);
     a.pl_pos = p->pl_pos;
     a.pl_off = p->pl_off;
-    a.pl_desc = p->pl_desc;
-    a.pl_row = p->pl_row;
-    a.pl_dest = p->pl_dest;
+    a.pl_piece = p->pl_piece;
     a.rec_cap = p->records;
     const size_t n1 = (size_t)std::max<int64_t>(p->records, 1);
     uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s);
@@ -660,9 +655,7 @@ spt_status run_mttkrp_noalloc(Tensor *t, const float *const *factors, int rank, 
     MttkrpArgs a = make_args(t, factors, rank, mode, out, p->ts);
     a.pl_pos = p->pl_pos;
     a.pl_off = p->pl_off;
-    a.pl_desc = p->pl_desc;
-    a.pl_row = p->pl_row;
-    a.pl_dest = p->pl_dest;
+    a.pl_piece = p->pl_piece;
     a.rec_cap = P;
     const int cap = p->ts == kDictTile ? dict_cap(t->nmodes, rank) : 0;
     if (cap > 0 && t->plan.row_cache != 0) {

@@ -74,9 +74,12 @@ struct ModePlan {
     int64_t *rec_off = nullptr;  // TABLE: device, nwg offsets
     // SEGMENT plan: per nonzero its position in the tile's row-grouped order;
     // per piece (tile-major, pl_off[tile] .. pl_off[tile + 1]) its
-    // start | length << 16, row and record (records of one row contiguous)
+    // start | length << 16, row and record (records of one row contiguous):
+    // packed as 4 u32 {desc, row, record, 0} per piece in pl_piece (one
+    // tensor), in the three arrays pl_desc / pl_row / pl_dest (batched plans)
     uint16_t *pl_pos = nullptr;
     int64_t *pl_off = nullptr;
+    uint32_t *pl_piece = nullptr;
     uint32_t *pl_desc = nullptr, *pl_row = nullptr, *pl_dest = nullptr;
 };
 
@@ -170,7 +173,8 @@ struct MttkrpArgs {
     // SEGMENT plan (see ModePlan)
     const uint16_t *pl_pos;
     const int64_t *pl_off;
-    const uint32_t *pl_desc, *pl_row, *pl_dest;
+    const uint32_t *pl_piece;  // one tensor: 4 u32 per piece, 16-byte aligned
+    const uint32_t *pl_desc, *pl_row, *pl_dest;  // batched members
     int64_t rec_cap;          // records the plan laid out (writes beyond are dropped)
     // row cache (SEGMENT, tiles of kDictTile): the tile dictionaries of the
     // non-output modes in order (o-th non-output mode), and the cached rows
@@ -196,8 +200,9 @@ struct PlanOut {
     uint32_t *pair_np;        // per pair: its pieces
 };
 spt_status launch_emit_plan(const MttkrpArgs &a, const PlanOut &o, hipStream_t s);
-spt_status launch_piece_dest(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first, uint32_t *dest,
-                             int64_t n, hipStream_t s);
+// packed[k] = {desc[k], prow[k], first record of piece k's pair + its index, 0}
+spt_status launch_piece_pack(const uint32_t *ppair, const uint32_t *psub, const uint32_t *pair_first,
+                             const uint32_t *desc, const uint32_t *prow, uint32_t *packed, int64_t n, hipStream_t s);
 spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s);
 // mttkrp_f64.hip
 bool f64_tile_ok(int tile, int nmodes);

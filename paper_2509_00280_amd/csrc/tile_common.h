@@ -40,6 +40,8 @@ __device__ __forceinline__ void load_vec(const float *p, float (&x)[VEC]) {
 // `rows` read as zero.  The descriptor is wave-uniform (SGPRs); R <= 4095.
 typedef int spt_i4 __attribute__((ext_vector_type(4)));
 typedef float spt_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t spt_u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t spt_u4 __attribute__((ext_vector_type(4)));
 __device__ spt_f4 spt_row_load4(spt_i4 rsrc, int vindex, int voffset, int soffset, int aux) __asm(
     "llvm.amdgcn.struct.buffer.load.v4f32");
 __device__ float spt_row_load1(spt_i4 rsrc, int vindex, int voffset, int soffset, int aux) __asm(
