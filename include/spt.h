@@ -88,7 +88,7 @@ typedef struct {
                                    becomes a record written with plain stores at a slot that keeps the
                                    records grouped by row; records are summed per row (no atomics
                                    except for rows split between two reducer chunks).  The plan is
-                                   built by spt_tensor_prepare: 2 B per nonzero plus 12 B per piece */
+                                   built by spt_tensor_prepare: 2 B per nonzero plus 16 B per piece */
 typedef struct {
     int tile[SPT_MAX_MODES];      /* nonzeros per workgroup tile: 256..1024 for DIRECT/REGROUP (larger
                                      values act as 1024), 1024/2048/4096 for SEGMENT (smaller values,
@@ -180,7 +180,7 @@ spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan, void *stream)
 /*
  * Build the per-mode state MTTKRP needs under the tensor's plan, for every
  * mode: the SEGMENT plan (a counting pass and one emission pass over the
- * nonzeros: 2 B per nonzero plus 12 B per piece), the tile dictionaries of
+ * nonzeros: 2 B per nonzero plus 16 B per piece), the tile dictionaries of
  * the row cache (2 B per nonzero per mode plus 4 B per distinct (tile, row)
  * pair) and, under the TABLE strategy, that strategy's plan for `rank`
  * (the only rank-dependent plan).  `what` is a mask of SPT_PREPARE_*.  It is
