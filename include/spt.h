@@ -100,6 +100,11 @@ typedef struct {
                                      through the tile dictionaries (built by spt_tensor_prepare: 2 B
                                      per nonzero per mode plus 4 B per distinct (tile, row) pair);
                                      0 reads every factor row from memory */
+    int batch_tile;               /* nonzeros per tile of this tensor in batched launches: 1024, 2048
+                                     (default; 0 means the default) or 4096.  One batched launch runs
+                                     one tile size, its first member's: spt_mttkrp_batched needs every
+                                     member prepared at it, spt_cp_als_batched re-plans members at it.
+                                     spt_autotune_batched picks it by measurement */
 } spt_plan;
 
 /* ---------------------------------------------------------------------- */
@@ -371,6 +376,33 @@ typedef struct {
  */
 spt_status spt_autotune(spt_tensor *t, const float *const *factors, int rank, double budget_ms, int random_samples,
                         uint64_t seed, spt_tune_result *result, void *stream);
+
+/* Outcome of spt_autotune_batched (host). */
+typedef struct {
+    double ms[3];           /* all-mode batched MTTKRP milliseconds at batch tiles 1024, 2048, 4096
+                               (0: that tile does not fit the batch's mode count) */
+    int best_tile;          /* the tile every member holds on return */
+    int layouts_tuned;      /* members whose layout was searched */
+    double layout_speedup;  /* geometric mean over those members of start_ms / best_ms */
+} spt_batch_tune_result;
+
+/*
+ * Autotuner for batches (the measured search of spt_autotune, applied to the
+ * encoding and tile of batched launches).  With layout_budget_ms > 0 every
+ * member's bit layout is searched first, as spt_autotune does for one tensor
+ * (its own factors[b] and ranks[b], seed + b, re-encoding ts[b] in place).
+ * Then the all-mode batched MTTKRP (spt_mttkrp_batched over every mode) is
+ * timed at each batched tile that fits the batch's mode count, and every
+ * member's plan takes the fastest (plan batch_tile); members are left
+ * prepared for batched launches at it (SPT_PREPARE_BATCHED).
+ *   ts       host array of count handles (in/out: a re-encoded member keeps
+ *            its handle).
+ *   factors  host array of count host arrays of device pointers.
+ * Synchronises.  Errors: SPT_E_INVALID_ARG, SPT_E_OOM, SPT_E_DEVICE.
+ */
+spt_status spt_autotune_batched(spt_tensor *ts, int count, const float *const *const *factors, const int *ranks,
+                                double layout_budget_ms, int random_samples, uint64_t seed,
+                                spt_batch_tune_result *result, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of CP-ALS requests.                        */

@@ -168,6 +168,7 @@ static void default_plan(const Tensor *t, spt_plan *p) {
         p->strategy[n] = SPT_STRATEGY_AUTO;
     }
     p->row_cache = 1;
+    p->batch_tile = kBatchTileDefault;
     (void)t;
 }
 
@@ -177,6 +178,8 @@ static bool plan_ok(const spt_plan *p, int nmodes) {
         if (T != 256 && T != 512 && T != 1024 && T != 2048 && T != 4096) return false;
         if (p->strategy[n] < SPT_STRATEGY_DIRECT || p->strategy[n] > SPT_STRATEGY_SEGMENT) return false;
     }
+    const int b = p->batch_tile;
+    if (b != 0 && b != 1024 && b != 2048 && b != 4096) return false;
     return p->row_cache == 0 || p->row_cache == 1;
 }
 
@@ -341,7 +344,7 @@ spt_status spt_tensor_get_plan(spt_tensor t, spt_plan *plan) {
 
 spt_status spt_tensor_set_plan(spt_tensor t, const spt_plan *plan, void *stream) {
     if (!t || !plan) return fail(SPT_E_INVALID_ARG, "NULL argument");
-    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256..4096 (power of two), strategy 0..5, row_cache 0 or 1");
+    if (!plan_ok(plan, t->nmodes)) return fail(SPT_E_INVALID_ARG, "plan: tile must be 256..4096 (power of two), strategy 0..5, row_cache 0 or 1, batch_tile 0, 1024, 2048 or 4096");
     // the old plans may still be read by queued work: released in stream order
     const hipStream_t s = (hipStream_t)stream;
     for (int n = 0; n < kMaxModes; ++n) release_mode_plan(t, n, s);

@@ -4,7 +4,8 @@
 //
 // Per mode index n, every member tensor with more than n modes takes part in
 // ONE launch of each step:
-//   * SEGMENT MTTKRP over all members' tiles (tiles of kBatchTile nonzeros);
+//   * SEGMENT MTTKRP over all members' tiles in one persistent launch (one
+//     tile size per launch: the batched tile of the first member);
 //     records carry rows of a concatenated output M_all (member b's rows start
 //     at row_base[b], leading dimension ld = the largest rank of the mode),
 //     one radix sort of all records by row, one segmented reduction into M_all;
@@ -65,10 +66,18 @@ void set_batch_plan_args(MttkrpArgs &a, const ModePlan &p) {
 // concatenated output (tensors in order, tile order kept within a row), one
 // scan of their piece counts.  Each tensor's records come out grouped by row,
 // numbered from 0 within the tensor.
-spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s) {
+int batch_tile_of(const Tensor *t) {
+    const int b = t->plan.batch_tile;
+    return (b == 1024 || b == 2048 || b == 4096) ? b : kBatchTileDefault;
+}
+
+spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, int tile, hipStream_t s) {
     std::vector<Tensor *> need;
-    for (Tensor *t : ts)
-        if (t->nmodes > mode && !t->bplan[mode].pl_off) need.push_back(t);
+    for (Tensor *t : ts) {
+        if (t->nmodes <= mode) continue;
+        if (t->bplan[mode].pl_off && t->bplan[mode].ts != tile) release_batch_plan(t, mode, s);  // stream-ordered
+        if (!t->bplan[mode].pl_off) need.push_back(t);
+    }
     if (need.empty()) return SPT_OK;
     const int n = (int)need.size();
     int nmax = 0;
@@ -76,14 +85,14 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
     int64_t tiles = 0, rows = 0;
     for (int i = 0; i < n; ++i) {
         items[i] = SegItem{};
-        items[i].a = make_args(need[i], nullptr, 1, mode, nullptr, kBatchTile);
+        items[i].a = make_args(need[i], nullptr, 1, mode, nullptr, tile);
         items[i].first_tile = tiles;
         items[i].row_base = rows;
-        tiles += (need[i]->nnz + kBatchTile - 1) / kBatchTile;
+        tiles += (need[i]->nnz + tile - 1) / tile;
         rows += need[i]->dims[mode];
         nmax = std::max(nmax, need[i]->nmodes);
     }
-    if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "batch: too many modes for the batched tile");
+    if (!seg_batch_fits(nmax, tile)) return fail(SPT_E_INVALID_ARG, "batch: too many modes for the batched tile");
     if (tiles == 0) return SPT_OK;
     DevBuf d_items, d_cnt;
     std::vector<int64_t> h(tiles, 0);
@@ -93,7 +102,7 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
         return fail(SPT_E_OOM, "batch plan: counts");
     }
     SPT_HIP(hipMemcpyAsync(d_items.p, items.data(), sizeof(SegItem) * n, hipMemcpyHostToDevice, s));
-    spt_status st = launch_count_pieces_batched((SegItem *)d_items.p, n, tiles, nmax, (int64_t *)d_cnt.p, s);
+    spt_status st = launch_count_pieces_batched((SegItem *)d_items.p, n, tiles, nmax, tile, (int64_t *)d_cnt.p, s);
     if (st == SPT_OK && (hipMemcpyAsync(h.data(), d_cnt.p, sizeof(int64_t) * tiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
                          hipStreamSynchronize(s) != hipSuccess))
         st = hip_fail(hipGetLastError(), "batch plan: counts");
@@ -107,7 +116,7 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
     std::vector<int64_t> gpiece(tiles), gpair(tiles), piece_base(n + 1, 0);
     int64_t G = 0, Q = 0;
     for (int i = 0; i < n; ++i) {
-        const int64_t nt = (need[i]->nnz + kBatchTile - 1) / kBatchTile;
+        const int64_t nt = (need[i]->nnz + tile - 1) / tile;
         loff[i].assign(nt + 1, 0);
         piece_base[i] = G;
         int64_t local = 0;
@@ -146,7 +155,7 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
             return fail(SPT_E_OOM, "batch plan: arrays");
         }
         SPT_HIP(hipMemcpyAsync(p.pl_off, loff[i].data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, s));
-        p.ts = kBatchTile;
+        p.ts = tile;
         p.records = P;
         p.strategy = SPT_STRATEGY_SEGMENT;
         p.valid = 1;
@@ -176,7 +185,7 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
     SPT_HIP(hipMemcpyAsync(d_gpiece.p, gpiece.data(), sizeof(int64_t) * tiles, hipMemcpyHostToDevice, s));
     SPT_HIP(hipMemcpyAsync(d_gpair.p, gpair.data(), sizeof(int64_t) * tiles, hipMemcpyHostToDevice, s));
     SPT_HIP(hipMemcpyAsync(d_base.p, piece_base.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
-    st = launch_emit_plan_batched((SegItem *)d_items.p, n, tiles, nmax, (int64_t *)d_gpiece.p, (int64_t *)d_gpair.p,
+    st = launch_emit_plan_batched((SegItem *)d_items.p, n, tiles, nmax, tile, (int64_t *)d_gpiece.p, (int64_t *)d_gpair.p,
                                   (uint32_t *)ppair.p, (uint32_t *)psub.p, (uint64_t *)keys.p, (uint32_t *)np.p, s);
     uint64_t *sk = nullptr;
     uint32_t *sidx = nullptr;
@@ -205,7 +214,7 @@ spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStre
 spt_status prepare_batched(Tensor *t, hipStream_t s) {
     std::vector<Tensor *> one{t};
     for (int n = 0; n < t->nmodes; ++n) {
-        spt_status st = ensure_batch_plans(one, n, s);
+        spt_status st = ensure_batch_plans(one, n, batch_tile_of(t), s);
         if (st != SPT_OK) return st;
     }
     return SPT_OK;
@@ -213,7 +222,7 @@ spt_status prepare_batched(Tensor *t, hipStream_t s) {
 
 // The batched MTTKRP pipeline of one mode into M_all (rows x ld, overwritten).
 spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_min, int nmodes_max,
-                                   int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
+                                   int tile, int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
                                    BatchMttkrpWs &ws, hipStream_t s) {
     if (rows == 0) return SPT_OK;
     if (records == 0 || total_tiles == 0) return launch_fill_zero(M_all, rows * (int64_t)ld, s);
@@ -221,9 +230,11 @@ spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t to
     const size_t n1 = (size_t)records;
     uint64_t *rrow = (uint64_t *)ws.rec_row.get(sizeof(uint64_t) * n1, s);
     float *rval = (float *)ws.rec_val.get(sizeof(float) * n1 * ld, s);
-    if (!rrow || !rval) return fail(SPT_E_OOM, "batch: record workspace");
+    unsigned long long *counter = (unsigned long long *)ws.counter.get(256, s);
+    if (!rrow || !rval || !counter) return fail(SPT_E_OOM, "batch: record workspace");
     // the batch's records come out grouped by row: no sort
-    spt_status st = launch_mttkrp_seg_batched(d_items, count, total_tiles, nmodes_min, nmodes_max, ld, vec4, rrow, rval, s);
+    spt_status st = launch_mttkrp_seg_batched(d_items, count, total_tiles, nmodes_min, nmodes_max, tile, ld, vec4, rrow,
+                                              rval, counter, s);
     if (st == SPT_OK) st = launch_fill_zero(M_all, rows * (int64_t)ld, s);
     if (st == SPT_OK) st = launch_reduce_records(rrow, nullptr, rval, records, ld, rows, M_all, s);
     return st;
@@ -336,11 +347,13 @@ spt_status BatchEngine::rebuild() {
         nmodes_max_ = std::max(nmodes_max_, m->t->nmodes);
         nmodes_min_ = std::min(nmodes_min_, m->t->nmodes);
     }
-    if (!act.empty() && !seg_batch_fits(nmodes_max_)) return fail(SPT_E_INVALID_ARG, "batch: too many modes");
+    // one tile size for the whole batch: the first member's batched tile
+    tile_ = act.empty() ? kBatchTileDefault : batch_tile_of(act[0]->t);
+    if (!act.empty() && !seg_batch_fits(nmodes_max_, tile_)) return fail(SPT_E_INVALID_ARG, "batch: too many modes");
     std::vector<Tensor *> ts;
     for (Member *m : act) ts.push_back(m->t);
     for (int n = 0; n < nmodes_max_; ++n) {
-        spt_status st = ensure_batch_plans(ts, n, s_);
+        spt_status st = ensure_batch_plans(ts, n, tile_, s_);
         if (st != SPT_OK) return st;
     }
     // host images of every item array, packed into one upload
@@ -381,7 +394,7 @@ spt_status BatchEngine::rebuild() {
             if (t->nmodes <= n) continue;
             const int R = m->R;
             SegItem si{};
-            si.a = make_args(t, (const float *const *)m->F, R, n, nullptr, kBatchTile);
+            si.a = make_args(t, (const float *const *)m->F, R, n, nullptr, tile_);
             set_batch_plan_args(si.a, t->bplan[n]);
             si.first_tile = tiles;
             si.rec_base = recs;
@@ -430,7 +443,7 @@ spt_status BatchEngine::rebuild() {
             g2.G = m->grams + (size_t)n * R * R;
             gc.push_back(g2);
             mi.member_idx.push_back(i);
-            tiles += (t->nnz + kBatchTile - 1) / kBatchTile;
+            tiles += (t->nnz + tile_ - 1) / tile_;
             recs += t->bplan[n].records;
             rows += In;
             blocks += nb;
@@ -546,8 +559,8 @@ spt_status BatchEngine::step(bool *before_kernels) {
     for (int n = 0; n < nmodes_max_; ++n) {
         const ModeItems &mi = modes_[n];
         if (mi.count == 0) continue;
-        spt_status st = run_mttkrp_batched_mode((const SegItem *)(d_items_ + mi.seg_off), mi.count, mi.tiles, nmodes_min_, nmodes_max_,
-                                                mi.records, mi.rows, mi.ld, mi.vec4, M_all_, ws_, s_);
+        spt_status st = run_mttkrp_batched_mode((const SegItem *)(d_items_ + mi.seg_off), mi.count, mi.tiles, nmodes_min_,
+                                                nmodes_max_, tile_, mi.records, mi.rows, mi.ld, mi.vec4, M_all_, ws_, s_);
         if (st == SPT_OK)
             st = launch_gram_batched((const GramItem *)(d_items_ + mi.gm_off), mi.count, mi.gm_slices, mi.rmax,
                                      (double *)gram_ws_.p, s_);
@@ -633,7 +646,7 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
     hipStream_t s = (hipStream_t)stream;
     std::vector<Tensor *> tv;
     std::vector<int> idx;
-    int rmax = 0, nmax = 0, nmin = kMaxModes;
+    int rmax = 0, nmax = 0, nmin = kMaxModes, tile = 0;
     bool vec4 = true;
     for (int b = 0; b < count; ++b) {
         Tensor *t = ts[b];
@@ -641,9 +654,11 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         if (t->nmodes <= mode) continue;
         if (ranks[b] < 1 || ranks[b] > 64) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: rank must be 1..64");
         if (!outs[b]) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: NULL output " + std::to_string(b));
-        if (!t->bplan[mode].pl_off)
+        if (tile == 0) tile = batch_tile_of(t);  // one tile size per launch: the first member's
+        if (!t->bplan[mode].pl_off || t->bplan[mode].ts != tile)
             return fail(SPT_E_INVALID_ARG, "mttkrp_batched: tensor " + std::to_string(b) +
-                                               " not prepared for the batched launch (spt_tensor_prepare)");
+                                               " not prepared for the batched launch at the batch's tile of " +
+                                               std::to_string(tile) + " (spt_tensor_prepare, plan batch_tile)");
         spt_status st = check_factors(t, factors[b], ranks[b], mode);
         if (st != SPT_OK) return st;
         tv.push_back(t);
@@ -654,7 +669,7 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         vec4 = vec4 && ranks[b] % 4 == 0;
     }
     if (tv.empty()) return SPT_OK;
-    if (!seg_batch_fits(nmax)) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: too many modes");
+    if (!seg_batch_fits(nmax, tile)) return fail(SPT_E_INVALID_ARG, "mttkrp_batched: too many modes");
     const int ld = rmax;
     std::vector<SegItem> items(tv.size());
     int64_t tiles = 0, recs = 0, rows = 0;
@@ -663,13 +678,13 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
         Tensor *t = tv[i];
         const int b = idx[i];
         items[i] = SegItem{};
-        items[i].a = make_args(t, factors[b], ranks[b], mode, nullptr, kBatchTile);
+        items[i].a = make_args(t, factors[b], ranks[b], mode, nullptr, tile);
         set_batch_plan_args(items[i].a, t->bplan[mode]);
         items[i].first_tile = tiles;
         items[i].rec_base = recs;
         items[i].row_base = rows;
         row_base[i] = rows;
-        tiles += (t->nnz + kBatchTile - 1) / kBatchTile;
+        tiles += (t->nnz + tile - 1) / tile;
         recs += t->bplan[mode].records;
         rows += t->dims[mode];
     }
@@ -682,7 +697,8 @@ spt_status spt_mttkrp_batched(const spt_tensor *ts, int count, const float *cons
     }
     spt_status st = upload_staged(d_items, items.data(), sizeof(SegItem) * items.size(), s);
     BatchMttkrpWs ws;
-    if (st == SPT_OK) st = run_mttkrp_batched_mode(d_items, (int)items.size(), tiles, nmin, nmax, recs, rows, ld, vec4, M, ws, s);
+    if (st == SPT_OK)
+        st = run_mttkrp_batched_mode(d_items, (int)items.size(), tiles, nmin, nmax, tile, recs, rows, ld, vec4, M, ws, s);
     for (size_t i = 0; st == SPT_OK && i < tv.size(); ++i) {
         const int b = idx[i];
         const int64_t In = tv[i]->dims[mode];

@@ -28,6 +28,8 @@
 // nonzero's index in that list) replace the key decode; the first cap rows
 // of every non-output mode's list are copied to LDS and a nonzero reads its
 // factor row there when its index is below cap.
+#include <atomic>
+
 #include "tile_common.h"
 
 #ifndef SPT_SEG_UB
@@ -824,17 +826,30 @@ __device__ __forceinline__ int seg_item_of(const SegItem *__restrict__ items, in
 // Every tensor's records start at its rec_base in the batch's record array,
 // its rows at row_base of the concatenated output (records of the whole batch
 // stay grouped by row: tensors are laid out in order).
+// Persistent: a grid sized to the resident workgroups pulls the batch's tiles
+// (T = 4 NT nonzeros each, over all tensors in order) from the counter
+// *next_tile, zero at launch, until the counter passes total_tiles.  A
+// workgroup's tiles only increase, so it finds each tile's tensor by moving
+// forward from the last one.
 template <int NT, int G, int VEC, int NB, int NMAX, int NFIX>
 __global__ __launch_bounds__(NT) void k_mttkrp_segp_batched(const SegItem *__restrict__ items, int count,
                                                             int64_t total_tiles, uint64_t *__restrict__ rec_row,
-                                                            float *__restrict__ rec_val, int ld) {
+                                                            float *__restrict__ rec_val, int ld,
+                                                            unsigned long long *__restrict__ next_tile) {
     extern __shared__ __align__(16) char lds[];
-    const int64_t it = xcd_remap(blockIdx.x, gridDim.x);
-    if (it >= total_tiles) return;
-    const int b = seg_item_of(items, count, it);
-    const SegItem &item = items[b];
-    segp_tile<NT, 4 * NT, G, VEC, NB, NMAX, NFIX, false, false>(item.a, it - item.first_tile, lds, rec_row, rec_val, ld, item.rec_base,
-                                           item.row_base);
+    __shared__ int64_t s_tile;
+    int b = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(next_tile, 1ull);
+        __syncthreads();  // also: every wave is done with the previous tile's LDS
+        const int64_t it = s_tile;
+        __syncthreads();  // every thread has read s_tile before it is replaced
+        if (it >= total_tiles) break;
+        while (b + 1 < count && items[b + 1].first_tile <= it) ++b;
+        const SegItem &item = items[b];
+        segp_tile<NT, 4 * NT, G, VEC, NB, NMAX, NFIX, false, false>(item.a, it - item.first_tile, lds, rec_row, rec_val,
+                                                                    ld, item.rec_base, item.row_base);
+    }
 }
 
 // The plan of one mode: positions of every nonzero, and per piece its
@@ -1174,47 +1189,92 @@ spt_status launch_mttkrp_seg(const MttkrpArgs &a, hipStream_t s) {
 }
 
 namespace {
-template <int NMAX, int NFIX, int G, int VEC, int NB>
+template <int NT, int NMAX, int NFIX, int G, int VEC, int NB>
 spt_status launch_segb_k(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
-                         int ld, hipStream_t s) {
-    constexpr int NT = kBatchTile / 4;
-    const size_t lds = segp_lds_bytes(kBatchTile, NMAX);
-    hipLaunchKernelGGL((k_mttkrp_segp_batched<NT, G, VEC, NB, NMAX, NFIX>), dim3((unsigned)total_tiles), dim3(NT), lds, s,
-                       items, count, total_tiles, rec_row, rec_val, ld);
+                         int ld, unsigned long long *next_tile, hipStream_t s) {
+    const size_t lds = segp_lds_bytes(4 * NT, NMAX);
+    static std::atomic<int> per_cu{0};  // resident workgroups per CU (fixed per instantiation: its LDS is)
+    int pc = per_cu.load(std::memory_order_relaxed);
+    if (pc == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &pc, reinterpret_cast<const void *>(&k_mttkrp_segp_batched<NT, G, VEC, NB, NMAX, NFIX>), NT, lds) !=
+                hipSuccess ||
+            pc < 1) {
+            (void)hipGetLastError();  // not a failure of this call: one resident workgroup per CU is assumed
+            pc = 1;
+        }
+        per_cu.store(pc, std::memory_order_relaxed);
+    }
+    const int64_t grid = std::min<int64_t>(total_tiles, (int64_t)pc * device_cus());
+    spt_status st = launch_fill_zero(reinterpret_cast<float *>(next_tile), 2, s);  // the tile counter
+    if (st != SPT_OK) return st;
+    hipLaunchKernelGGL((k_mttkrp_segp_batched<NT, G, VEC, NB, NMAX, NFIX>), dim3((unsigned)grid), dim3(NT), lds, s, items,
+                       count, total_tiles, rec_row, rec_val, ld, next_tile);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
 
-template <int NMAX, int NFIX>
+template <int NT, int NMAX, int NFIX>
 spt_status launch_segb_n(const SegItem *items, int count, int64_t total_tiles, uint64_t *rec_row, float *rec_val,
-                         int ld, bool vec4, hipStream_t s) {
+                         int ld, bool vec4, unsigned long long *next_tile, hipStream_t s) {
     if (vec4) {
         const int r4 = ld >> 2;
-        if (r4 <= 1) return launch_segb_k<NMAX, NFIX, 1, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        if (r4 <= 2) return launch_segb_k<NMAX, NFIX, 2, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        if (r4 <= 4) return launch_segb_k<NMAX, NFIX, 4, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        if (r4 <= 8) return launch_segb_k<NMAX, NFIX, 8, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
-        return launch_segb_k<NMAX, NFIX, 16, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+        if (r4 <= 1) return launch_segb_k<NT, NMAX, NFIX, 1, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, next_tile, s);
+        if (r4 <= 2) return launch_segb_k<NT, NMAX, NFIX, 2, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, next_tile, s);
+        if (r4 <= 4) return launch_segb_k<NT, NMAX, NFIX, 4, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, next_tile, s);
+        if (r4 <= 8) return launch_segb_k<NT, NMAX, NFIX, 8, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, next_tile, s);
+        return launch_segb_k<NT, NMAX, NFIX, 16, 4, 1>(items, count, total_tiles, rec_row, rec_val, ld, next_tile, s);
     }
-    return launch_segb_k<NMAX, NFIX, 64, 1, 1>(items, count, total_tiles, rec_row, rec_val, ld, s);
+    return launch_segb_k<NT, NMAX, NFIX, 64, 1, 1>(items, count, total_tiles, rec_row, rec_val, ld, next_tile, s);
+}
+
+template <int NT>
+spt_status launch_segb_t(const SegItem *items, int count, int64_t total_tiles, int nmodes_min, int nmodes_max, int ld,
+                         bool vec4, uint64_t *rec_row, float *rec_val, unsigned long long *next_tile, hipStream_t s) {
+    if (nmodes_min == 3 && nmodes_max == 3)
+        return launch_segb_n<NT, 3, 3>(items, count, total_tiles, rec_row, rec_val, ld, vec4, next_tile, s);
+    if (nmodes_max <= 4) return launch_segb_n<NT, 4, 0>(items, count, total_tiles, rec_row, rec_val, ld, vec4, next_tile, s);
+    return launch_segb_n<NT, 8, 0>(items, count, total_tiles, rec_row, rec_val, ld, vec4, next_tile, s);
+}
+
+template <int NT>
+void launch_emit_b(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, const int64_t *gpiece_off,
+                   const int64_t *gpair_off, uint32_t *ppair, uint32_t *psub, uint64_t *pair_key, uint32_t *pair_np,
+                   hipStream_t s) {
+    constexpr int T = 4 * NT;
+    if (nmodes_max <= 4)
+        hipLaunchKernelGGL((k_emit_plan_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT), seg_lds_bytes(T, 4), s,
+                           items, count, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np);
+    else
+        hipLaunchKernelGGL((k_emit_plan_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
+                           seg_lds_bytes(T, nmodes_max), s,
+                           items, count, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np);
+}
+
+template <int NT>
+void launch_count_b(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int64_t *counts,
+                    hipStream_t s) {
+    constexpr int T = 4 * NT;
+    if (nmodes_max <= 4)
+        hipLaunchKernelGGL((k_count_pieces_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT), seg_lds_bytes(T, 4), s,
+                           items, count, total_tiles, counts);
+    else
+        hipLaunchKernelGGL((k_count_pieces_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
+                           seg_lds_bytes(T, nmodes_max), s,
+                           items, count, total_tiles, counts);
 }
 }  // namespace
 
-bool seg_batch_fits(int nmodes_max) { return seg_tile_ok(kBatchTile, nmodes_max); }
+bool seg_batch_fits(int nmodes_max, int tile) { return seg_tile_ok(tile, nmodes_max); }
 
-spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int tile,
                                     const int64_t *gpiece_off, const int64_t *gpair_off, uint32_t *ppair,
                                     uint32_t *psub, uint64_t *pair_key, uint32_t *pair_np, hipStream_t s) {
     if (total_tiles == 0) return SPT_OK;
-    constexpr int NT = kBatchTile / 4;
-    if (nmodes_max <= 4)
-        hipLaunchKernelGGL((k_emit_plan_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT),
-                           seg_lds_bytes(kBatchTile, 4), s, items, count, gpiece_off, gpair_off, ppair, psub, pair_key,
-                           pair_np);
-    else
-        hipLaunchKernelGGL((k_emit_plan_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
-                           seg_lds_bytes(kBatchTile, 8), s, items, count, gpiece_off, gpair_off, ppair, psub, pair_key,
-                           pair_np);
+    if (!seg_batch_fits(nmodes_max, tile)) return fail(SPT_E_INVALID_ARG, "batch plan: tile does not fit LDS");
+    if (tile == 1024) launch_emit_b<256>(items, count, total_tiles, nmodes_max, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np, s);
+    else if (tile == 2048) launch_emit_b<512>(items, count, total_tiles, nmodes_max, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np, s);
+    else launch_emit_b<1024>(items, count, total_tiles, nmodes_max, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np, s);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
@@ -1229,29 +1289,29 @@ spt_status launch_piece_dest_batched(const SegItem *items, int count, const int6
     return SPT_OK;
 }
 
-spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int tile,
                                        int64_t *counts, hipStream_t s) {
     if (total_tiles == 0) return SPT_OK;
-    constexpr int NT = kBatchTile / 4;
-    if (nmodes_max <= 4)
-        hipLaunchKernelGGL((k_count_pieces_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT),
-                           seg_lds_bytes(kBatchTile, 4), s, items, count, total_tiles, counts);
-    else
-        hipLaunchKernelGGL((k_count_pieces_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
-                           seg_lds_bytes(kBatchTile, 8), s, items, count, total_tiles, counts);
+    if (!seg_batch_fits(nmodes_max, tile)) return fail(SPT_E_INVALID_ARG, "batch plan: tile does not fit LDS");
+    if (tile == 1024) launch_count_b<256>(items, count, total_tiles, nmodes_max, counts, s);
+    else if (tile == 2048) launch_count_b<512>(items, count, total_tiles, nmodes_max, counts, s);
+    else launch_count_b<1024>(items, count, total_tiles, nmodes_max, counts, s);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }
 
 spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_min,
-                                     int nmodes_max, int ld, bool vec4, uint64_t *rec_row, float *rec_val,
-                                     hipStream_t s) {
+                                     int nmodes_max, int tile, int ld, bool vec4, uint64_t *rec_row, float *rec_val,
+                                     unsigned long long *next_tile, hipStream_t s) {
     if (total_tiles == 0) return SPT_OK;
     if (ld > 64 || (vec4 && (ld & 3))) return fail(SPT_E_INVALID_ARG, "batched MTTKRP: rank above 64");
-    if (nmodes_min == 3 && nmodes_max == 3)
-        return launch_segb_n<3, 3>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
-    if (nmodes_max <= 4) return launch_segb_n<4, 0>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
-    return launch_segb_n<8, 0>(items, count, total_tiles, rec_row, rec_val, ld, vec4, s);
+    if (!seg_batch_fits(nmodes_max, tile)) return fail(SPT_E_INVALID_ARG, "batched MTTKRP: tile does not fit LDS");
+    if (!next_tile) return fail(SPT_E_INVALID_ARG, "batched MTTKRP: no tile counter");
+    if (tile == 1024)
+        return launch_segb_t<256>(items, count, total_tiles, nmodes_min, nmodes_max, ld, vec4, rec_row, rec_val, next_tile, s);
+    if (tile == 2048)
+        return launch_segb_t<512>(items, count, total_tiles, nmodes_min, nmodes_max, ld, vec4, rec_row, rec_val, next_tile, s);
+    return launch_segb_t<1024>(items, count, total_tiles, nmodes_min, nmodes_max, ld, vec4, rec_row, rec_val, next_tile, s);
 }
 
 }  // namespace spt

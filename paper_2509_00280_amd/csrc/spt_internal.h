@@ -100,7 +100,7 @@ struct Tensor {
     double norm_x2 = 0.0;
     spt_plan plan{};
     ModePlan mplan[kMaxModes];
-    // batched SEGMENT plan per mode (tiles of kBatchTile; stream-ordered allocations)
+    // batched SEGMENT plan per mode (tiles of bplan[n].ts nonzeros; stream-ordered allocations)
     ModePlan bplan[kMaxModes];
     // tile dictionaries (tiles of kDictTile, built by spt_tensor_prepare): per mode slot[nnz] u16,
     // row[distinct (tile, row) pairs] u32, off[ntiles + 1]
@@ -218,29 +218,33 @@ spt_status launch_emit_dict(const MttkrpArgs &a, const int64_t *off, uint32_t *r
 // cache does not fit).
 int dict_cap(int nmodes, int rank);
 
-// Batched SEGMENT MTTKRP: every tensor's tiles of kBatchTile nonzeros in one
-// launch, each with the tensor's batched plan (a.pl_*); records carry rows of
-// the batch's concatenated output (row_base + row) and go to rec_base + the
-// plan's record, so the batch's records stay grouped by row.
-constexpr int kBatchTile = 2048;
+// Batched SEGMENT MTTKRP: every tensor's tiles (one tile size per launch:
+// 1024, 2048 or 4096 nonzeros) in one persistent launch, each with the
+// tensor's batched plan (a.pl_*); records carry rows of the batch's
+// concatenated output (row_base + row) and go to rec_base + the plan's
+// record, so the batch's records stay grouped by row.
+constexpr int kBatchTileDefault = 2048;
+// the batched tile of a tensor: its plan's batch_tile, else the default
+int batch_tile_of(const Tensor *t);
 struct SegItem {
     MttkrpArgs a;        // a.pl_*: the tensor's batched plan for this mode; a.rec_cap its records
     int64_t first_tile;  // prefix of tiles over the batch
     int64_t rec_base;    // first record of this tensor
     int64_t row_base;    // first row of this tensor in the concatenated output
 };
-bool seg_batch_fits(int nmodes_max);
+bool seg_batch_fits(int nmodes_max, int tile);
 // per global tile: pieces | distinct rows << 32
-spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+spt_status launch_count_pieces_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int tile,
                                        int64_t *counts, hipStream_t s);
-spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max,
+spt_status launch_emit_plan_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_max, int tile,
                                     const int64_t *gpiece_off, const int64_t *gpair_off, uint32_t *ppair,
                                     uint32_t *psub, uint64_t *pair_key, uint32_t *pair_np, hipStream_t s);
 spt_status launch_piece_dest_batched(const SegItem *items, int count, const int64_t *piece_base, const uint32_t *ppair,
                                      const uint32_t *psub, const uint32_t *pair_first, int64_t n, hipStream_t s);
+// next_tile: a device counter (8 bytes) the launch zeroes and the workgroups pull tiles from
 spt_status launch_mttkrp_seg_batched(const SegItem *items, int count, int64_t total_tiles, int nmodes_min,
-                                     int nmodes_max, int ld, bool vec4, uint64_t *rec_row, float *rec_val,
-                                     hipStream_t s);
+                                     int nmodes_max, int tile, int ld, bool vec4, uint64_t *rec_row, float *rec_val,
+                                     unsigned long long *next_tile, hipStream_t s);
 
 // Batched dense steps (dense.hip): one workgroup per item, except apply
 // (a grid over the items' row blocks).
@@ -340,16 +344,19 @@ struct DevBuf {
 
 // record and sort buffers of the batched MTTKRP
 struct BatchMttkrpWs {
-    DevBuf rec_row, rec_val;
+    DevBuf rec_row, rec_val, counter;
     void release(hipStream_t s) {
         rec_row.release(s);
         rec_val.release(s);
+        counter.release(s);
     }
 };
 spt_status run_mttkrp_batched_mode(const SegItem *d_items, int count, int64_t total_tiles, int nmodes_min, int nmodes_max,
-                                   int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
+                                   int tile, int64_t records, int64_t rows, int ld, bool vec4, float *M_all,
                                    BatchMttkrpWs &ws, hipStream_t s);
-spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, hipStream_t s);
+// batched plans of `mode` at `tile` for the tensors that lack them (a plan
+// at another tile is released and rebuilt); synchronises s when it builds
+spt_status ensure_batch_plans(const std::vector<Tensor *> &ts, int mode, int tile, hipStream_t s);
 // every mode's batched plan of one tensor (synchronises s)
 spt_status prepare_batched(Tensor *t, hipStream_t s);
 // host-to-device copy through a pinned staging ring (asynchronous)
@@ -396,6 +403,7 @@ private:
     std::vector<double> hfit_;
     std::vector<int> hstat_;
     BatchMttkrpWs ws_;
+    int tile_ = kBatchTileDefault;  // batched tile of the current members
 };
 
 

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -347,6 +348,93 @@ spt_status spt_autotune(spt_tensor *tp, const float *const *factors, int rank, d
     if (st != SPT_OK) return st;
     r.best_ms = best;
     *res = r;
+    return SPT_OK;
+}
+
+// Batches: the members' layouts (each by the search above, with its own
+// factors and rank, under the same reward) and then the batch's tile, by
+// timing the all-mode batched MTTKRP at every tile that fits.
+spt_status spt_autotune_batched(spt_tensor *ts, int count, const float *const *const *factors, const int *ranks,
+                                double layout_budget_ms, int random_samples, uint64_t seed,
+                                spt_batch_tune_result *result, void *stream) {
+    if (count < 1 || !ts || !factors || !ranks || !result) return fail(SPT_E_INVALID_ARG, "autotune_batched: NULL argument");
+    const hipStream_t s = (hipStream_t)stream;
+    int nmax = 0;
+    for (int b = 0; b < count; ++b) {
+        if (!ts[b] || !factors[b]) return fail(SPT_E_INVALID_ARG, "autotune_batched: NULL member " + std::to_string(b));
+        if (ranks[b] < 1 || ranks[b] > 64) return fail(SPT_E_INVALID_ARG, "autotune_batched: rank must be 1..64");
+        spt_status st = check_factors(ts[b], factors[b], ranks[b], -1);
+        if (st != SPT_OK) return st;
+        nmax = std::max(nmax, ts[b]->nmodes);
+    }
+    spt_batch_tune_result r{};
+    double log_gain = 0.0;
+    if (layout_budget_ms > 0.0) {
+        for (int b = 0; b < count; ++b) {
+            spt_tune_result tr{};
+            spt_status st = spt_autotune(&ts[b], factors[b], ranks[b], layout_budget_ms, random_samples, seed + (uint64_t)b,
+                                         &tr, stream);
+            if (st != SPT_OK) return st;
+            ++r.layouts_tuned;
+            if (tr.best_ms > 0.0 && tr.start_ms > 0.0) log_gain += std::log(tr.start_ms / tr.best_ms);
+        }
+    }
+    r.layout_speedup = r.layouts_tuned ? std::exp(log_gain / r.layouts_tuned) : 1.0;
+    // one output buffer per member, as large as its largest mode
+    std::vector<float *> outs(count, nullptr);
+    spt_status st = SPT_OK;
+    for (int b = 0; b < count && st == SPT_OK; ++b) {
+        int64_t rows = 1;
+        for (int n = 0; n < ts[b]->nmodes; ++n) rows = std::max(rows, ts[b]->dims[n]);
+        outs[b] = (float *)dev_alloc(sizeof(float) * (size_t)rows * ranks[b], s);
+        if (!outs[b]) st = fail(SPT_E_OOM, "autotune_batched: outputs");
+    }
+    std::vector<Tensor *> tv(ts, ts + count);
+    const int tiles[3] = {1024, 2048, 4096};
+    auto all_modes = [&]() -> spt_status {
+        for (int n = 0; n < nmax; ++n) {
+            spt_status e = spt_mttkrp_batched(ts, count, factors, ranks, n, outs.data(), stream);
+            if (e != SPT_OK) return e;
+        }
+        return SPT_OK;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == SPT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = hip_fail(hipGetLastError(), "autotune_batched: events");
+    double best = 0.0;
+    int best_tile = 0;
+    for (int i = 0; i < 3 && st == SPT_OK; ++i) {
+        const int T = tiles[i];
+        r.ms[i] = 0.0;
+        if (!seg_batch_fits(nmax, T)) continue;
+        for (Tensor *t : tv) t->plan.batch_tile = T;
+        for (int n = 0; n < nmax && st == SPT_OK; ++n) st = ensure_batch_plans(tv, n, T, s);
+        if (st == SPT_OK) st = all_modes();  // warm-up
+        constexpr int kReps = 3;
+        if (st == SPT_OK && hipEventRecord(e0, s) != hipSuccess) st = hip_fail(hipGetLastError(), "autotune_batched: event");
+        for (int k = 0; k < kReps && st == SPT_OK; ++k) st = all_modes();
+        float el = 0.f;
+        if (st == SPT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&el, e0, e1) != hipSuccess))
+            st = hip_fail(hipGetLastError(), "autotune_batched: timing");
+        if (st != SPT_OK) break;
+        r.ms[i] = el / kReps;
+        if (best_tile == 0 || r.ms[i] < best) {
+            best = r.ms[i];
+            best_tile = T;
+        }
+    }
+    if (st == SPT_OK && best_tile == 0) st = fail(SPT_E_INVALID_ARG, "autotune_batched: no batched tile fits");
+    if (st == SPT_OK) {
+        for (Tensor *t : tv) t->plan.batch_tile = best_tile;
+        for (int n = 0; n < nmax && st == SPT_OK; ++n) st = ensure_batch_plans(tv, n, best_tile, s);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (float *o : outs) dev_free(o, s);
+    if (st != SPT_OK) return st;
+    r.best_tile = best_tile;
+    *result = r;
     return SPT_OK;
 }
 

@@ -39,7 +39,13 @@ class TensorInfo(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int * MAX_MODES), ("strategy", ctypes.c_int * MAX_MODES), ("row_cache", ctypes.c_int)]
+    _fields_ = [("tile", ctypes.c_int * MAX_MODES), ("strategy", ctypes.c_int * MAX_MODES), ("row_cache", ctypes.c_int),
+                ("batch_tile", ctypes.c_int)]
+
+
+class BatchTuneResult(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 3), ("best_tile", ctypes.c_int), ("layouts_tuned", ctypes.c_int),
+                ("layout_speedup", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -111,6 +117,8 @@ def lib():
                                        ctypes.POINTER(d), ctypes.POINTER(i), _VP])
     _sig(L, "spt_autotune", st, [ctypes.POINTER(_VP), _PP, i, d, i, ctypes.c_uint64, ctypes.POINTER(TuneResult),
                                  _VP])
+    _sig(L, "spt_autotune_batched", st, [_PP, i, ctypes.POINTER(_PP), ctypes.POINTER(i), d, i, ctypes.c_uint64,
+                                         ctypes.POINTER(BatchTuneResult), _VP])
     _sig(L, "spt_server_create", st, [ctypes.c_size_t, i, ctypes.POINTER(_VP)])
     _sig(L, "spt_server_submit", st, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
     _sig(L, "spt_server_wait", st, [_VP, ctypes.c_uint64, d, ctypes.POINTER(Result), _PP, _VP])
@@ -293,9 +301,10 @@ class Tensor:
     def get_plan(self) -> dict:
         p = Plan()
         _check(lib().spt_tensor_get_plan(self._h, ctypes.byref(p)))
-        return {"tile": list(p.tile), "strategy": list(p.strategy), "row_cache": int(p.row_cache)}
+        return {"tile": list(p.tile), "strategy": list(p.strategy), "row_cache": int(p.row_cache),
+                "batch_tile": int(p.batch_tile)}
 
-    def set_plan(self, tile=None, strategy=None, row_cache=None):
+    def set_plan(self, tile=None, strategy=None, row_cache=None, batch_tile=None):
         p = Plan()
         _check(lib().spt_tensor_get_plan(self._h, ctypes.byref(p)))
         for n in range(MAX_MODES):
@@ -307,8 +316,11 @@ class Tensor:
                     strategy if isinstance(strategy, int) else p.strategy[n])
         if row_cache is not None:
             p.row_cache = 1 if row_cache else 0
+        if batch_tile is not None:
+            p.batch_tile = int(batch_tile)
         _check(lib().spt_tensor_set_plan(self._h, ctypes.byref(p), _stream(None)))
         self._prepared_rank = None
+        self._batched = False
 
     def prepare(self, rank: int, batched: bool = False, stream=None):
         """Build the per-mode MTTKRP state (plans, tile dictionaries) for ``rank``."""
@@ -512,6 +524,36 @@ def autotune(t: Tensor, factors, budget_ms: float = 2000.0, random_samples: int 
     t._batched = False
     return {"best_ms": res.best_ms, "alto_ms": res.alto_ms, "start_ms": res.start_ms,
             "candidates": res.candidates, "random_samples": res.random_samples, "cache_hits": res.cache_hits}
+
+
+def autotune_batched(tensors, factor_lists, layout_budget_ms: float = 0.0, random_samples: int = 2, seed: int = 0,
+                     stream=None):
+    """Batch autotuner: optionally every member's layout (``layout_budget_ms`` > 0), then the batched
+    tile by timing the all-mode batched MTTKRP at 1024, 2048 and 4096 nonzeros per tile.
+
+    Returns a dict: ms (tile -> all-mode batched ms, 0 when the tile does not fit),
+    best_tile, layouts_tuned, layout_speedup."""
+    count = len(tensors)
+    if len(factor_lists) != count or count == 0:
+        raise ValueError("one factor list per tensor, at least one tensor")
+    for t, fl in zip(tensors, factor_lists):
+        R = check_factors(fl, t.info()["dims"])
+        if R > 64:
+            raise ValueError("batched launches take ranks 1..64")
+    hs = (ctypes.c_void_p * count)(*[t.handle.value for t in tensors])
+    farrs = [_ptr_array(fl) for fl in factor_lists]
+    fptrs = (_PP * count)(*[ctypes.cast(a, _PP) for a in farrs])
+    ranks = (ctypes.c_int * count)(*[int(fl[0].shape[1]) for fl in factor_lists])
+    res = BatchTuneResult()
+    _check(lib().spt_autotune_batched(hs, count, fptrs, ranks, float(layout_budget_ms), int(random_samples),
+                                      ctypes.c_uint64(int(seed)), ctypes.byref(res), _stream(stream)))
+    for t, h in zip(tensors, hs):
+        t._h = ctypes.c_void_p(h)
+        t._batched = True
+        if layout_budget_ms > 0:
+            t._prepared_rank = None
+    return {"ms": {1024: res.ms[0], 2048: res.ms[1], 4096: res.ms[2]}, "best_tile": res.best_tile,
+            "layouts_tuned": res.layouts_tuned, "layout_speedup": res.layout_speedup}
 
 
 _ALLOC_HOOKS = None
