@@ -289,7 +289,8 @@ BatchEngine::~BatchEngine() {
 }
 
 void BatchEngine::release_buffers() {
-    for (DevBuf *b : {&items_buf_, &M_buf_, &fit_buf_, &status_buf_, &inner_buf_, &resid_buf_, &gram_ws_}) b->release(s_);
+    for (DevBuf *b : {&items_buf_, &M_buf_, &fit_buf_, &status_buf_, &inner_buf_, &resid_buf_, &resid_items_buf_, &gram_ws_})
+        b->release(s_);
     d_items_ = nullptr;
     M_all_ = nullptr;
     fit_all_ = nullptr;
@@ -594,19 +595,44 @@ spt_status BatchEngine::step(bool *before_kernels) {
         if (!m->done && 1.0 - hfit_[4 * i] < 1e-2 && m->t->nnz > 0) direct.push_back(i);
     }
     if (!direct.empty()) {
-        int64_t need = 0;
-        for (int i : direct) need = std::max<int64_t>(need, (active_[i]->t->nnz + 1023) / 1024);
-        resid_ = (double *)resid_buf_.get(sizeof(double) * 2 * need, s_);
-        if (!resid_) return fail(SPT_E_OOM, "batch: residual partials");
+        // one residual launch over every member that takes the direct fit,
+        // then one fit launch (a workgroup per member)
+        std::vector<ResidItem> ri;
+        std::vector<FitDirectItem> fi;
+        int64_t tiles = 0;
+        int rmax = 0, nmax = 0;
+        bool vec4 = true;
         for (int i : direct) {
             Member *m = active_[i];
-            // each member's residual runs after the previous one (shared partials)
-            MttkrpArgs a = make_args(m->t, (const float *const *)m->F, m->R, -1, nullptr, 1024);
-            const int parts = (int)((m->t->nnz + 1023) / 1024);
-            st = launch_resid(a, m->lambda, resid_, parts, s_);
-            if (st == SPT_OK) st = launch_fit_direct(resid_, parts, m->t->norm_x2, fit_all_ + 4 * i, s_);
-            if (st != SPT_OK) return st;
+            ResidItem r{};
+            r.a = make_args(m->t, (const float *const *)m->F, m->R, -1, nullptr, kResidTile);
+            r.lambda = m->lambda;
+            r.first_tile = tiles;  // partials rebased below
+            ri.push_back(r);
+            FitDirectItem f{};
+            f.nparts = (m->t->nnz + kResidTile - 1) / kResidTile;
+            f.norm_x2 = m->t->norm_x2;
+            f.out = fit_all_ + 4 * i;
+            fi.push_back(f);
+            tiles += f.nparts;
+            rmax = std::max(rmax, m->R);
+            nmax = std::max(nmax, m->t->nmodes);
+            vec4 = vec4 && m->R % 4 == 0;
         }
+        resid_ = (double *)resid_buf_.get(sizeof(double) * 2 * std::max<int64_t>(tiles, 1), s_);
+        char *d_ri = (char *)resid_items_buf_.get(sizeof(ResidItem) * ri.size() + 256 + sizeof(FitDirectItem) * fi.size(), s_);
+        if (!resid_ || !d_ri) return fail(SPT_E_OOM, "batch: residual partials");
+        for (size_t k = 0; k < ri.size(); ++k) {
+            ri[k].partials = resid_ + 2 * ri[k].first_tile;
+            fi[k].parts = ri[k].partials;
+        }
+        const size_t fi_off = (sizeof(ResidItem) * ri.size() + 255) & ~size_t(255);
+        st = upload_staged(d_ri, ri.data(), sizeof(ResidItem) * ri.size(), s_);
+        if (st == SPT_OK) st = upload_staged(d_ri + fi_off, fi.data(), sizeof(FitDirectItem) * fi.size(), s_);
+        if (st == SPT_OK)
+            st = launch_resid_batched((const ResidItem *)d_ri, (int)ri.size(), tiles, nmax, rmax, vec4, s_);
+        if (st == SPT_OK) st = launch_fit_direct_batched((const FitDirectItem *)(d_ri + fi_off), (int)fi.size(), s_);
+        if (st != SPT_OK) return st;
         if (hipMemcpyAsync(hfit_.data(), fit_all_, sizeof(double) * 4 * A, hipMemcpyDeviceToHost, s_) != hipSuccess ||
             hipStreamSynchronize(s_) != hipSuccess)
             return hip_fail(hipGetLastError(), "batch: direct fit readback");

@@ -610,12 +610,12 @@ __global__ __launch_bounds__(kThreads) void k_fit_batched(const FitItem *__restr
 }
 
 // out[1] must hold |Xhat|^2 from k_fit; writes out[0] (fit) and out[3] (residual^2).
-__global__ __launch_bounds__(kThreads) void k_fit_direct(const double *__restrict__ parts, int nparts, double norm_x2,
-                                                         double *__restrict__ out) {
+__device__ __forceinline__ void fit_direct_body(const double *__restrict__ parts, int64_t nparts, double norm_x2,
+                                                double *__restrict__ out) {
     __shared__ double red[2][4];
     const int tid = threadIdx.x;
     double a = 0.0, b = 0.0;
-    for (int i = tid; i < nparts; i += kThreads) {
+    for (int64_t i = tid; i < nparts; i += kThreads) {
         a += parts[2 * i];
         b += parts[2 * i + 1];
     }
@@ -638,6 +638,16 @@ __global__ __launch_bounds__(kThreads) void k_fit_direct(const double *__restric
         out[0] = 1.0 - sqrt(r2) / sqrt(norm_x2);
         out[3] = r2;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fit_direct(const double *__restrict__ parts, int nparts, double norm_x2,
+                                                         double *__restrict__ out) {
+    fit_direct_body(parts, nparts, norm_x2, out);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fit_direct_batched(const FitDirectItem *__restrict__ items) {
+    const FitDirectItem &it = items[blockIdx.x];
+    fit_direct_body(it.parts, it.nparts, it.norm_x2, it.out);
 }
 
 }  // namespace
@@ -707,6 +717,13 @@ spt_status launch_fit(const double *grams, int nmodes, int rank, const double *l
                       int nparts, double norm_x2, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_fit, dim3(1), dim3(kThreads), 0, s, grams, nmodes, rank, lambda, inner_partials, nparts, norm_x2,
                        out);
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
+}
+
+spt_status launch_fit_direct_batched(const FitDirectItem *items, int count, hipStream_t s) {
+    if (count <= 0) return SPT_OK;
+    hipLaunchKernelGGL(k_fit_direct_batched, dim3((unsigned)count), dim3(kThreads), 0, s, items);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

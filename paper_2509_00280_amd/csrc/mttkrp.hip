@@ -301,12 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs a, int64_t ntile
 // partials[2*b] = sum over the tile of (v - xhat)^2, partials[2*b+1] = sum xhat^2 (FP64),
 // xhat = sum_r lambda_r prod_k C^(k)[i_k, r].
 template <int G, int VEC, int NB, int NMAX>
-__global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles, const double *__restrict__ lam,
-                                                    double *__restrict__ partials) {
-    extern __shared__ __align__(16) char lds[];
+__device__ __forceinline__ void resid_tile(const MttkrpArgs &a, int64_t tile, const double *__restrict__ lam,
+                                           double *__restrict__ partials, char *lds) {
     __shared__ uint32_t wsum[4];
     __shared__ double red[2][kThreads / 64];
-    const int64_t tile = blockIdx.x;
     const TileLds L = carve(lds, a.tile, NMAX);
     const CodecRegs cr = load_codec_regs(a.codec);
     const int cnt = stage_tile<NMAX, false>(a, tile, L, -1, wsum, cr);
@@ -380,6 +378,30 @@ __global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles
     }
 }
 
+template <int G, int VEC, int NB, int NMAX>
+__global__ __launch_bounds__(kThreads) void k_resid(MttkrpArgs a, int64_t ntiles, const double *__restrict__ lam,
+                                                    double *__restrict__ partials) {
+    extern __shared__ __align__(16) char lds[];
+    resid_tile<G, VEC, NB, NMAX>(a, blockIdx.x, lam, partials, lds);
+}
+
+// Residual of many tensors in one launch: tile `it` of the launch belongs to
+// the last item whose first_tile <= it; its partials go to the item's array.
+template <int G, int VEC, int NB, int NMAX>
+__global__ __launch_bounds__(kThreads) void k_resid_batched(const ResidItem *__restrict__ items, int count) {
+    extern __shared__ __align__(16) char lds[];
+    const int64_t it = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_tile <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const ResidItem &r = items[lo];
+    resid_tile<G, VEC, NB, NMAX>(r.a, it - r.first_tile, r.lambda, r.partials, lds);
+}
+
 __global__ __launch_bounds__(kThreads) void k_fill_zero(float4 *__restrict__ p, int64_t n4, float *__restrict__ tail,
                                                         int ntail) {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kThreads)
@@ -415,6 +437,25 @@ spt_status launch_nmax(const MttkrpArgs &a, bool regroup, int64_t ntiles, hipStr
     if (R <= 128) return launch_walk<64, 1, 2, NMAX>(a, regroup, ntiles, s);
     if (R <= 192) return launch_walk<64, 1, 3, NMAX>(a, regroup, ntiles, s);
     return launch_walk<64, 1, 4, NMAX>(a, regroup, ntiles, s);
+}
+
+template <int NMAX>
+spt_status launch_resid_batched_nmax(const ResidItem *items, int count, int64_t total_tiles, int rmax, bool vec4,
+                                     hipStream_t s) {
+    const size_t lds = tile_lds_bytes(kResidTile, NMAX, false);
+    const dim3 g((unsigned)total_tiles), b(kThreads);
+    if (vec4 && rmax <= 64) {
+        const int r4 = rmax >> 2;
+        if (r4 <= 1) hipLaunchKernelGGL((k_resid_batched<1, 4, 1, NMAX>), g, b, lds, s, items, count);
+        else if (r4 <= 2) hipLaunchKernelGGL((k_resid_batched<2, 4, 1, NMAX>), g, b, lds, s, items, count);
+        else if (r4 <= 4) hipLaunchKernelGGL((k_resid_batched<4, 4, 1, NMAX>), g, b, lds, s, items, count);
+        else if (r4 <= 8) hipLaunchKernelGGL((k_resid_batched<8, 4, 1, NMAX>), g, b, lds, s, items, count);
+        else hipLaunchKernelGGL((k_resid_batched<16, 4, 1, NMAX>), g, b, lds, s, items, count);
+    } else {
+        hipLaunchKernelGGL((k_resid_batched<64, 1, 1, NMAX>), g, b, lds, s, items, count);
+    }
+    SPT_HIP(hipGetLastError());
+    return SPT_OK;
 }
 
 template <int NMAX>
@@ -464,6 +505,14 @@ spt_status launch_resid(const MttkrpArgs &a, const double *lam, double *partials
     if (ntiles == 0) return SPT_OK;
     if (a.nmodes <= 4) return launch_resid_nmax<4>(a, lam, partials, ntiles, s);
     return launch_resid_nmax<8>(a, lam, partials, ntiles, s);
+}
+
+spt_status launch_resid_batched(const ResidItem *items, int count, int64_t total_tiles, int nmodes_max, int rmax,
+                                bool vec4, hipStream_t s) {
+    if (total_tiles == 0 || count == 0) return SPT_OK;
+    if (rmax > 64) return fail(SPT_E_INVALID_ARG, "resid_batched: rank above 64");
+    if (nmodes_max <= 4) return launch_resid_batched_nmax<4>(items, count, total_tiles, rmax, vec4, s);
+    return launch_resid_batched_nmax<8>(items, count, total_tiles, rmax, vec4, s);
 }
 
 }  // namespace spt

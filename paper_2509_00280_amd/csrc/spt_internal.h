@@ -395,7 +395,7 @@ private:
     int init_count_ = 0, init_rmax_ = 0;
     int64_t init_slices_ = 0;
     DevBuf gram_ws_;  // partial Grams of the batched Gram launches
-    DevBuf items_buf_, M_buf_, fit_buf_, status_buf_, inner_buf_, resid_buf_;
+    DevBuf items_buf_, M_buf_, fit_buf_, status_buf_, inner_buf_, resid_buf_, resid_items_buf_;
     std::vector<char> blob_;  // host image of the item arrays (kept until the next upload)
     float *M_all_ = nullptr;
     double *fit_all_ = nullptr, *inner_all_ = nullptr, *resid_ = nullptr;
@@ -432,6 +432,26 @@ spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, con
 
 // residual over the nonzeros (direct fit): out2[0] += sum (v - xhat)^2, out2[1] += sum xhat^2
 spt_status launch_resid(const MttkrpArgs &a, const double *lam, double *partials, int nparts, hipStream_t s);
+// the same for many tensors in one launch: item b's tiles (of kResidTile
+// nonzeros; a.tile must be kResidTile) start at first_tile of the launch and
+// write 2 doubles each to partials[2 * local tile]
+constexpr int kResidTile = 1024;
+struct ResidItem {
+    MttkrpArgs a;
+    const double *lambda;
+    double *partials;
+    int64_t first_tile;
+};
+spt_status launch_resid_batched(const ResidItem *items, int count, int64_t total_tiles, int nmodes_max, int rmax,
+                                bool vec4, hipStream_t s);
+// the direct fit of many tensors, one workgroup each (as launch_fit_direct)
+struct FitDirectItem {
+    const double *parts;
+    double *out;
+    double norm_x2;
+    int64_t nparts;
+};
+spt_status launch_fit_direct_batched(const FitDirectItem *items, int count, hipStream_t s);
 
 // dense.hip
 spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double *work, size_t work_bytes,

@@ -154,3 +154,36 @@ def test_autotune_batched_tile_only_then_cp_als(spt):
         e, el = cpd_error(to_host(Fb[b]), lams[b].cpu().numpy(), to_host(Fs), lam_s.cpu().numpy())
         assert abs(fits[b] - fit_s) <= TOL_FIT
         assert e <= TOL_ROW and el <= TOL_ROW
+
+
+def _exact_rank(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    true = [rng.random((d, R)) + 0.1 for d in dims]
+    X = true[0]
+    for f in true[1:]:
+        X = np.einsum("...r,jr->...jr", X, f)
+    X = X.sum(axis=-1)
+    coords = np.stack(np.nonzero(np.ones(dims))).astype(np.uint32)
+    t = synth.SparseCOO(tuple(dims), coords, X[tuple(coords)].astype(np.float32))
+    F0 = [rng.standard_normal((d, R)).astype(np.float32) for d in dims]
+    return t, F0, R
+
+
+def test_cp_als_batched_direct_fit_recovery(spt):
+    """Members that converge (1 - fit < 1e-2) take the direct FP64 residual, for
+    the whole batch in one launch: exact rank-R tensors (3 and 4 modes, ranks
+    4, 5 and 8, so both lane layouts) next to a member that stays far from it."""
+    members = [_exact_rank((30, 20, 10), 4, 2), _exact_rank((12, 9, 8, 6), 5, 3), _exact_rank((25, 16, 12), 8, 4)]
+    members.append(_members(count=1, seed=66, ranks=(8,))[0])
+    hs = _encode_all(spt, members)
+    iters = 120
+    Fb = [factors_dev(F) for _, F, _ in members]
+    lams, fits, its = spt.cp_als_batched(hs, Fb, iters)
+    for b, ((t, F, R), h) in enumerate(zip(members, hs)):
+        Fs = factors_dev(F)
+        lam_s, fit_s, _ = spt.cp_als(h, Fs, iters)
+        ref = oracle.cp_als(t.coords, t.vals, t.dims, F, iters=iters)
+        print(f"member {b}: batched fit {fits[b]:.8f} single {fit_s:.8f} oracle {ref['fit']:.8f}", flush=True)
+        assert abs(fits[b] - fit_s) <= TOL_FIT and abs(fits[b] - ref["fit"]) <= TOL_FIT
+        if b < 3:
+            assert fits[b] > 0.99  # the direct residual is in use
