@@ -220,15 +220,15 @@ __device__ __forceinline__ void seg_stage(const MttkrpArgs &a, int64_t tile, con
 // exactly NFIX modes (no run-time mode test between the gathers, which would
 // otherwise make the compiler wait for one mode's rows before the next
 // mode's gathers are issued).
-// DICT: a crdg entry with kDictHit set is the LDS slot of a row held in
-// `cache` (non-output mode o, slot s at cache[(o * cap + s) * R]); any other
-// entry is a global row.  Every lane reads its step's rows from LDS first,
-// then the lanes whose row is global load it over the LDS value.
+// DICT: a crdg entry is either the byte offset in `ldsb` of a row held in
+// the LDS row cache (at most lim, the offset of the cache's last row) or, with
+// kDictMiss set, a global row.  Every lane reads its step's rows from LDS
+// first, then the lanes whose row is global load it over the LDS value.
 template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT, class Pieces, bool DICT = false>
 __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__restrict__ crdg,
                                          const float *__restrict__ valg, int npieces, const Pieces &pieces,
                                          uint64_t *__restrict__ rec_row, float *__restrict__ rec_val, int ld,
-                                         int64_t row_base, const float *__restrict__ cache = nullptr, int cap = 0) {
+                                         int64_t row_base, const char *__restrict__ ldsb = nullptr, uint32_t lim = 0) {
     constexpr int UB = DICT ? kUnrollDict : kUnroll;
     constexpr int NO = NMAX - 1;  // non-output modes at most
     const int j = threadIdx.x % G;
@@ -291,24 +291,25 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
                         for (int u = 0; u < UB; ++u) row[o][u] = crdg[o * T + pp[u]];
                 float xv[NO][UB][NB][VEC];
                 if constexpr (DICT) {
+                    // every index read of the step is issued before anything
+                    // waits for one (the scheduler may not hoist a use between them)
+                    __builtin_amdgcn_sched_barrier(0);
                     // Every lane first reads LDS (a miss reads the last cached
-                    // row, a clamped slot), then the misses load their rows
-                    // globally into the same registers.  A global load into the
-                    // registers of an LDS read waits for that read; with all LDS
-                    // reads of the step issued first the loads wait for one LDS
-                    // round trip, and no branch splits hits from misses.
+                    // row: its entry, flag set, clamps to lim), then the misses
+                    // load their rows globally into the same registers.  A global
+                    // load into the registers of an LDS read waits for that read;
+                    // with all LDS reads of the step issued first the loads wait
+                    // for one LDS round trip, and no branch splits hits from misses.
 #pragma unroll
                     for (int o = 0; o < NO; ++o) {
 #pragma unroll
                         for (int u = 0; u < UB; ++u) {
-                            const uint32_t sl = min(row[o][u] - kDictHit, (uint32_t)(cap - 1));
+                            const uint32_t off = min(row[o][u], lim);
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 const int c = (b * G + j) * VEC;
                                 if (o < no && (EXACT || c < R)) {
-                                    // row stride: a compile-time shift when the groups cover R exactly
-                                    const int rs = EXACT ? G * VEC * NB : R;
-                                    const float *cp = cache + ((size_t)(o * cap) + sl) * rs + c;
+                                    const float *cp = reinterpret_cast<const float *>(ldsb + off) + c;
                                     if constexpr (VEC == 4) {
                                         const float4 t4 = *reinterpret_cast<const float4 *>(cp);
                                         xv[o][u][b][0] = t4.x;
@@ -333,7 +334,7 @@ __device__ __forceinline__ void seg_walk(const MttkrpArgs &a, const uint32_t *__
                                 for (int b = 0; b < NB; ++b) {
                                     const int c = (b * G + j) * VEC;
                                     if (EXACT || c < R) {
-                                        if (!(rv & kDictHit)) load_row_vec<VEC>(fb[o], rv, c, xv[o][u][b]);
+                                        if (rv & kDictMiss) load_row_vec<VEC>(fb[o], rv & ~kDictMiss, c, xv[o][u][b]);
                                     } else {
 #pragma unroll
                                         for (int v = 0; v < VEC; ++v) xv[o][u][b][v] = 0.f;
@@ -772,9 +773,10 @@ __device__ __forceinline__ void segd_tile(const MttkrpArgs &a, int64_t tile, cha
             }
         }
     }
-    // scatter: cached rows by slot, the others by global row.  The global
-    // rows of all PER nonzeros are loaded before the first LDS store, so
-    // the thread waits for them once.
+    // scatter: cached rows by their byte offset in LDS, the others by global
+    // row with kDictMiss set.  The global rows of all PER nonzeros are loaded
+    // before the first LDS store, so the thread waits for them once.
+    const uint32_t cache_off = (uint32_t)(reinterpret_cast<const char *>(cache) - lds);
     uint32_t grow[NO][PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -792,15 +794,18 @@ __device__ __forceinline__ void segd_tile(const MttkrpArgs &a, int64_t tile, cha
             for (int o = 0; o < NO; ++o) {
                 if (o < no) {
                     const uint32_t si = min(sl[o][u], (uint32_t)dlast[o]);
-                    crdg[o * T + q[u]] = (int)si < dn[o] ? (si | kDictHit) : grow[o][u];
+                    crdg[o * T + q[u]] = (int)si < dn[o] ? cache_off + ((uint32_t)(o * cap) + si) * (uint32_t)(R * 4)
+                                                         : (grow[o][u] | kDictMiss);
                 }
             }
         }
     }
     __syncthreads();
+    // the largest entry a cached row can have: the last slot of the last mode
+    const uint32_t lim = cache_off + ((uint32_t)(no * cap) - 1u) * (uint32_t)(R * 4);
     seg_walk<NT, T, G, VEC, NB, NMAX, NFIX, EXACT, PackedPieces<T>, true>(
         a, crdg, valg, (int)(k1 - k0), PackedPieces<T>{reinterpret_cast<const spt_u4 *>(a.pl_piece), k0, a.rec_cap},
-        a.rec_row, a.rec_val, a.rank, 0, cache, cap);
+        a.rec_row, a.rec_val, a.rank, 0, lds, lim);
 }
 
 template <int NT, int T, int G, int VEC, int NB, int NMAX, int NFIX, bool EXACT>

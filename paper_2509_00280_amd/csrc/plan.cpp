@@ -123,7 +123,7 @@ static bool dict_eligible(const Tensor *t) {
     if (t->dict_state < 0 || t->nmodes < 2 || t->nmodes > 4 || t->nnz == 0 || !seg_tile_ok(kDictTile, t->nmodes))
         return false;
     for (int k = 0; k < t->nmodes; ++k)
-        if (t->dims[k] >= (int64_t)kDictHit) return false;
+        if (t->dims[k] >= (int64_t)kDictMiss) return false;
     return true;
 }
 

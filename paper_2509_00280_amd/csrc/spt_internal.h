@@ -14,7 +14,7 @@ namespace spt {
 constexpr int kMaxModes = SPT_MAX_MODES;
 constexpr int kMaxRuns = 160;          // l(p) <= 128 bits plus splits at 32-bit word boundaries
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
-constexpr uint32_t kDictHit = 0x80000000u;  // row-cache entry flag (global rows stay below it)
+constexpr uint32_t kDictMiss = 0x80000000u;  // row-cache entry flag of a global row (global rows stay below it)
 constexpr int kDictTile = 4096;             // tile of the dictionaries and the row-cached kernel
 #ifndef SPT_DICT_LDS_KB
 #define SPT_DICT_LDS_KB 80
