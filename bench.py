@@ -769,7 +769,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; sharding across GPUs is not implemented; "
+                                   "--gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
