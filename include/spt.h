@@ -22,9 +22,10 @@
  *    returns a message (thread-local).
  *  - The caller owns every buffer it passes; the library owns the memory
  *    behind an spt_tensor until spt_tensor_free.
- *  - Every device buffer the library owns is taken from and returned to the
- *    allocator hook (spt_set_allocator) in stream order: releasing memory
- *    never synchronises the device or a stream.
+ *  - Every device buffer the library owns is taken from and returned to its
+ *    source in stream order: releasing memory never synchronises the device
+ *    or a stream.  The source is the library's block cache (spt_memory_stats)
+ *    unless an allocator hook is set (spt_set_allocator).
  */
 #ifndef SPT_H
 #define SPT_H
@@ -121,14 +122,41 @@ typedef struct {
  * that a buffer is used on one stream, which holds for every call except the
  * server, whose requests the library synchronises before release.  Requests
  * are rounded up to 256 bytes and the returned pointer must be 256-byte
- * aligned.  Passing NULL for both restores the default (the device's
- * stream-ordered memory pool).  Every buffer goes back to the allocator
- * that supplied it, whatever hook is set when it is released.
+ * aligned.  Passing NULL for both restores the default (the block cache
+ * below).  Every buffer goes back to the allocator that supplied it,
+ * whatever hook is set when it is released.
  * Errors: SPT_E_INVALID_ARG (exactly one hook NULL).
  */
 typedef void *(*spt_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*spt_release_fn)(void *ptr, void *stream, void *ctx);
 spt_status spt_set_allocator(spt_alloc_fn alloc, spt_release_fn release, void *ctx);
+
+/*
+ * The default source of device memory is a block cache per device: blocks
+ * come from hipMalloc and are kept after release.  A block released on a
+ * stream serves later requests on that stream at once (stream order); a
+ * request on another stream takes it only after the work ordered before the
+ * release has completed.  Requests of 2 MiB or more round up to a multiple
+ * of 2 MiB and may take an idle block up to 1/8 + 2 MiB larger; smaller
+ * requests round up to a power of two (at least 512 bytes).  hipMalloc runs
+ * only when no idle block fits, so repeating a call with the same sizes
+ * allocates nothing from the driver.  If hipMalloc fails, the idle blocks of
+ * the device are returned to the driver and the request retried once
+ * (SPT_E_OOM if that fails too).  A stream handle that released library
+ * memory must not be destroyed and re-created while that work is pending
+ * (reuse on "the same stream" is decided by handle value).
+ *
+ * spt_memory_stats fills a host array of 4: bytes held by live buffers,
+ * bytes of idle cached blocks, hipMalloc calls so far and requests served
+ * from idle blocks so far (all devices; hook-supplied memory not included).
+ * Errors: SPT_E_INVALID_ARG (NULL).
+ *
+ * spt_empty_cache returns every idle block to the driver (waits for the
+ * work ordered before each release, then hipFree).  Live buffers stay.
+ * Errors: SPT_E_DEVICE.
+ */
+spt_status spt_memory_stats(int64_t *stats);
+spt_status spt_empty_cache(void);
 
 /* ---------------------------------------------------------------------- */
 /* Encoding (Section III-C: linearized tensor, positions of l(p) bits).    */

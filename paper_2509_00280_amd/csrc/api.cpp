@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -35,26 +36,11 @@ spt_status hip_fail(hipError_t e, const char *what) {
 // Every device buffer the library owns comes from dev_alloc and goes back
 // through dev_free on a stream, in stream order: a buffer released on stream
 // s may be reused by work ordered after that point of s, so releasing never
-// waits for the device.  By default the bytes come from the device's
-// stream-ordered pool (release threshold raised once per device, so repeated
-// calls do not return memory to the driver); spt_set_allocator replaces the
-// source, e.g. with PyTorch's caching allocator.
-static std::once_flag g_pool_once[64];
+// waits for the device.  spt_set_allocator can replace the source, e.g. with
+// PyTorch's caching allocator; the default is the block cache below.
 static std::atomic<spt_alloc_fn> g_alloc{nullptr};
 static std::atomic<spt_release_fn> g_release{nullptr};
 static std::atomic<void *> g_alloc_ctx{nullptr};
-
-static void tune_pool() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-    std::call_once(g_pool_once[dev], [dev]() {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t thr = ~0ull;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-        }
-    });
-}
 
 // Buffers taken from a hook remember the hook that releases them, so
 // changing the hook never sends a buffer to the wrong allocator.
@@ -64,6 +50,143 @@ struct HookOwner {
 };
 static std::mutex g_owner_mu;
 static std::unordered_map<void *, HookOwner> g_owner;
+
+// Default source: a cache of device blocks per device.  A block comes from
+// hipMalloc once and stays with the library after release.  A block released
+// on stream s serves a later request on s at once (stream order makes that
+// safe); a request on another stream takes it only once the event recorded
+// at its release has completed.  hipMalloc runs only when no idle block fits;
+// when it fails, the idle blocks of that device are returned to the driver
+// (after their release events) and the request is tried once more.  The
+// runtime's stream-ordered pool is not used: once many different sizes had
+// passed through it (a layout search), single hipMallocAsync and hipFreeAsync
+// calls were measured holding the host for 0.15 s to 2.7 s with the GPU idle.
+namespace {
+constexpr size_t kLargeGrain = size_t(1) << 21;  // 2 MiB: large requests round up to this
+constexpr int kMaxDevices = 64;
+constexpr int kMaxProbe = 32;  // idle blocks examined per request
+
+struct Block {
+    size_t bytes = 0;
+    int dev = 0;
+    hipStream_t stream = nullptr;  // stream of the last release
+    hipEvent_t ev = nullptr;       // recorded at the last release; nullptr: no work pending
+};
+
+struct BlockCache {
+    std::mutex mu;
+    std::unordered_map<void *, Block> live;
+    std::multimap<size_t, std::pair<void *, Block>> idle[kMaxDevices];
+    int64_t bytes_live = 0, bytes_idle = 0, device_allocs = 0, reuses = 0;
+};
+
+// Never destroyed: blocks may still be released while the process exits.
+BlockCache &cache() {
+    static BlockCache *c = new BlockCache;
+    return *c;
+}
+
+size_t cache_size(size_t bytes) {
+    if (bytes >= kLargeGrain) return (bytes + kLargeGrain - 1) & ~(kLargeGrain - 1);
+    size_t b = 512;
+    while (b < bytes) b <<= 1;
+    return b;
+}
+
+// Largest idle block a request of `need` bytes may take.
+size_t cache_limit(size_t need) { return need < kLargeGrain ? need : need + need / 8 + kLargeGrain; }
+
+// Returns the idle blocks of `dev` to the driver (caller holds the lock).
+void release_idle(BlockCache &c, int dev) {
+    for (auto &kv : c.idle[dev]) {
+        Block &b = kv.second.second;
+        if (b.ev) {
+            (void)hipEventSynchronize(b.ev);
+            (void)hipEventDestroy(b.ev);
+        }
+        (void)hipFree(kv.second.first);
+        c.bytes_idle -= (int64_t)b.bytes;
+    }
+    c.idle[dev].clear();
+}
+
+void *cache_alloc(size_t bytes, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const size_t need = cache_size(bytes);
+    BlockCache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto &idle = c.idle[dev];
+    int probed = 0;
+    for (auto it = idle.lower_bound(need); it != idle.end() && it->first <= cache_limit(need) && probed < kMaxProbe;
+         ++it, ++probed) {
+        Block &b = it->second.second;
+        bool ready = b.ev == nullptr || b.stream == s;
+        if (!ready) {
+            const hipError_t q = hipEventQuery(b.ev);
+            if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
+            ready = q == hipSuccess;
+        }
+        if (!ready) continue;
+        void *p = it->second.first;
+        Block blk = b;
+        idle.erase(it);
+        c.bytes_idle -= (int64_t)blk.bytes;
+        c.bytes_live += (int64_t)blk.bytes;
+        ++c.reuses;
+        c.live[p] = blk;
+        return p;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release_idle(c, dev);
+        e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    Block blk;
+    blk.bytes = need;
+    blk.dev = dev;
+    c.live[p] = blk;
+    c.bytes_live += (int64_t)need;
+    ++c.device_allocs;
+    return p;
+}
+
+bool cache_free(void *p, hipStream_t s) {
+    BlockCache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return false;
+    Block b = it->second;
+    c.live.erase(it);
+    b.stream = s;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    bool recorded = false;
+    if (cur == b.dev) {
+        if (!b.ev && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) b.ev = nullptr;
+        recorded = b.ev && hipEventRecord(b.ev, s) == hipSuccess;
+    }
+    if (!recorded) {  // no event: wait here so that every stream may take the block
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+        b.ev = nullptr;
+    }
+    c.bytes_live -= (int64_t)b.bytes;
+    c.bytes_idle += (int64_t)b.bytes;
+    c.idle[b.dev].emplace(b.bytes, std::make_pair(p, b));
+    return true;
+}
+}  // namespace
 
 void *dev_alloc(size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 16;
@@ -81,13 +204,7 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
         g_owner[p] = HookOwner{rel, ctx};
         return p;
     }
-    tune_pool();
-    void *p = nullptr;
-    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    return p;
+    return cache_alloc(bytes, s);
 }
 
 void dev_free(void *p, hipStream_t s) {
@@ -105,7 +222,31 @@ void dev_free(void *p, hipStream_t s) {
         o.release(p, (void *)s, o.ctx);
         return;
     }
-    (void)hipFreeAsync(p, s);
+    (void)cache_free(p, s);
+}
+
+spt_status memory_stats(int64_t *stats) {
+    BlockCache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    stats[0] = c.bytes_live;
+    stats[1] = c.bytes_idle;
+    stats[2] = c.device_allocs;
+    stats[3] = c.reuses;
+    return SPT_OK;
+}
+
+spt_status empty_cache() {
+    BlockCache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return hip_fail(hipGetLastError(), "empty_cache");
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (c.idle[d].empty()) continue;
+        if (hipSetDevice(d) != hipSuccess) return hip_fail(hipGetLastError(), "empty_cache: set device");
+        release_idle(c, d);
+    }
+    if (hipSetDevice(cur) != hipSuccess) return hip_fail(hipGetLastError(), "empty_cache: restore device");
+    return SPT_OK;
 }
 
 // ---------------------------------------------------------------- codec
@@ -232,6 +373,13 @@ spt_status spt_set_allocator(spt_alloc_fn alloc, spt_release_fn release, void *c
     g_alloc.store(alloc);
     return SPT_OK;
 }
+
+spt_status spt_memory_stats(int64_t *stats) {
+    if (!stats) return fail(SPT_E_INVALID_ARG, "memory_stats: NULL output");
+    return memory_stats(stats);
+}
+
+spt_status spt_empty_cache(void) { return empty_cache(); }
 
 spt_status spt_profile_enable(int on) { return profile_enable(on); }
 
@@ -471,6 +619,12 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
     double *resid = (double *)dev_alloc(sizeof(double) * 2 * std::max<int64_t>(resid_tiles, 1), s);
     double *fitd = (double *)dev_alloc(sizeof(double) * 4 + sizeof(int) * kMaxModes, s);
     double *lam = (double *)dev_alloc(sizeof(double) * R, s);
+    // one record workspace for every mode's MTTKRP (the largest plan's records)
+    RecordWs ws;
+    ws.records = std::max<int64_t>(max_plan_records(t), 1);
+    ws.val_floats = ws.records * R;
+    ws.row = (uint64_t *)dev_alloc(sizeof(uint64_t) * ws.records, s);
+    ws.val = (float *)dev_alloc(sizeof(float) * ws.val_floats, s);
     // the iterations run on copies: the caller's factors and lambda are
     // written only when the call succeeds
     float *F[kMaxModes] = {};
@@ -479,9 +633,10 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
     auto cleanup = [&]() {
         dev_free(M, s); dev_free(grams, s); dev_free(gram_m, s); dev_free(S, s); dev_free(gwork, s);
         dev_free(inner, s); dev_free(resid, s); dev_free(fitd, s); dev_free(lam, s);
+        dev_free(ws.row, s); dev_free(ws.val, s);
         for (int k = 0; k < N; ++k) dev_free(F[k], s);
     };
-    if (!M || !grams || !gram_m || !S || !gwork || !inner || !resid || !fitd || !lam || !fok) {
+    if (!M || !grams || !gram_m || !S || !gwork || !inner || !resid || !fitd || !lam || !ws.row || !ws.val || !fok) {
         cleanup();
         return fail(SPT_E_OOM, "cp_als: workspace allocation failed");
     }
@@ -505,7 +660,7 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
     while (it < max_iters) {
         for (int n = 0; n < N; ++n) {
             const int64_t In = t->dims[n];
-            CK(run_mttkrp(t, (const float *const *)F, R, n, M, s));
+            CK(run_mttkrp(t, (const float *const *)F, R, n, M, s, &ws));
             CK(launch_gram(M, In, R, gram_m, gwork, gw, s));
             CK(launch_solve_prep(grams, N, n, R, gram_m, S, lam, status + n, s));
             CK(launch_apply(M, In, R, S, F[n], lam, n == N - 1 ? inner : nullptr, nullptr, s));

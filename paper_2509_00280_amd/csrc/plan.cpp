@@ -404,20 +404,22 @@ void prof_clear_locked() {
 }
 }  // namespace
 
-spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s,
+                           const RecordWs *ws);
 
-spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
+spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s,
+                      const RecordWs *ws) {
     bool on;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         on = g_prof_on;
     }
-    if (!on) return run_mttkrp_impl(t, factors, rank, mode, out, s);
+    if (!on) return run_mttkrp_impl(t, factors, rank, mode, out, s, ws);
     ProfEvent e{mode, nullptr, nullptr};
     SPT_HIP(hipEventCreate(&e.a));
     SPT_HIP(hipEventCreate(&e.b));
     SPT_HIP(hipEventRecord(e.a, s));
-    spt_status st = run_mttkrp_impl(t, factors, rank, mode, out, s);
+    spt_status st = run_mttkrp_impl(t, factors, rank, mode, out, s, ws);
     SPT_HIP(hipEventRecord(e.b, s));
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back(e);
@@ -453,14 +455,21 @@ spt_status profile_read(double *ms, int64_t *launches) {
 // records are radix-sorted by row first.  The record buffers belong to the
 // call (taken and released in stream order on s).
 spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int64_t rows, float *out, hipStream_t s,
-                              bool segment, TableArgs *ta = nullptr, int nwg = 0) {
+                              bool segment, TableArgs *ta = nullptr, int nwg = 0, const RecordWs *ws = nullptr) {
     const size_t n1 = (size_t)std::max<int64_t>(P, 1);
-    uint64_t *rrow = (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s);
-    float *rval = (float *)dev_alloc(sizeof(float) * n1 * rank, s);
+    // SEGMENT records go to the caller's workspace when they fit
+    const bool own = !(segment && ws && ws->row && ws->val && (int64_t)n1 <= ws->records &&
+                       (int64_t)n1 * rank <= ws->val_floats);
+    uint64_t *rrow = own ? (uint64_t *)dev_alloc(sizeof(uint64_t) * n1, s) : ws->row;
+    float *rval = own ? (float *)dev_alloc(sizeof(float) * n1 * rank, s) : ws->val;
     uint64_t *keys2 = nullptr;
     uint32_t *ia = nullptr, *ib = nullptr, *cnt = nullptr;
     auto release = [&]() {
-        dev_free(rrow, s); dev_free(rval, s); dev_free(keys2, s); dev_free(ia, s); dev_free(ib, s); dev_free(cnt, s);
+        if (own) {
+            dev_free(rrow, s);
+            dev_free(rval, s);
+        }
+        dev_free(keys2, s); dev_free(ia, s); dev_free(ib, s); dev_free(cnt, s);
     };
     if (!rrow || !rval) {
         release();
@@ -496,7 +505,15 @@ spt_status reduce_via_records(Tensor *t, MttkrpArgs &a, int64_t P, int rank, int
     return st;
 }
 
-spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s) {
+int64_t max_plan_records(const Tensor *t) {
+    int64_t m = 0;
+    for (int n = 0; n < t->nmodes; ++n)
+        if (t->mplan[n].valid) m = std::max<int64_t>(m, t->mplan[n].records);
+    return m;
+}
+
+spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s,
+                           const RecordWs *ws) {
     ModePlan *p = nullptr;
     spt_status st = resolve_plan(t, mode, rank, s, &p, false);
     if (st != SPT_OK) return st;
@@ -525,7 +542,7 @@ spt_status run_mttkrp_impl(Tensor *t, const float *const *factors, int rank, int
                 a.d_cap = cap;
             }
         }
-        return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/true);
+        return reduce_via_records(t, a, p->records, rank, rows, out, s, /*segment=*/true, nullptr, 0, ws);
     }
     if (t->nnz == 0 || p->strategy == SPT_STRATEGY_SEGMENT || p->strategy == SPT_STRATEGY_DIRECT ||
         p->strategy == SPT_STRATEGY_REGROUP) {

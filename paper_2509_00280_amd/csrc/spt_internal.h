@@ -50,6 +50,8 @@ void make_codec(int nmodes, const int *lbits, const uint8_t *layout, int lp, Cod
 // ---------------------------------------------------------------- device memory
 void *dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
+spt_status memory_stats(int64_t *stats);
+spt_status empty_cache();
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
@@ -118,7 +120,19 @@ spt_status resolve_plan(Tensor *t, int mode, int rank, hipStream_t s, ModePlan *
 // every mode's plan at `rank` and the tile dictionaries (synchronises s)
 spt_status prepare_single(Tensor *t, int rank, hipStream_t s);
 // mode-`mode` MTTKRP into out (overwritten), per the tensor's prepared plan
-spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s);
+// A caller-owned record workspace: an MTTKRP call whose SEGMENT records fit
+// writes them there instead of allocating (a driver that calls every mode in
+// turn on one stream allocates once).
+struct RecordWs {
+    uint64_t *row = nullptr;
+    float *val = nullptr;
+    int64_t records = 0;    // capacity in records
+    int64_t val_floats = 0;  // capacity of val
+};
+// the largest record count over the tensor's modes under its prepared plans
+int64_t max_plan_records(const Tensor *t);
+spt_status run_mttkrp(Tensor *t, const float *const *factors, int rank, int mode, float *out, hipStream_t s,
+                      const RecordWs *ws = nullptr);
 // FP64 MTTKRP (FP64 values, factors, records and accumulation) on the SEGMENT plan
 spt_status run_mttkrp_f64(Tensor *t, const double *const *factors, int rank, int mode, double *out, hipStream_t s);
 // the same with the record workspace in the library's fixed device array

@@ -127,6 +127,8 @@ def lib():
     _sig(L, "spt_server_destroy", None, [_VP])
     _sig(L, "spt_profile_enable", st, [i])
     _sig(L, "spt_profile_read", st, [ctypes.POINTER(d), ctypes.POINTER(i64)])
+    _sig(L, "spt_memory_stats", st, [ctypes.POINTER(i64)])
+    _sig(L, "spt_empty_cache", st, [])
     _LIB = L
     return L
 
@@ -682,6 +684,19 @@ def profile_read() -> dict:
     n = (ctypes.c_int64 * MAX_MODES)()
     _check(lib().spt_profile_read(ms, n))
     return {"mttkrp_ms": list(ms), "mttkrp_launches": list(n)}
+
+
+def memory_stats() -> dict:
+    """The library's device block cache: bytes in live buffers and in idle
+    blocks, hipMalloc calls and requests served from idle blocks so far."""
+    v = (ctypes.c_int64 * 4)()
+    _check(lib().spt_memory_stats(v))
+    return {"bytes_live": v[0], "bytes_idle": v[1], "device_allocs": v[2], "reuses": v[3]}
+
+
+def empty_cache():
+    """Return the idle blocks of the library's cache to the driver."""
+    _check(lib().spt_empty_cache())
 
 
 def version() -> str:
