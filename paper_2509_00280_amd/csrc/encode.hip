@@ -6,9 +6,10 @@
 // Radix sort design (one pass per 8-bit digit):
 //   hist    : per 4096-element tile, a 256-bin digit histogram (per-wave LDS bins)
 //   scan    : one workgroup per digit scans the tiles' counts (digit-major array)
-//   scatter : each tile ranks its elements stably (wave ballots give the rank among
-//             equal digits in lane order, LDS carries counts across waves and rounds),
-//             regroups them by digit in LDS, then writes runs of equal digit
+//   scatter : each wave ranks a contiguous quarter of the tile stably on its own
+//             (ballots order equal digits by lane, the wave's LDS counters carry
+//             them across rounds), one barrier merges the waves' counts, then the
+//             tile is regrouped by digit in LDS and runs of equal digit are written
 //             contiguously so global stores coalesce.
 #include "tile_common.h"
 
@@ -135,76 +136,103 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     uint64_t *__restrict__ out_lo, uint64_t *__restrict__ out_hi, uint32_t *__restrict__ out_idx, int64_t n,
     int word, int shift, const uint32_t *__restrict__ counts, const uint32_t *__restrict__ totals, int nblocks) {
     constexpr int TILE = kThreads * ITEMS;
+    constexpr int WAVES = kThreads / 64;
+    constexpr int WSPAN = 64 * ITEMS;  // consecutive elements ranked by one wave
+    static_assert(WSPAN < (1 << 24), "rank field");
     __shared__ uint64_t s_lo[TILE];
     __shared__ uint64_t s_hi[KW == 2 ? TILE : 1];
     __shared__ uint32_t s_idx[TILE];
+    __shared__ uint32_t wcnt[WAVES][256];  // per wave and digit: count, then the waves' exclusive offsets
     __shared__ uint32_t digit_off[256];
     __shared__ uint32_t local_start[256];
-    __shared__ uint32_t run_cnt[256];
-    __shared__ uint32_t wc[4][256];
     __shared__ uint32_t wsum[4];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int b = blockIdx.x;
     const int64_t base = (int64_t)b * TILE;
+    const int64_t wbase = base + (int64_t)wave * WSPAN;
 
-    {
-        const uint32_t tot = totals[tid];
-        const uint32_t digit_base = block_scan_256(tot, wsum);
-        const uint32_t mine = counts[(int64_t)tid * nblocks + b];
-        const uint32_t next = (b + 1 < nblocks) ? counts[(int64_t)tid * nblocks + b + 1] : tot;
-        const uint32_t cnt_b = next - mine;
-        digit_off[tid] = digit_base + mine;
-        local_start[tid] = block_scan_256(cnt_b, wsum);
-        run_cnt[tid] = 0;
+    // every load of the wave's span is issued before the ranking waits for one
+    uint64_t klo[ITEMS], khi[ITEMS];
+    uint32_t idx[ITEMS], dr[ITEMS];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t e = wbase + i * 64 + lane;
+        klo[i] = 0;
+        khi[i] = 0;
+        idx[i] = (uint32_t)e;
+        if (e < n) {
+            klo[i] = in_lo[e];
+            if (KW == 2) khi[i] = in_hi[e];
+            if (in_idx) idx[i] = in_idx[e];
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) wcnt[w][tid] = 0;
+    {
+        const uint32_t digit_base = block_scan_256(totals[tid], wsum);  // synchronises the block
+        digit_off[tid] = digit_base + counts[(int64_t)tid * nblocks + b];
     }
     __syncthreads();
 
+    // Rank within the wave: equal digits of one round are ordered by lane
+    // (ballots), rounds in order through the wave's own LDS counters.  The
+    // counter update of a digit's first lane takes the value read by the whole
+    // wave, so no other wave and no barrier is involved.
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const int64_t e = base + i * kThreads + tid;
-        const bool valid = e < n;
-        uint64_t klo = 0, khi = 0;
-        uint32_t idx = 0, d = 0;
-        if (valid) {
-            klo = in_lo[e];
-            if (KW == 2) khi = in_hi[e];
-            idx = in_idx ? in_idx[e] : (uint32_t)e;
-            d = (uint32_t)(((word == 0) ? klo : khi) >> shift) & 255u;
-        }
+        const bool valid = wbase + i * 64 + lane < n;
+        const uint32_t d = (uint32_t)(((word == 0) ? klo[i] : khi[i]) >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
             const uint64_t m = __ballot(valid && ((d >> bit) & 1u));
             peers &= ((d >> bit) & 1u) ? m : ~m;
         }
-        const uint32_t rank_w = __popcll(peers & lt_mask);
-        if (valid && rank_w == 0) wc[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = local_start[d] + run_cnt[d] + rank_w;
-            for (int w = 0; w < wave; ++w) pos += wc[w][d];
-            s_lo[pos] = klo;
-            if (KW == 2) s_hi[pos] = khi;
-            s_idx[pos] = idx;
-        }
-        __syncthreads();
-        run_cnt[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
-        __syncthreads();
+        const uint32_t before = __popcll(peers & lt_mask);
+        uint32_t old = 0;
+        if (valid) old = wcnt[wave][d];
+        if (valid && before == 0) wcnt[wave][d] = old + (uint32_t)__popcll(peers);
+        dr[i] = d | ((old + before) << 8);
     }
+    __syncthreads();
 
+    // digit d of this tile starts at local_start[d]; wave w's part of it
+    // follows the parts of waves 0..w-1
+    {
+        uint32_t c[WAVES], run = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) c[w] = wcnt[w][tid];
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            wcnt[w][tid] = run;
+            run += c[w];
+        }
+        local_start[tid] = block_scan_256(run, wsum);  // synchronises the block
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (wbase + i * 64 + lane < n) {
+            const uint32_t d = dr[i] & 255u;
+            const uint32_t pos = local_start[d] + wcnt[wave][d] + (dr[i] >> 8);
+            s_lo[pos] = klo[i];
+            if (KW == 2) s_hi[pos] = khi[i];
+            s_idx[pos] = idx[i];
+        }
+    }
+    __syncthreads();
+
+    // runs of equal digit are contiguous in LDS and in the output
     const int cnt = (int)((n - base) < TILE ? (n - base) : TILE);
     for (int q = tid; q < cnt; q += kThreads) {
-        const uint64_t klo = s_lo[q];
-        const uint64_t khi = (KW == 2) ? s_hi[q] : 0;
-        const uint32_t d = (uint32_t)(((word == 0) ? klo : khi) >> shift) & 255u;
+        const uint64_t klo_q = s_lo[q];
+        const uint64_t khi_q = (KW == 2) ? s_hi[q] : 0;
+        const uint32_t d = (uint32_t)(((word == 0) ? klo_q : khi_q) >> shift) & 255u;
         const int64_t dst = (int64_t)digit_off[d] + (q - (int)local_start[d]);
-        out_lo[dst] = klo;
-        if (KW == 2) out_hi[dst] = khi;
+        out_lo[dst] = klo_q;
+        if (KW == 2) out_hi[dst] = khi_q;
         out_idx[dst] = s_idx[q];
     }
 }
