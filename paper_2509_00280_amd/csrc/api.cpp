@@ -662,9 +662,8 @@ spt_status spt_cp_als(spt_tensor t, int rank, int max_iters, double tol, float *
             const int64_t In = t->dims[n];
             CK(run_mttkrp(t, (const float *const *)F, R, n, M, s, &ws));
             CK(launch_gram(M, In, R, gram_m, gwork, gw, s));
-            CK(launch_solve_prep(grams, N, n, R, gram_m, S, lam, status + n, s));
+            CK(launch_solve_prep(grams, N, n, R, gram_m, S, lam, status + n, grams + (size_t)n * R * R, s));
             CK(launch_apply(M, In, R, S, F[n], lam, n == N - 1 ? inner : nullptr, nullptr, s));
-            CK(launch_gram(F[n], In, R, grams + (size_t)n * R * R, gwork, gw, s));
         }
         CK(launch_fit(grams, N, R, lam, inner, inner_parts, t->norm_x2, fitd, s));
         double hf[4];
@@ -746,7 +745,7 @@ spt_status spt_als_update(const double *grams, int nmodes, int mode, int rank, c
     spt_status st = SPT_OK;
     if (rows > 0) st = launch_gram(M, rows, R, gram_m, gwork, gw, s);
     else st = launch_fill_zero((float *)gram_m, 2 * (int64_t)R * R, s);  // FP64 zeros are all-zero bits
-    if (st == SPT_OK) st = launch_solve_prep(grams, nmodes, mode, R, gram_m, S, lam, status, s);
+    if (st == SPT_OK) st = launch_solve_prep(grams, nmodes, mode, R, gram_m, S, lam, status, nullptr, s);
     int hs = 0;
     if (st == SPT_OK && (hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
                          hipStreamSynchronize(s) != hipSuccess))

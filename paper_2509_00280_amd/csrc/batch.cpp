@@ -376,7 +376,7 @@ spt_status BatchEngine::rebuild() {
     for (int n = 0; n < nmodes_max_; ++n) {
         ModeItems &mi = modes_[n];
         std::vector<SegItem> seg;
-        std::vector<GramItem> gm, gc;
+        std::vector<GramItem> gm;
         std::vector<SolveItem> sv;
         std::vector<ApplyItem> ap;
         int rmax = 0;
@@ -416,6 +416,7 @@ spt_status BatchEngine::rebuild() {
             so.S = m->S;
             so.lambda = m->lambda;
             so.status = nullptr;  // rebased below (status_all + 8 i)
+            so.gram_new = m->grams + (size_t)n * R * R;  // the solve forms the new factor's Gram
             so.nmodes = t->nmodes;
             so.rank = R;
             sv.push_back(so);
@@ -436,13 +437,6 @@ spt_status BatchEngine::rebuild() {
             ai.ldm = ld;
             ai.rank = R;
             ap.push_back(ai);
-            GramItem g2{};
-            g2.C = m->F[n];
-            g2.rows = In;
-            g2.ld = R;
-            g2.rank = R;
-            g2.G = m->grams + (size_t)n * R * R;
-            gc.push_back(g2);
             mi.member_idx.push_back(i);
             tiles += (t->nnz + tile_ - 1) / tile_;
             recs += t->bplan[n].records;
@@ -461,13 +455,10 @@ spt_status BatchEngine::rebuild() {
         max_records = std::max(max_records, recs);
         mi.seg_v = std::move(seg);
         mi.gm_slices = assign_slices(gm);
-        mi.gc_slices = assign_slices(gc);
-        gram_need = std::max(gram_need, std::max(gram_batched_ws_bytes(mi.gm_slices, rmax),
-                                                 gram_batched_ws_bytes(mi.gc_slices, rmax)));
+        gram_need = std::max(gram_need, gram_batched_ws_bytes(mi.gm_slices, rmax));
         mi.gm_v = std::move(gm);
         mi.sv_v = std::move(sv);
         mi.ap_v = std::move(ap);
-        mi.gc_v = std::move(gc);
     }
     (void)max_records;
     // device buffers that item pointers refer to (replaced in stream order)
@@ -503,7 +494,6 @@ spt_status BatchEngine::rebuild() {
         mi.gm_off = put(mi.gm_v.data(), sizeof(GramItem) * mi.gm_v.size());
         mi.sv_off = put(mi.sv_v.data(), sizeof(SolveItem) * mi.sv_v.size());
         mi.ap_off = put(mi.ap_v.data(), sizeof(ApplyItem) * mi.ap_v.size());
-        mi.gc_off = put(mi.gc_v.data(), sizeof(GramItem) * mi.gc_v.size());
     }
     fit_off_ = put(fit.data(), sizeof(FitItem) * fit.size());
     // initial Grams of the new members' factors
@@ -568,9 +558,6 @@ spt_status BatchEngine::step(bool *before_kernels) {
         if (st == SPT_OK) st = launch_solve_prep_batched((const SolveItem *)(d_items_ + mi.sv_off), mi.count, n, s_);
         if (st == SPT_OK)
             st = launch_apply_batched((const ApplyItem *)(d_items_ + mi.ap_off), mi.count, mi.blocks, mi.rmax, s_);
-        if (st == SPT_OK)
-            st = launch_gram_batched((const GramItem *)(d_items_ + mi.gc_off), mi.count, mi.gc_slices, mi.rmax,
-                                     (double *)gram_ws_.p, s_);
         if (st != SPT_OK) return st;
     }
     spt_status st = launch_fit_batched((const FitItem *)(d_items_ + fit_off_), A, s_);

@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restr
 constexpr int kSolveThreads = 1024;  // 16 waves: 4 matrix elements per thread at R = 64
 __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                 const double *__restrict__ gram_m, double *__restrict__ S,
-                                                double *__restrict__ lambda, int *__restrict__ status) {
+                                                double *__restrict__ lambda, int *__restrict__ status,
+                                                double *__restrict__ gram_new) {
     __shared__ double A[64 * 64];
     __shared__ double B[64 * 64];
     const int tid = threadIdx.x;
@@ -387,19 +388,38 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         lambda[r] = lam_s[r];
     }
     __syncthreads();
+    // The Gram of the new factor C = M S without reading C: C^T C = S^T Gm S,
+    // and with S = W diag(1/lambda), W symmetric, its (p, q) entry is
+    // (W Tm)[p][q] / (lambda_p lambda_q).  FP64 throughout, so it is the Gram
+    // of the exact product rather than of C rounded to FP32.  Only the other
+    // modes' Grams were read above, so the slot of `mode` may be overwritten.
+    if (gram_new) {
+#pragma unroll
+        for (int m = 0; m < PT; ++m) {
+            const int e = tid + m * kSolveThreads;
+            if (e < RR) {
+                const int p = ei[m], q = ek[m];
+                double acc = 0.0;
+                for (int a = 0; a < R; ++a) acc += B[p * R + a] * A[a * R + q];
+                gram_new[e] = acc / (lam_s[p] * lam_s[q]);
+            }
+        }
+    }
     for (int e = tid; e < RR; e += kSolveThreads) S[e] = B[e] / lam_s[e % R];
     if (tid == 0) *status = attempt;
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_solve_prep(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                          const double *__restrict__ gram_m, double *__restrict__ S,
-                                                         double *__restrict__ lambda, int *__restrict__ status) {
-    solve_prep_body(grams, nmodes, mode, R, gram_m, S, lambda, status);
+                                                         double *__restrict__ lambda, int *__restrict__ status,
+                                                         double *__restrict__ gram_new) {
+    solve_prep_body(grams, nmodes, mode, R, gram_m, S, lambda, status, gram_new);
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_solve_prep_batched(const SolveItem *__restrict__ items, int mode) {
     const SolveItem &it = items[blockIdx.x];
-    solve_prep_body(it.grams, it.nmodes, mode, it.rank, it.gram_m, it.S, it.lambda, it.status + mode);
+    solve_prep_body(it.grams, it.nmodes, mode, it.rank, it.gram_m, it.S, it.lambda, it.status + mode,
+                    it.gram_new);
 }
 
 // ------------------------------------------------------------------ apply
@@ -679,10 +699,10 @@ spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double
 }
 
 spt_status launch_solve_prep(const double *grams, int nmodes, int mode, int rank, const double *gram_m, double *S,
-                             double *lambda, int *status_out, hipStream_t s) {
+                             double *lambda, int *status_out, double *gram_new, hipStream_t s) {
     if (rank > 64) return fail(SPT_E_INVALID_ARG, "solve: rank above 64");
     hipLaunchKernelGGL(k_solve_prep, dim3(1), dim3(kSolveThreads), 0, s, grams, nmodes, mode, rank, gram_m, S, lambda,
-                       status_out);
+                       status_out, gram_new);
     SPT_HIP(hipGetLastError());
     return SPT_OK;
 }

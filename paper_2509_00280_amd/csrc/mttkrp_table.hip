@@ -391,7 +391,7 @@ __global__ __launch_bounds__(256) void k_reduce_priv(const float *__restrict__ p
 #define SPT_RED_UB 8
 #endif
 #ifndef SPT_RED_CHUNK
-#define SPT_RED_CHUNK 256
+#define SPT_RED_CHUNK 512
 #endif
 
 template <int G, int VEC, int NB>

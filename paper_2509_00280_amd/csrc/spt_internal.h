@@ -277,6 +277,7 @@ struct SolveItem {
     const double *gram_m; // rank x rank Gram of the MTTKRP output
     double *S, *lambda;
     int *status;          // nmodes entries; entry `mode` is written
+    double *gram_new;     // rank x rank: Gram of the updated factor (the member's slot of `mode`)
     int nmodes, rank;
 };
 struct ApplyItem {
@@ -325,11 +326,11 @@ struct ModeItems {
     int count = 0, ld = 0, rmax = 0;
     bool vec4 = true;
     int64_t tiles = 0, records = 0, rows = 0, blocks = 0;
-    size_t seg_off = 0, gm_off = 0, sv_off = 0, ap_off = 0, gc_off = 0;
+    size_t seg_off = 0, gm_off = 0, sv_off = 0, ap_off = 0;
     std::vector<int> member_idx;
     std::vector<SegItem> seg_v;
-    std::vector<GramItem> gm_v, gc_v;
-    int64_t gm_slices = 0, gc_slices = 0;
+    std::vector<GramItem> gm_v;
+    int64_t gm_slices = 0;
     std::vector<SolveItem> sv_v;
     std::vector<ApplyItem> ap_v;
 };
@@ -473,8 +474,9 @@ spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double
 size_t gram_work_bytes(int64_t rows, int rank);
 // solve preparation: V = Hadamard of grams[k != mode]; Cholesky with ridge; W = V^-1;
 // lambda_r = sqrt((W Gm W)_rr) (1 if 0); S = W diag(1/lambda).  status_out: 0 ok, >0 ridge retries, <0 failure.
+// gram_new (or null): the Gram S^T Gm S of the updated factor M S, in FP64 (may be grams + mode * rank^2).
 spt_status launch_solve_prep(const double *grams, int nmodes, int mode, int rank, const double *gram_m,
-                             double *S, double *lambda, int *status_out, hipStream_t s);
+                             double *S, double *lambda, int *status_out, double *gram_new, hipStream_t s);
 // C = fp32(M S) row by row; optional fused inner-product partials sum_{i,r} M C lambda.
 spt_status launch_apply(const float *M, int64_t rows, int rank, const double *S, float *C,
                         const double *lambda, double *inner_partials, int *nparts_out, hipStream_t s);
