@@ -51,10 +51,11 @@ constexpr int kUnrollDict = 2;       // the same, row-cached walk
 #endif
 constexpr int kSegpThreads4096 = SPT_SEGP_NT4096;  // threads of the MTTKRP kernel on 4096-nonzero tiles
 
-// LDS of the hashing stage: crdg[nm - 1][T] u32 (non-output coordinates,
-// row-grouped), valg[T] f32, hkey[T] u32 (slot -> row), hcnt[T + 4] u32
-// (packed counts, then prefixes; entry T holds the totals), ptab[T] u16
-// (piece -> slot).
+// A tile staged together with its hash tables: crdg[nm - 1][T] u32
+// (non-output coordinates, row-grouped), valg[T] f32, hkey[T] u32 (slot ->
+// row), hcnt[T + 4] u32 (packed counts, then prefixes; entry T holds the
+// totals), ptab[T] u16 (piece -> slot).  The budget that decides which tile
+// sizes a tensor of nmodes modes may use (seg_tile_ok).
 __host__ __device__ inline size_t seg_lds_bytes(int T, int nmodes) {
     return (size_t)(nmodes - 1) * T * 4 + (size_t)T * 4 + (size_t)T * 4 + (size_t)(T + 4) * 4 + (size_t)T * 2;
 }
@@ -72,10 +73,16 @@ struct SegLds {
     uint16_t *ptab;
 };
 
-__device__ __forceinline__ SegLds seg_carve(char *p, int T, int nmodes) {
+// LDS of the plan's counting and emission passes, which stage nothing:
+// occ[T] u32 (emission's pair index per slot), hkey[T], hcnt[T + 4] u32 and
+// ptab[T] u16.  About half of seg_lds_bytes at 4 modes, so two 1024-thread
+// workgroups share a CU.
+__host__ __device__ inline size_t seg_plan_lds_bytes(int T) { return (size_t)T * 12 + 16 + (size_t)T * 2; }
+
+__device__ __forceinline__ SegLds seg_carve_plan(char *p, int T) {
     SegLds L;
-    L.crdg = (uint32_t *)p;
-    L.valg = (float *)(L.crdg + (size_t)(nmodes - 1) * T);
+    L.crdg = nullptr;
+    L.valg = (float *)p;
     L.hkey = (uint32_t *)(L.valg + T);
     L.hcnt = L.hkey + T;
     L.ptab = (uint16_t *)(L.hcnt + T + 4);
@@ -871,7 +878,7 @@ __device__ __forceinline__ void emit_tile(const MttkrpArgs &a, int64_t tile, cha
                                           uint32_t *__restrict__ ppair, uint32_t *__restrict__ psub,
                                           uint64_t *__restrict__ pair_key, uint32_t *__restrict__ pair_np) {
     constexpr int T = 4 * NT;
-    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const SegLds L = seg_carve_plan(lds, T);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum, pos);
     // pair index of every occupied slot: exclusive count of occupied slots before it
@@ -1026,7 +1033,7 @@ __global__ __launch_bounds__(NT) void k_count_pieces(MttkrpArgs a, int64_t ntile
     extern __shared__ __align__(16) char lds[];
     __shared__ uint32_t wsum[NT / 64];
     const int64_t tile = blockIdx.x;
-    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const SegLds L = seg_carve_plan(lds, T);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, tile, L, cr, wsum);
     const int64_t c = tile_counts<T>(L);
@@ -1042,7 +1049,7 @@ __global__ __launch_bounds__(NT) void k_count_pieces_batched(const SegItem *__re
     const int64_t it = blockIdx.x;
     const int b = seg_item_of(items, count, it);
     const MttkrpArgs &a = items[b].a;
-    const SegLds L = seg_carve(lds, T, a.nmodes);
+    const SegLds L = seg_carve_plan(lds, T);
     const CodecRegs cr = load_codec_regs(a.codec);
     seg_stage<NT, NMAX, false>(a, it - items[b].first_tile, L, cr, wsum);
     const int64_t c = tile_counts<T>(L);
@@ -1096,7 +1103,7 @@ spt_status launch_seg_nt(const MttkrpArgs &a, int64_t ntiles, hipStream_t s) {
 
 template <int NT>
 spt_status launch_emit_nt(const MttkrpArgs &a, int64_t ntiles, const PlanOut &o, hipStream_t s) {
-    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
+    const size_t lds = seg_plan_lds_bytes(4 * NT);
     if (a.nmodes <= 4)
         hipLaunchKernelGGL((k_emit_plan<NT, 4>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, o.pair_off, o.pos,
                            o.desc, o.prow, o.ppair, o.psub, o.pair_key, o.pair_np);
@@ -1109,7 +1116,7 @@ spt_status launch_emit_nt(const MttkrpArgs &a, int64_t ntiles, const PlanOut &o,
 
 template <int NT>
 spt_status launch_count_nt(const MttkrpArgs &a, int64_t ntiles, int64_t *out, hipStream_t s) {
-    const size_t lds = seg_lds_bytes(4 * NT, a.nmodes);
+    const size_t lds = seg_plan_lds_bytes(4 * NT);
     if (a.nmodes <= 4)
         hipLaunchKernelGGL((k_count_pieces<NT, 4>), dim3((unsigned)ntiles), dim3(NT), lds, s, a, ntiles, out);
     else
@@ -1248,11 +1255,11 @@ void launch_emit_b(const SegItem *items, int count, int64_t total_tiles, int nmo
                    hipStream_t s) {
     constexpr int T = 4 * NT;
     if (nmodes_max <= 4)
-        hipLaunchKernelGGL((k_emit_plan_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT), seg_lds_bytes(T, 4), s,
+        hipLaunchKernelGGL((k_emit_plan_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT), seg_plan_lds_bytes(T), s,
                            items, count, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np);
     else
         hipLaunchKernelGGL((k_emit_plan_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
-                           seg_lds_bytes(T, nmodes_max), s,
+                           seg_plan_lds_bytes(T), s,
                            items, count, gpiece_off, gpair_off, ppair, psub, pair_key, pair_np);
 }
 
@@ -1261,11 +1268,11 @@ void launch_count_b(const SegItem *items, int count, int64_t total_tiles, int nm
                     hipStream_t s) {
     constexpr int T = 4 * NT;
     if (nmodes_max <= 4)
-        hipLaunchKernelGGL((k_count_pieces_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT), seg_lds_bytes(T, 4), s,
+        hipLaunchKernelGGL((k_count_pieces_batched<NT, 4>), dim3((unsigned)total_tiles), dim3(NT), seg_plan_lds_bytes(T), s,
                            items, count, total_tiles, counts);
     else
         hipLaunchKernelGGL((k_count_pieces_batched<NT, 8>), dim3((unsigned)total_tiles), dim3(NT),
-                           seg_lds_bytes(T, nmodes_max), s,
+                           seg_plan_lds_bytes(T), s,
                            items, count, total_tiles, counts);
 }
 }  // namespace
