@@ -229,8 +229,11 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restr
 // ------------------------------------------------------------------ solve preparation
 // One workgroup; R <= 64.  LDS: two R x R FP64 matrices.  W = V^-1 from the
 // Cholesky factor: a right-looking factorisation and a right-looking forward
-// substitution, in both of which all threads update the matrix per column
-// (R barrier pairs each), then W = L^-T L^-1.
+// substitution, then W = L^-T L^-1.  In both sweeps every thread updates the
+// same matrix elements in place at every step, and the only values a step
+// reads from other threads (the pivot column, the pivot row) are staged in
+// a double-buffered vector by their owners during the step before: one
+// barrier per step.
 constexpr int kSolveThreads = 1024;  // 16 waves: 4 matrix elements per thread at R = 64
 __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                 const double *__restrict__ gram_m, double *__restrict__ S,
@@ -238,6 +241,7 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
                                                 double *__restrict__ gram_new) {
     __shared__ double A[64 * 64];
     __shared__ double B[64 * 64];
+    __shared__ double vec[2][64];  // staged pivot column (Cholesky) or pivot row (substitution)
     const int tid = threadIdx.x;
     const int RR = R * R;
     // V = Hadamard product of the Grams of every mode except `mode` -> A
@@ -265,37 +269,39 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         for (int e = tid; e < RR; e += kSolveThreads) {
             const int i = e / R, j = e % R;
             B[e] = A[e] + (i == j ? ridge : 0.0);
+            if (j == 0) vec[0][i] = B[e];
         }
         __syncthreads();
-        // Right-looking Cholesky V = L L^T in place (lower triangle of B): per
-        // column every thread updates its elements of the trailing matrix
-        // from the values before the step.  All threads read the same pivot.
+        // Right-looking Cholesky V = L L^T in place (lower triangle of B): at
+        // step j every thread updates its elements of the trailing matrix
+        // from column j as it was before the step (vec[j & 1]), and the owners
+        // of column j + 1 stage its updated values for the next step.  All
+        // threads read the same pivot, so they leave the loop together.
         bool ok = true;
         for (int j = 0; j < R; ++j) {
-            const double d = B[j * R + j];
+            const double *cj = vec[j & 1];
+            double *cn = vec[(j + 1) & 1];
+            const double d = cj[j];
             if (!(d > 0.0) || !isfinite(d)) {
                 ok = false;
                 break;
             }
             const double l = sqrt(d), il = 1.0 / l, id = 1.0 / d;
-            double nv[PT];
 #pragma unroll
             for (int m = 0; m < PT; ++m) {
                 const int e = tid + m * kSolveThreads;
-                nv[m] = 0.0;
                 if (e < RR) {
                     const int i = ei[m], k = ek[m];
-                    const double x = B[e];
-                    if (k == j) nv[m] = i == j ? l : (i > j ? x * il : x);
-                    else if (i > j && k > j && k <= i) nv[m] = x - B[i * R + j] * B[k * R + j] * id;
-                    else nv[m] = x;
+                    double x = B[e];
+                    if (k == j) {
+                        x = i == j ? l : (i > j ? x * il : x);
+                        B[e] = x;
+                    } else if (i > j && k > j && k <= i) {
+                        x -= cj[i] * cj[k] * id;
+                        B[e] = x;
+                    }
+                    if (k == j + 1 && i > j) cn[i] = x;
                 }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < PT; ++m) {
-                const int e = tid + m * kSolveThreads;
-                if (e < RR) B[e] = nv[m];
             }
             __syncthreads();
         }
@@ -306,29 +312,34 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         if (tid == 0) *status = -1;
         return;
     }
-    // X = L^-1 into A by right-looking forward substitution on the identity
-    for (int e = tid; e < RR; e += kSolveThreads) A[e] = (e / R == e % R) ? 1.0 : 0.0;
+    // X = L^-1 into A by right-looking forward substitution on the identity:
+    // at step i every thread updates its elements of rows below i from row i
+    // as it was before the step (vec[i & 1]); the owners of row i + 1 stage
+    // its updated values.  L (in B) is only read.
+    for (int e = tid; e < RR; e += kSolveThreads) {
+        A[e] = (e / R == e % R) ? 1.0 : 0.0;
+        if (e < R) vec[0][e] = A[e];
+    }
     __syncthreads();
     for (int i = 0; i < R; ++i) {
+        const double *ri = vec[i & 1];
+        double *rn = vec[(i + 1) & 1];
         const double ii = 1.0 / B[i * R + i];
-        double nv[PT];
 #pragma unroll
         for (int m = 0; m < PT; ++m) {
             const int e = tid + m * kSolveThreads;
-            nv[m] = 0.0;
             if (e < RR) {
                 const int k = ei[m], c = ek[m];
-                const double x = A[e];
-                if (k == i) nv[m] = x * ii;
-                else if (k > i && c <= i) nv[m] = x - B[k * R + i] * A[i * R + c] * ii;
-                else nv[m] = x;
+                double x = A[e];
+                if (k == i) {
+                    x *= ii;
+                    A[e] = x;
+                } else if (k > i && c <= i) {
+                    x -= B[k * R + i] * ri[c] * ii;
+                    A[e] = x;
+                }
+                if (k == i + 1) rn[c] = x;
             }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            if (e < RR) A[e] = nv[m];
         }
         __syncthreads();
     }
