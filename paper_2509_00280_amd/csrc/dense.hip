@@ -522,16 +522,30 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const float *__restrict
     __syncthreads();
     const int mrow = lane & 15, kq = lane >> 4;
     const int64_t ntile = (rows + 15) / 16;
+    const bool vec_ok = R == RP && ((uintptr_t)M & 15u) == 0;
     double inner = 0.0;
     for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave; t < ntile;
          t += (int64_t)gridDim.x * (kThreads / 64)) {
         const int64_t r0 = t * 16;
         const int64_t arow = r0 + mrow;
         float a[KS];
+        if (vec_ok && arow < rows) {
+            // the lane's KS values are contiguous and 16-byte aligned: vector loads
+            const float4 *mp = reinterpret_cast<const float4 *>(M + arow * R + kq * KS);
 #pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            const int c = kq * KS + j;
-            a[j] = (arow < rows && c < R) ? M[arow * R + c] : 0.f;
+            for (int j4 = 0; j4 < KS / 4; ++j4) {
+                const float4 v = mp[j4];
+                a[4 * j4] = v.x;
+                a[4 * j4 + 1] = v.y;
+                a[4 * j4 + 2] = v.z;
+                a[4 * j4 + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                const int c = kq * KS + j;
+                a[j] = (arow < rows && c < R) ? M[arow * R + c] : 0.f;
+            }
         }
         double4_t acc[NB];
 #pragma unroll
