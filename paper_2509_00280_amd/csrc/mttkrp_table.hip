@@ -541,7 +541,11 @@ spt_status launch_reduce_priv(const float *part, int nwg, int64_t rows, int R, f
 spt_status launch_reduce_records(const uint64_t *srow, const uint32_t *sidx, const float *rec_val, int64_t P, int R,
                                  int64_t rows, float *out, hipStream_t s) {
     if (P <= 0) return SPT_OK;
-    constexpr int chunk = SPT_RED_CHUNK;
+    // Long chunks mean fewer runs cut at a chunk edge (atomics), short ones
+    // less serial work per lane group: the longest chunk (up to
+    // SPT_RED_CHUNK) that still leaves 4096 lane groups, at least 64 records.
+    int chunk = SPT_RED_CHUNK;
+    while (chunk > 64 && P / chunk < 4096) chunk >>= 1;
     auto go = [&](auto kern, int G) -> spt_status {
         const int groups = 256 / G;
         const int64_t blocks = (P + (int64_t)groups * chunk - 1) / ((int64_t)groups * chunk);
