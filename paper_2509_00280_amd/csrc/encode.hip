@@ -19,19 +19,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ void deposit_runs(const CodecRegs &c, int n, uint32_t coord, uint32_t (&w)[4]) {
-#pragma unroll
-    for (int word = 0; word < 4; ++word) {
-        const int r0 = __builtin_amdgcn_readlane(c.rb, n * 5 + word);
-        const int r1 = __builtin_amdgcn_readlane(c.rb, n * 5 + word + 1);
-        for (int r = r0; r < r1; ++r) {
-            const uint32_t d = run_desc(c, r);
-            const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
-            w[word] |= __builtin_amdgcn_ubfe(coord, cpos, len) << kpos;
-        }
-    }
-}
-
 __device__ __forceinline__ uint32_t extract_runs(const CodecRegs &c, int n, const uint32_t (&w)[4]) {
     return decode_mode(c, n, 4, w);
 }
@@ -41,23 +28,62 @@ struct DimsArg {
 };
 
 // key = interleave(coords); idx = e.  err[0] counts out-of-range nonzeros,
-// err[1] holds the smallest offending nonzero index, err[2] its mode.
+// err[1] holds the smallest offending nonzero index, err[2] its mode.  Each
+// thread takes kDepositU nonzeros a grid stride apart per round: all their
+// coordinates are loaded before any key is formed, and every bit run of the
+// codec is applied to all of them.
+constexpr int kDepositU = 4;
 __global__ __launch_bounds__(kThreads) void k_deposit(const uint32_t *__restrict__ coords, int64_t nnz,
                                                       DimsArg dims, Codec codec, uint64_t *__restrict__ lo,
                                                       uint64_t *__restrict__ hi, int *__restrict__ err) {
     const CodecRegs cl = load_codec_regs(codec);
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kThreads) {
-        uint32_t w[4] = {0, 0, 0, 0};
-        for (int n = 0; n < codec.nmodes; ++n) {
-            const uint32_t i = __builtin_nontemporal_load(coords + (int64_t)n * nnz + e);
-            if (i >= dims.d[n]) {
-                atomicAdd(err, 1);
-                atomicMin((unsigned long long *)(err + 2), ((unsigned long long)e << 8) | (unsigned)n);
+    const int nm = codec.nmodes;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e0 = (int64_t)blockIdx.x * kThreads + threadIdx.x; e0 < nnz; e0 += stride * kDepositU) {
+        uint32_t c[kMaxModes][kDepositU];
+#pragma unroll
+        for (int n = 0; n < kMaxModes; ++n)
+#pragma unroll
+            for (int u = 0; u < kDepositU; ++u) {
+                const int64_t e = e0 + u * stride;
+                c[n][u] = 0;
+                if (n < nm && e < nnz) c[n][u] = __builtin_nontemporal_load(coords + (int64_t)n * nnz + e);
             }
-            deposit_runs(cl, n, i, w);
+        uint32_t w[kDepositU][4];
+#pragma unroll
+        for (int u = 0; u < kDepositU; ++u) w[u][0] = w[u][1] = w[u][2] = w[u][3] = 0;
+#pragma unroll
+        for (int n = 0; n < kMaxModes; ++n) {
+            if (n < nm) {
+#pragma unroll
+                for (int u = 0; u < kDepositU; ++u) {
+                    const int64_t e = e0 + u * stride;
+                    if (e < nnz && c[n][u] >= dims.d[n]) {
+                        atomicAdd(err, 1);
+                        atomicMin((unsigned long long *)(err + 2), ((unsigned long long)e << 8) | (unsigned)n);
+                    }
+                }
+#pragma unroll
+                for (int word = 0; word < 4; ++word) {
+                    const int r0 = __builtin_amdgcn_readlane(cl.rb, n * 5 + word);
+                    const int r1 = __builtin_amdgcn_readlane(cl.rb, n * 5 + word + 1);
+                    for (int r = r0; r < r1; ++r) {
+                        const uint32_t d = run_desc(cl, r);
+                        const uint32_t kpos = (d >> 8) & 31u, cpos = (d >> 16) & 31u, len = d >> 24;
+#pragma unroll
+                        for (int u = 0; u < kDepositU; ++u) w[u][word] |= __builtin_amdgcn_ubfe(c[n][u], cpos, len) << kpos;
+                    }
+                }
+            }
         }
-        lo[e] = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
-        if (codec.key_words == 2) hi[e] = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+#pragma unroll
+        for (int u = 0; u < kDepositU; ++u) {
+            const int64_t e = e0 + u * stride;
+            if (e < nnz) {
+                lo[e] = (uint64_t)w[u][0] | ((uint64_t)w[u][1] << 32);
+                if (codec.key_words == 2) hi[e] = (uint64_t)w[u][2] | ((uint64_t)w[u][3] << 32);
+            }
+        }
     }
 }
 
