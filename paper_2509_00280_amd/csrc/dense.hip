@@ -227,13 +227,16 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restr
 }
 
 // ------------------------------------------------------------------ solve preparation
-// One workgroup; R <= 64.  LDS: two R x R FP64 matrices.  W = V^-1 from the
-// Cholesky factor: a right-looking factorisation and a right-looking forward
-// substitution, then W = L^-T L^-1.  In both sweeps every thread updates the
-// same matrix elements in place at every step, and the only values a step
-// reads from other threads (the pivot column, the pivot row) are staged in
-// a double-buffered vector by their owners during the step before: one
-// barrier per step.
+// One workgroup; R <= 64.  LDS: three R x R FP64 matrices.  W = V^-1 from
+// the Cholesky factor: a right-looking factorisation V = L L^T and, in the
+// same sweep, a right-looking forward substitution X = L^-1 (step j of the
+// substitution needs only column j of L, which step j of the factorisation
+// forms), then W = X^T X.  Every thread updates the same matrix elements in
+// place at every step; the only values a step reads from other threads (the
+// pivot column, the pivot row of X) are staged in double-buffered vectors by
+// their owners during the step before: one barrier per step.  The pivot's
+// reciprocal square root comes from the hardware estimate and two Newton
+// steps, which gives l, 1/l and 1/l^2 without a square root or a divide.
 constexpr int kSolveThreads = 1024;  // 16 waves: 4 matrix elements per thread at R = 64
 __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                 const double *__restrict__ gram_m, double *__restrict__ S,
@@ -241,7 +244,9 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
                                                 double *__restrict__ gram_new) {
     __shared__ double A[64 * 64];
     __shared__ double B[64 * 64];
-    __shared__ double vec[2][64];  // staged pivot column (Cholesky) or pivot row (substitution)
+    __shared__ double Xs[64 * 64];
+    __shared__ double vec[2][64];   // staged pivot column of the factorisation
+    __shared__ double vecx[2][64];  // staged pivot row of X
     const int tid = threadIdx.x;
     const int RR = R * R;
     // V = Hadamard product of the Grams of every mode except `mode` -> A
@@ -269,24 +274,34 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         for (int e = tid; e < RR; e += kSolveThreads) {
             const int i = e / R, j = e % R;
             B[e] = A[e] + (i == j ? ridge : 0.0);
+            Xs[e] = i == j ? 1.0 : 0.0;
             if (j == 0) vec[0][i] = B[e];
+            if (i == 0) vecx[0][j] = Xs[e];
         }
         __syncthreads();
-        // Right-looking Cholesky V = L L^T in place (lower triangle of B): at
-        // step j every thread updates its elements of the trailing matrix
-        // from column j as it was before the step (vec[j & 1]), and the owners
-        // of column j + 1 stage its updated values for the next step.  All
-        // threads read the same pivot, so they leave the loop together.
+        // Step j: with column j of the working matrix as it was before the
+        // step (cj) and l = L[j][j], the factorisation scales column j and
+        // updates the trailing matrix (lower triangle of B), and the
+        // substitution scales row j of X and subtracts L[i][j] X[j][:] / l
+        // (= cj[i] X[j][:] / d) from the rows below, X[j][:] as it was before
+        // the step (rj).  The owners of column j + 1 and of row j + 1 of X
+        // stage them for the next step.  All threads read the same pivot, so
+        // they leave the loop together.
         bool ok = true;
         for (int j = 0; j < R; ++j) {
             const double *cj = vec[j & 1];
             double *cn = vec[(j + 1) & 1];
+            const double *rj = vecx[j & 1];
+            double *rn = vecx[(j + 1) & 1];
             const double d = cj[j];
             if (!(d > 0.0) || !isfinite(d)) {
                 ok = false;
                 break;
             }
-            const double l = sqrt(d), il = 1.0 / l, id = 1.0 / d;
+            double r = __builtin_amdgcn_rsq(d);
+            r = r * (1.5 - 0.5 * d * r * r);
+            r = r * (1.5 - 0.5 * d * r * r);
+            const double l = d * r, il = r, id = r * r;
 #pragma unroll
             for (int m = 0; m < PT; ++m) {
                 const int e = tid + m * kSolveThreads;
@@ -301,6 +316,15 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
                         B[e] = x;
                     }
                     if (k == j + 1 && i > j) cn[i] = x;
+                    double y = Xs[e];
+                    if (i == j) {
+                        y *= il;
+                        Xs[e] = y;
+                    } else if (i > j && k <= j) {
+                        y -= cj[i] * rj[k] * id;
+                        Xs[e] = y;
+                    }
+                    if (i == j + 1) rn[k] = y;
                 }
             }
             __syncthreads();
@@ -312,37 +336,6 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         if (tid == 0) *status = -1;
         return;
     }
-    // X = L^-1 into A by right-looking forward substitution on the identity:
-    // at step i every thread updates its elements of rows below i from row i
-    // as it was before the step (vec[i & 1]); the owners of row i + 1 stage
-    // its updated values.  L (in B) is only read.
-    for (int e = tid; e < RR; e += kSolveThreads) {
-        A[e] = (e / R == e % R) ? 1.0 : 0.0;
-        if (e < R) vec[0][e] = A[e];
-    }
-    __syncthreads();
-    for (int i = 0; i < R; ++i) {
-        const double *ri = vec[i & 1];
-        double *rn = vec[(i + 1) & 1];
-        const double ii = 1.0 / B[i * R + i];
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            if (e < RR) {
-                const int k = ei[m], c = ek[m];
-                double x = A[e];
-                if (k == i) {
-                    x *= ii;
-                    A[e] = x;
-                } else if (k > i && c <= i) {
-                    x -= B[k * R + i] * ri[c] * ii;
-                    A[e] = x;
-                }
-                if (k == i + 1) rn[c] = x;
-            }
-        }
-        __syncthreads();
-    }
     // W = X^T X = V^-1 into B
     {
         double wv[PT];
@@ -353,7 +346,7 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
             if (e < RR) {
                 const int p = ei[m], q = ek[m];
                 double acc = 0.0;
-                for (int i = p > q ? p : q; i < R; ++i) acc += A[i * R + p] * A[i * R + q];
+                for (int i = p > q ? p : q; i < R; ++i) acc += Xs[i * R + p] * Xs[i * R + q];
                 wv[m] = acc;
             }
         }
