@@ -237,6 +237,23 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce2(const double *__restr
 // their owners during the step before: one barrier per step.  The pivot's
 // reciprocal square root comes from the hardware estimate and two Newton
 // steps, which gives l, 1/l and 1/l^2 without a square root or a divide.
+// One 16 x 16 tile (ti, tj) of X^T Y for R x R row-major LDS matrices (R <=
+// 64) on v_mfma_f64_16x16x4_f64 (A[m][k] from lane m + 16 k, B[k][n] from
+// lane n + 16 k; D[m][n] in lane n + 16 (m % 4), element m / 4).  Indices at
+// or beyond R read as 0.  Every lane of the wave must be active.
+__device__ __forceinline__ double4_t solve_mfma_tile(const double *X, const double *Y, int R, int ti, int tj,
+                                                     int lane) {
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const int kq = lane >> 4, row = ti * 16 + (lane & 15), col = tj * 16 + (lane & 15);
+    for (int k0 = 0; k0 < R; k0 += 4) {
+        const int k = k0 + kq;
+        const double a = (k < R && row < R) ? X[k * R + row] : 0.0;
+        const double b = (k < R && col < R) ? Y[k * R + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 constexpr int kSolveThreads = 1024;  // 16 waves: 4 matrix elements per thread at R = 64
 __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams, int nmodes, int mode, int R,
                                                 const double *__restrict__ gram_m, double *__restrict__ S,
@@ -336,79 +353,46 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
         if (tid == 0) *status = -1;
         return;
     }
-    // W = X^T X = V^-1 into B
-    {
-        double wv[PT];
+    // The three R x R products below run on FP64 MFMA, one 16 x 16 output
+    // tile per wave.  Every left operand is read transposed (X^T, and the
+    // symmetric Gm and W), so a wave's reads of either operand run along a
+    // row of LDS.
+    const int wave = tid >> 6, lane = tid & 63, nt = (R + 15) / 16;
+    const bool tile_wave = wave < nt * nt;
+    const int ti = tile_wave ? wave / nt : 0, tj = tile_wave ? wave % nt : 0;
+    auto store_tile = [&](const double4_t &acc, double *dst) {
 #pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            wv[m] = 0.0;
-            if (e < RR) {
-                const int p = ei[m], q = ek[m];
-                double acc = 0.0;
-                for (int i = p > q ? p : q; i < R; ++i) acc += Xs[i * R + p] * Xs[i * R + q];
-                wv[m] = acc;
-            }
+        for (int e = 0; e < 4; ++e) {
+            const int r = ti * 16 + 4 * e + (lane >> 4), c = tj * 16 + (lane & 15);
+            if (r < R && c < R) dst[r * R + c] = acc[e];
         }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            if (e < RR) B[e] = wv[m];
-        }
-    }
-    __syncthreads();
-    // B = W = V^-1.  Tm = gram_m W into A (gram_m staged in A first)
+    };
+    // W = X^T X = V^-1 into B (L is no longer needed)
+    if (tile_wave) store_tile(solve_mfma_tile(Xs, Xs, R, ti, tj, lane), B);
     for (int e = tid; e < RR; e += kSolveThreads) A[e] = gram_m[e];
     __syncthreads();
-    {
-        double tv[PT];
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            tv[m] = 0.0;
-            if (e < RR) {
-                const int a = ei[m], r = ek[m];
-                double acc = 0.0;
-                for (int b = 0; b < R; ++b) acc += A[a * R + b] * B[b * R + r];
-                tv[m] = acc;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            if (e < RR) A[e] = tv[m];
-        }
-    }
+    // Tm = Gm W into Xs
+    if (tile_wave) store_tile(solve_mfma_tile(A, B, R, ti, tj, lane), Xs);
     __syncthreads();
-    // lambda_r^2 = sum_a W[r][a] Tm[a][r]
+    // P = W Tm = W Gm W into A (every read of Gm is done)
+    if (tile_wave) store_tile(solve_mfma_tile(B, Xs, R, ti, tj, lane), A);
+    __syncthreads();
+    // lambda_r^2 = P[r][r]
     __shared__ double lam_s[64];
     for (int r = tid; r < R; r += kSolveThreads) {
-        double s = 0.0;
-        for (int a = 0; a < R; ++a) s += B[r * R + a] * A[a * R + r];
-        const double l = s > 0.0 ? sqrt(s) : 0.0;
+        const double s2 = A[r * R + r];
+        const double l = s2 > 0.0 ? sqrt(s2) : 0.0;
         lam_s[r] = l > 0.0 ? l : 1.0;
         lambda[r] = lam_s[r];
     }
     __syncthreads();
     // The Gram of the new factor C = M S without reading C: C^T C = S^T Gm S,
     // and with S = W diag(1/lambda), W symmetric, its (p, q) entry is
-    // (W Tm)[p][q] / (lambda_p lambda_q).  FP64 throughout, so it is the Gram
-    // of the exact product rather than of C rounded to FP32.  Only the other
+    // P[p][q] / (lambda_p lambda_q).  FP64 throughout, so it is the Gram of
+    // the exact product rather than of C rounded to FP32.  Only the other
     // modes' Grams were read above, so the slot of `mode` may be overwritten.
-    if (gram_new) {
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = tid + m * kSolveThreads;
-            if (e < RR) {
-                const int p = ei[m], q = ek[m];
-                double acc = 0.0;
-                for (int a = 0; a < R; ++a) acc += B[p * R + a] * A[a * R + q];
-                gram_new[e] = acc / (lam_s[p] * lam_s[q]);
-            }
-        }
-    }
+    if (gram_new)
+        for (int e = tid; e < RR; e += kSolveThreads) gram_new[e] = A[e] / (lam_s[e / R] * lam_s[e % R]);
     for (int e = tid; e < RR; e += kSolveThreads) S[e] = B[e] / lam_s[e % R];
     if (tid == 0) *status = attempt;
 }
