@@ -277,13 +277,20 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
     double trace = 0.0;
     for (int i = 0; i < R; ++i) trace += A[i * R + i];
     const double ridge0 = 1e-12 * trace / R;
-    constexpr int PT = 64 * 64 / kSolveThreads;  // elements per thread (R <= 64)
-    int ei[PT], ek[PT];                     // row and column of each (e < RR)
+    // The sweep below changes only lower triangles (of the working matrix and
+    // of X): each thread owns up to PT of their R (R + 1) / 2 elements, the
+    // t-th in row i = largest with i (i + 1) / 2 <= t, column t - i (i + 1) / 2.
+    constexpr int PT = (64 * 65 / 2 + kSolveThreads - 1) / kSolveThreads;
+    const int RT = R * (R + 1) / 2;
+    int ei[PT], ek[PT];  // row and column of each owned element (t < RT)
 #pragma unroll
     for (int m = 0; m < PT; ++m) {
-        const int e = tid + m * kSolveThreads;
-        ei[m] = e / R;
-        ek[m] = e - ei[m] * R;
+        const int t = tid + m * kSolveThreads;
+        int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        while (i > 0 && i * (i + 1) / 2 > t) --i;
+        ei[m] = i;
+        ek[m] = t - i * (i + 1) / 2;
     }
     int attempt = 0;
     for (; attempt < 4; ++attempt) {
@@ -321,9 +328,8 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
             const double l = d * r, il = r, id = r * r;
 #pragma unroll
             for (int m = 0; m < PT; ++m) {
-                const int e = tid + m * kSolveThreads;
-                if (e < RR) {
-                    const int i = ei[m], k = ek[m];
+                if (tid + m * kSolveThreads < RT) {
+                    const int i = ei[m], k = ek[m], e = i * R + k;
                     double x = B[e];
                     if (k == j) {
                         x = i == j ? l : (i > j ? x * il : x);
