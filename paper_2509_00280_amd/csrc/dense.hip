@@ -328,7 +328,8 @@ __device__ __forceinline__ void solve_prep_body(const double *__restrict__ grams
             const double l = d * r, il = r, id = r * r;
 #pragma unroll
             for (int m = 0; m < PT; ++m) {
-                if (tid + m * kSolveThreads < RT) {
+                // rows above the pivot are final in both matrices
+                if (tid + m * kSolveThreads < RT && ei[m] >= j) {
                     const int i = ei[m], k = ek[m], e = i * R + k;
                     double x = B[e];
                     if (k == j) {
