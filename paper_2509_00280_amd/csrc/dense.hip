@@ -696,7 +696,7 @@ spt_status launch_gram(const float *C, int64_t rows, int rank, double *G, double
     if (nb == 1) hipLaunchKernelGGL((k_gram_partial<1, 4>), g, b, 0, s, C, rows, rank, work);
     else if (nb == 2) hipLaunchKernelGGL((k_gram_partial<2, 4>), g, b, 0, s, C, rows, rank, work);
     else if (nb == 3) hipLaunchKernelGGL((k_gram_partial<3, 2>), g, b, 0, s, C, rows, rank, work);
-    else hipLaunchKernelGGL((k_gram_partial<4, 2>), g, b, 0, s, C, rows, rank, work);
+    else hipLaunchKernelGGL((k_gram_partial<4, 1>), g, b, 0, s, C, rows, rank, work);
     const int nslices = chunks;
     const int S = std::min(kGramSplit, nslices);
     double *w2 = work + (size_t)nslices * ld * ld;
